@@ -1,0 +1,174 @@
+/*
+ * perm.h -- C ABI of libperm_mi355x.so: the permanent of a sparse n x n
+ * matrix on an AMD Instinct MI355X (gfx950), by the Gray-code
+ * Nijenhuis-Wilf variant of Ryser's formula with matrix-specific generated
+ * kernels (Elbek & Kaya, arXiv 2501.15126).
+ *
+ * What is computed (Sec. I Eq. (1); Sec. II Eq. (2) and Alg. 1):
+ *
+ *   perm(A) = sum over permutations s of prod_i a_{i,s(i)}
+ *           = (4 (n mod 2) - 2) * sum_{g=0}^{2^(n-1)-1} (-1)^g prod_i x_i(Gray_g)
+ *
+ * where x_i(S) = a_{i,n-1} - (sum_j a_ij)/2 + sum_{j in S} a_ij and S ranges
+ * over subsets of the first n-1 columns in binary reflected Gray-code order.
+ *
+ * Conventions for every entry point:
+ *  - All functions are thread-safe.  The library owns all device memory,
+ *    streams, events and generated code objects; the caller owns its inputs
+ *    and outputs, which the library never retains after a call returns.
+ *  - Matrices are passed in compressed sparse column form (CCS, the paper's
+ *    CSC of Sec. II): colptr int32[n+1], rowidx int32[nnz], val double[nnz],
+ *    HOST pointers, 0-based indices.  Rules (violations give PERM_EINVAL):
+ *      colptr[0] == 0, colptr non-decreasing, colptr[n] == nnz;
+ *      0 <= rowidx < n and strictly increasing inside each column;
+ *      every val finite.
+ *    Explicit zeros are accepted and dropped.  n < 1 -> PERM_EINVAL;
+ *    n > PERM_MAX_N -> PERM_ETOOBIG.
+ *  - A structurally singular matrix (no perfect matching of its nonzero
+ *    pattern) has permanent exactly +0.0, returned without any kernel launch.
+ *  - On error, the status is returned and perm_last_error() describes it.
+ *  - Results are deterministic: the same input and options give bitwise the
+ *    same result (no floating-point atomics; fixed-order reductions).
+ */
+#ifndef PERM_MI355X_H
+#define PERM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PERM_MAX_N 64
+
+typedef enum {
+    PERM_OK = 0,
+    PERM_EINVAL = 1,      /* malformed input or option */
+    PERM_ETOOBIG = 2,     /* n or a size beyond what the library supports */
+    PERM_ENOMEM = 3,      /* host or device allocation failed */
+    PERM_EDEVICE = 4,     /* HIP runtime error or no usable gfx950 device */
+    PERM_ECOMPILE = 5,    /* hipRTC failed to compile a generated kernel */
+    PERM_EAGAIN = 6,      /* server: admission refused, try again later */
+    PERM_ENOTREADY = 7,   /* server: result not ready yet */
+    PERM_ECANCELED = 8    /* the computation was cancelled */
+} perm_status;
+
+/* One sparse matrix in CCS form (host memory, caller-owned). */
+typedef struct {
+    int32_t n;
+    const int32_t *colptr;
+    const int32_t *rowidx;
+    const double *val;
+} perm_csc;
+
+/* Kernel families.
+ *  PERM_MODE_AUTO    Alg. 4 ordering; x fully in VGPRs with a multi-level
+ *                    cache of partial products (the default).
+ *  PERM_MODE_PURE    x fully in VGPRs, columns in ascending-degree order, the
+ *                    whole product recomputed every step (the paper's
+ *                    register-only generated kernel, Sec. III-IV).
+ *  PERM_MODE_HYBRID  Alg. 4 ordering and Alg. 5 partition: rows < k in VGPRs,
+ *                    rows >= k in global memory with their product cached and
+ *                    recomputed only when a column >= c flips (Sec. V). */
+typedef enum { PERM_MODE_AUTO = 0, PERM_MODE_PURE = 1, PERM_MODE_HYBRID = 2 } perm_mode;
+
+/* Options; pass NULL for all defaults, or zero-initialise and set fields. */
+typedef struct {
+    int32_t mode;          /* perm_mode */
+    int32_t chunk_log2;    /* log2 of Gray steps per lane chunk; 0 = automatic */
+    int32_t unroll_log2;   /* log2 of the static unrolled block; 0 = automatic */
+    int32_t block;         /* threads per workgroup, multiple of 64, <= 1024; 0 = 256 */
+    int32_t vgpr_budget;   /* target VGPRs per lane for the level plan; 0 = 128 */
+    int32_t force_k;       /* > 0: override Alg. 5's k (HYBRID only), with force_c */
+    int32_t force_c;       /* > 0: override Alg. 5's c (HYBRID only) */
+    int32_t max_levels;    /* > 0: cap on cached product levels (AUTO); 0 = budget-driven */
+    double gr_ratio;       /* Alg. 5 global/register update cost ratio; 0 = 16 */
+    void *hip_stream;      /* hipStream_t to launch on; NULL = the library's stream */
+    /* Optional host output: per-workgroup partial sums of the Gray-term sum
+     * (before the final factor), as (hi, lo) double pairs, workgroup b
+     * covering Gray indices [b*W, (b+1)*W) with W = block * 2^chunk_log2.
+     * Filled only if the capacity (in workgroups) is large enough. */
+    double *block_partials;
+    int64_t block_partials_cap;
+} perm_opts;
+
+/* Statistics of one call (all optional to read). */
+typedef struct {
+    double kernel_ms;       /* device time of the Gray-kernel launch(es): HIP
+                               events recorded on the launch stream */
+    double reduce_ms;       /* device time of the final reduction kernel */
+    double compile_ms;      /* hipRTC compile + module load; 0 on a cache hit */
+    double host_ms;         /* validate + structure check + order + partition + codegen */
+    double total_ms;        /* wall time of the whole call */
+    double steps;           /* Gray-code steps evaluated: 2^(n-1) */
+    double ops_per_step;    /* FP64 VALU operations per step of the generated
+                               code, weighted by column frequency (Lemma 1) */
+    double flops_per_step;  /* same, counting an FMA that replaces a multiply
+                               and an add the method needs as 2 */
+    double sum_hi, sum_lo;  /* the Gray-term sum before the final factor */
+    int64_t nblocks;        /* workgroups launched */
+    int64_t nchunks;        /* lane chunks (2^(n-1-chunk_log2)) */
+    int32_t n, nnz;         /* after dropping explicit zeros */
+    int32_t mode;           /* kernel family actually used */
+    int32_t k, c;           /* register rows / register-only columns */
+    int32_t levels;         /* cached product levels */
+    int32_t chunk_log2, unroll_log2, block;
+    int32_t vgprs, sgprs, scratch_bytes, lds_bytes;
+    int32_t waves_per_simd; /* occupancy reported by the HIP occupancy API */
+    int32_t cache_hit;      /* generated code object reused */
+    int32_t singular;       /* 1 if answered as 0 by the structural check */
+} perm_stats;
+
+/* Permanent of one matrix (Alg. 1 end to end).  Returns NaN on error
+ * (see perm_last_error).  Synchronous. */
+double perm_sparse(int32_t n, const int32_t *colptr, const int32_t *rowidx, const double *val);
+
+/* Same with options and statistics.  *out receives the permanent.  opts and
+ * st may be NULL.  Synchronous: returns after the result is on the host. */
+perm_status perm_sparse_ex(const perm_csc *a, const perm_opts *opts, double *out, perm_stats *st);
+
+/* Permanents of `count` matrices (any mix of sizes), out[i] for mats[i].
+ * Synchronous.  Each result equals perm_sparse_ex's for that matrix alone,
+ * bitwise, with the same options. */
+perm_status perm_batch(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out);
+
+/* ---- Introspection of the host-side steps (used by tests) -------------- */
+
+/* The preprocessing decisions for a matrix without running it.
+ * row_perm / col_perm (caller buffers of n int32, may be NULL) receive the
+ * ordering: ordered position -> original index (Alg. 4, or ascending column
+ * degree in PURE mode).  tau (caller buffer of 2n+1 doubles, may be NULL)
+ * receives the thread-count model used by Alg. 5 (threads resident on the
+ * device when each uses r registers for x, r = 0..2n).  *k, *c receive
+ * Alg. 5's partition (AUTO and PURE report k = n, c = n - 1), *levels the
+ * number of cached product levels, *structural_rank the size of a maximum
+ * matching of the pattern (after dropping explicit zeros). */
+perm_status perm_plan(const perm_csc *a, const perm_opts *opts, int32_t *row_perm, int32_t *col_perm,
+                      double *tau, int32_t *k, int32_t *c, int32_t *levels, int32_t *structural_rank);
+
+/* Alg. 5 alone on an already ordered pattern, with a caller-supplied tau
+ * table (2n+1 entries) and GRratio. */
+perm_status perm_partition(const perm_csc *ordered, const double *tau, double gr_ratio, int32_t *k,
+                           int32_t *c);
+
+/* The HIP source text generated for a matrix.  Writes at most cap bytes
+ * (NUL-terminated when it fits) and the full length to *len. */
+perm_status perm_codegen(const perm_csc *a, const perm_opts *opts, char *buf, size_t cap, size_t *len);
+
+/* Compile the generated kernel for a matrix with hipRTC (gfx950; no GPU
+ * needed) without launching it, and report the plan and the code object's
+ * resources (vgprs, sgprs, scratch_bytes, lds_bytes, compile_ms) in *st. */
+perm_status perm_compile_info(const perm_csc *a, const perm_opts *opts, perm_stats *st);
+
+/* Description of the last error on the calling thread (never NULL; valid
+ * until the next library call on that thread). */
+const char *perm_last_error(void);
+
+/* Library version string. */
+const char *perm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PERM_MI355X_H */

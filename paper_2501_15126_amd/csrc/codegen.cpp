@@ -1,0 +1,337 @@
+// codegen.cpp -- emits the matrix-specific gfx950 kernel (HIP C++ for hipRTC).
+//
+// What the generated kernel computes: the Gray-term sum of Alg. 1 over the
+// chunks [chunk_begin, chunk_end), chunk m covering Gray indices
+// [m 2^kappa, (m+1) 2^kappa), one chunk per lane.  For each workgroup it
+// writes the double-double sum of its lanes' chunks to partials[2b], [2b+1].
+//
+// How (the paper's ideas, rebuilt for a 64-wide wavefront):
+//  * x lives in named variables, one per row, so the compiler keeps it in
+//    VGPRs; the matrix values are exact hex-float literals in the code
+//    (Sec. III-B, Listings 2-3: per-column inclusion/exclusion updates).
+//  * Chunks are power-of-two sized and aligned, so at local step l every lane
+//    flips the same column ctz(l) (Theorem 1) with the same direction, except
+//    at l = 2^(kappa-1) where the direction is the parity of the chunk index
+//    (Lemma 2, first case); that one step uses a per-lane +-1 multiplier.  The
+//    step that would differ in column (l = 2^kappa, Lemma 2's second case) is
+//    the next chunk's start and is never executed inside a chunk.
+//  * The loop body is a static unrolled block of 2^u steps whose columns and
+//    signs are compile-time constants, followed by one wave-uniform dynamic
+//    step (a scalar switch on ctz).
+//  * Products are cached by level (a generalisation of Sec. V's cached
+//    global product, Listings 4-5): rows are grouped by the first flipped
+//    column that touches them, S_l = product of x over levels >= l is kept,
+//    and a flip of column j recomputes only the levels up to the highest
+//    level column j touches.  With one level this is the plain full product.
+//  * Rows >= k (HYBRID) live in global memory, [row][lane] so that a wave's
+//    accesses are contiguous (Sec. V), and their product is recomputed only
+//    when a column that touches them flips.
+#include <cstdio>
+#include <map>
+#include <sstream>
+
+#include "perm_internal.h"
+
+namespace permx {
+
+const char *const kGrayKernelName = "perm_gray";
+
+namespace {
+
+std::string lit(double v) {
+    char b[64];
+    snprintf(b, sizeof b, "%a", v);  // exact binary64 value as a hex-float literal
+    return b;
+}
+
+enum class Sign { Plus, Minus, Uniform, Lane };
+
+struct Gen {
+    const Plan &p;
+    std::ostringstream os;
+    int tmp = 0;
+    std::vector<std::vector<int>> level_rows;
+
+    explicit Gen(const Plan &plan) : p(plan) {
+        level_rows.assign(p.nlevels, {});
+        for (int r = 0; r < p.n; ++r) level_rows[p.row_level[r]].push_back(r);
+    }
+
+    std::string fresh() { return "t" + std::to_string(tmp++); }
+    std::string xname(int r) const { return "x" + std::to_string(r); }
+    std::string cold_addr(int r) const {
+        return "xg[(u64)" + std::to_string(r - p.k) + " * xs + lid]";
+    }
+
+    // Pairwise (tree) product of the named values; returns the result name.
+    std::string product(std::vector<std::string> vals, const char *ind) {
+        if (vals.empty()) return "1.0";
+        while (vals.size() > 1) {
+            std::vector<std::string> next;
+            for (size_t i = 0; i + 1 < vals.size(); i += 2) {
+                std::string t = fresh();
+                os << ind << "const double " << t << " = " << vals[i] << " * " << vals[i + 1] << ";\n";
+                next.push_back(t);
+            }
+            if (vals.size() % 2) next.push_back(vals.back());
+            vals.swap(next);
+        }
+        return vals[0];
+    }
+
+    // Names of the current x values of level l's rows; cold rows not in
+    // `cur` are loaded from global memory.
+    std::vector<std::string> level_values(int l, std::map<int, std::string> &cur, const char *ind) {
+        std::vector<std::string> v;
+        for (int r : level_rows[l]) {
+            if (r < p.k) {
+                v.push_back(xname(r));
+            } else if (cur.count(r)) {
+                v.push_back(cur[r]);
+            } else {
+                std::string t = fresh();
+                os << ind << "const double " << t << " = " << cold_addr(r) << ";\n";
+                cur[r] = t;
+                v.push_back(t);
+            }
+        }
+        return v;
+    }
+
+    // x updates of one Gray step flipping column j in direction sg; updated
+    // cold rows are recorded in `cur`.
+    void update(int j, Sign sg, std::map<int, std::string> &cur, const char *I) {
+        const Ccs &B = p.B;
+        for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) {
+            const int r = B.rowidx[q];
+            const std::string a = lit(B.val[q]);
+            std::string target;
+            if (r < p.k) {
+                target = xname(r);
+            } else {
+                target = fresh();
+                os << I << "double " << target << " = " << cold_addr(r) << ";\n";
+                cur[r] = target;
+            }
+            if (sg == Sign::Plus)
+                os << I << target << " += " << a << ";\n";
+            else if (sg == Sign::Minus)
+                os << I << target << " -= " << a << ";\n";
+            else if (sg == Sign::Uniform)
+                os << I << target << " += (neg ? -(" << a << ") : (" << a << "));\n";
+            else
+                os << I << target << " = fma(lsgn, " << a << ", " << target << ");\n";
+            if (r >= p.k) os << I << cold_addr(r) << " = " << target << ";\n";
+        }
+    }
+
+    // Recompute the cached product of level l: S_l = prod(level l) * S_{l+1}.
+    void refresh_level(int l, std::map<int, std::string> &cur, const char *I) {
+        std::vector<std::string> v = level_values(l, cur, I);
+        if (l + 1 < p.nlevels) v.push_back("S" + std::to_string(l + 1));
+        std::string prod = product(v, I);
+        os << I << "S" << l << " = " << prod << ";\n";
+    }
+
+    // One Gray step: flip column j with the given direction, refresh the
+    // cached products it invalidates and accumulate the term with sign
+    // term_sign into accumulator acc.
+    void step(int j, Sign sg, int term_sign, int acc, const char *ind) {
+        std::map<int, std::string> cur;
+        os << ind << "{  // column " << j
+           << (sg == Sign::Plus ? " +" : sg == Sign::Minus ? " -" : sg == Sign::Uniform ? " uniform sign" : " lane sign")
+           << "\n";
+        std::string in = std::string(ind) + "  ";
+        const char *I = in.c_str();
+        update(j, sg, cur, I);
+        for (int l = p.col_top[j]; l >= 1; --l) refresh_level(l, cur, I);
+        accumulate(term_sign, acc, cur, I);
+        os << ind << "}\n";
+    }
+
+    // acc += term_sign * (product of level 0) * S_1   (one FMA)
+    void accumulate(int term_sign, int acc, std::map<int, std::string> &cur, const char *I,
+                    const char *weight = nullptr) {
+        std::vector<std::string> v = level_values(0, cur, I);
+        if (weight) v.push_back(weight);
+        std::string last;
+        if (p.nlevels > 1) {
+            last = "S1";
+        } else {
+            last = v.back();
+            v.pop_back();
+        }
+        std::string pr = product(v, I);
+        os << I << "acc" << acc << " = fma(" << (term_sign < 0 ? "-" : "") << pr << ", " << last << ", acc" << acc
+           << ");\n";
+    }
+
+    // Static block of steps i = 1 .. 2^u - 1 inside a 2^(u+1)-aligned pair of
+    // blocks; `second` selects the second block (where the step i = 2^(u-1)
+    // excludes instead of includes).
+    void static_block(bool second, const char *ind) {
+        const int U = 1 << p.u;
+        for (int i = 1; i < U; ++i) {
+            const int j = __builtin_ctz(i);
+            bool neg;
+            if (j + 1 < p.u)
+                neg = (i >> (j + 1)) & 1;  // Theorem 1 with the chunk-local index
+            else
+                neg = second;              // bit u of the local index
+            step(j, neg ? Sign::Minus : Sign::Plus, (i & 1) ? -1 : 1, (i >> 1) & 1, ind);
+        }
+    }
+
+    std::string run() {
+        const Ccs &B = p.B;
+        const int n = p.n, k = p.k, L = p.nlevels;
+        const int kappa = p.kappa, u = p.u, U = 1 << u;
+        const uint64_t DELTA = 1ull << kappa;
+        os << "// generated by libperm_mi355x: n=" << n << " nnz=" << p.nnz << " k=" << k << " c=" << p.c
+           << " levels=" << L << " kappa=" << kappa << " u=" << u << " block=" << p.block << "\n";
+        os << "typedef unsigned long long u64;\n"
+              "typedef unsigned int u32;\n"
+              "struct dd { double h, l; };\n"
+              "__device__ __forceinline__ dd two_sum(double a, double b) {\n"
+              "  const double s = a + b; const double bb = s - a;\n"
+              "  dd r; r.h = s; r.l = (a - (s - bb)) + (b - bb); return r; }\n"
+              "__device__ __forceinline__ dd dd_add(dd x, dd y) {\n"
+              "  const dd s = two_sum(x.h, y.h); const double e = s.l + (x.l + y.l);\n"
+              "  dd r; r.h = s.h + e; r.l = e - (r.h - s.h); return r; }\n";
+        // perm_lane: the Gray-term sum of chunk m (one lane's work); cold rows
+        // of this lane live at xg[(r - k) * xs + lid].
+        os << "__device__ __forceinline__ dd perm_lane(const u64 m, double* __restrict__ xg, const u64 xs,\n"
+              "                                        const u64 lid) {\n";
+        os << "  const u64 g0 = m << "
+           << kappa
+           << ";\n"
+              "  const u64 G = g0 ^ (g0 >> 1);\n";
+        // ---- chunk start: x(Gray_{m 2^kappa}) ----
+        for (int r = 0; r < n; ++r)
+            os << "  double " << (r < k ? xname(r) : "cx" + std::to_string(r)) << " = " << lit(p.base_x_hi[r]) << ";\n";
+        const int jlo = kappa >= 1 ? kappa - 1 : 0;  // lower Gray bits of an aligned start are zero
+        for (int j = jlo; j < n - 1; ++j) {
+            if (B.colptr[j + 1] == B.colptr[j]) continue;
+            os << "  { const double b = (double)((G >> " << j << ") & 1ull);\n";
+            for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) {
+                const int r = B.rowidx[q];
+                const std::string v = r < k ? xname(r) : "cx" + std::to_string(r);
+                os << "    " << v << " = fma(b, " << lit(B.val[q]) << ", " << v << ");\n";
+            }
+            os << "  }\n";
+        }
+        std::map<int, std::string> cur;
+        for (int r = k; r < n; ++r) {
+            os << "  " << cold_addr(r) << " = cx" << r << ";\n";
+            cur[r] = "cx" + std::to_string(r);
+        }
+        for (int l = L - 1; l >= 1; --l) {
+            std::vector<std::string> v = level_values(l, cur, "  ");
+            if (l + 1 < L) v.push_back("S" + std::to_string(l + 1));
+            std::string prod = product(v, "  ");
+            os << "  double S" << l << " = " << prod << ";\n";
+        }
+        os << "  double acc0 = 0.0, acc1 = 0.0;\n";
+        accumulate(+1, 0, cur, "  ");  // term g = m 2^kappa (even index: sign +)
+        // ---- Gray loop over local steps 1 .. 2^kappa - 1 ----
+        if (kappa >= 1) {
+            os << "  const double lsgn = (m & 1ull) ? -1.0 : 1.0;  // direction at local step 2^(kappa-1)\n";
+            os << "#pragma clang loop unroll(disable)\n";
+            os << "  for (u32 base = 0; base < " << DELTA << "u; base += " << 2 * U << "u) {\n";
+            static_block(false, "    ");
+            // local step base + 2^u flips column u; its direction is bit u+1
+            // of the local index (uniform), or the chunk parity when u+1 = kappa
+            const int term_u = (u == 0) ? -1 : 1;
+            if (u + 1 == kappa) {
+                step(u, Sign::Lane, term_u, 0, "    ");
+            } else {
+                os << "    {\n      const bool neg = (base >> " << (u + 1) << ") & 1u;\n";
+                step(u, Sign::Uniform, term_u, 0, "      ");
+                os << "    }\n";
+            }
+            static_block(true, "    ");
+            // local step base + 2^(u+1): column jj = ctz >= u + 1, the same in
+            // every lane.  Branch-free: for each row that one of these columns
+            // touches, a scalar select picks that column's entry (0 when row r
+            // is not in column jj), one FMA applies it with the step's
+            // direction, then every level these columns can reach is refreshed.
+            if (u + 1 <= kappa - 1) {
+                const Ccs &B = p.B;
+                int top_max = 0;
+                std::map<int, std::vector<std::pair<int, double>>> rows;  // row -> (column, value)
+                for (int j = u + 1; j <= kappa - 1; ++j) {
+                    top_max = std::max(top_max, p.col_top[j]);
+                    for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) rows[B.rowidx[q]].push_back({j, B.val[q]});
+                }
+                // The last iteration reaches ell = 2^kappa, which is not a step of
+                // this chunk: no column matches jj = kappa there, and the weight w
+                // = 0 drops its term.  (A branch here instead makes the compiler
+                // restructure the loop at a large cost in registers.)
+                os << "    const u32 ell = base + " << 2 * U << "u;\n";
+                os << "    {\n";
+                os << "      const double w = (ell < " << DELTA << "u) ? 1.0 : 0.0;\n";
+                os << "      const int jj = __builtin_ctz(ell);\n";
+                os << "      const double sgu = ((ell >> (jj + 1)) & 1u) ? -1.0 : 1.0;\n";
+                os << "      const double sg = (jj == " << kappa - 1 << ") ? lsgn : sgu;\n";
+                std::map<int, std::string> cur;
+                for (auto &rv : rows) {
+                    const int r = rv.first;
+                    std::string sel = "0.0";
+                    for (auto it = rv.second.rbegin(); it != rv.second.rend(); ++it)
+                        sel = "(jj == " + std::to_string(it->first) + " ? " + lit(it->second) + " : " + sel + ")";
+                    std::string target;
+                    if (r < p.k) {
+                        target = xname(r);
+                    } else {
+                        target = fresh();
+                        os << "      double " << target << " = " << cold_addr(r) << ";\n";
+                        cur[r] = target;
+                    }
+                    os << "      " << target << " = fma(sg, " << sel << ", " << target << ");\n";
+                    if (r >= p.k) os << "      " << cold_addr(r) << " = " << target << ";\n";
+                }
+                for (int l = top_max; l >= 1; --l) refresh_level(l, cur, "      ");
+                accumulate(1, 1, cur, "      ", "w");
+                os << "    }\n";
+            }
+            os << "  }\n";
+        }
+        os << "  return two_sum(acc0, acc1);\n}\n";
+        // ---- the kernel: one chunk per lane, then a deterministic reduction
+        //      lane -> wave (butterfly) -> workgroup ----
+        const int nw = p.block / 64;
+        os << "extern \"C\" __global__ void __launch_bounds__(" << p.block << ") " << kGrayKernelName
+           << "(const u64 chunk_begin, const u64 chunk_end, double* __restrict__ partials,\n"
+              "    double* __restrict__ xg, const u64 xs) {\n";
+        os << "  const u64 lid = (u64)blockIdx.x * " << p.block << "u + threadIdx.x;\n"
+              "  const bool active = chunk_begin + lid < chunk_end;\n"
+              "  // an inactive lane (past the last chunk) replays a valid chunk and contributes 0\n"
+              "  const u64 m = active ? chunk_begin + lid : chunk_begin;\n"
+              "  dd cs = perm_lane(m, xg, xs, lid);\n"
+              "  if (!active) { cs.h = 0.0; cs.l = 0.0; }\n"
+              "  for (int off = 32; off > 0; off >>= 1) {\n"
+              "    dd o; o.h = __shfl_xor(cs.h, off, 64); o.l = __shfl_xor(cs.l, off, 64);\n"
+              "    cs = dd_add(cs, o);\n"
+              "  }\n";
+        os << "  __shared__ double wsum[" << 2 * nw << "];\n"
+              "  if ((threadIdx.x & 63u) == 0) { wsum[2 * (threadIdx.x >> 6)] = cs.h; wsum[2 * (threadIdx.x >> 6) + 1] = cs.l; }\n"
+              "  __syncthreads();\n"
+              "  if (threadIdx.x == 0) {\n"
+              "    dd t; t.h = wsum[0]; t.l = wsum[1];\n";
+        os << "    for (int w = 1; w < " << nw << "; ++w) { dd o; o.h = wsum[2 * w]; o.l = wsum[2 * w + 1]; t = dd_add(t, o); }\n";
+        os << "    partials[2 * (u64)blockIdx.x] = t.h;\n"
+              "    partials[2 * (u64)blockIdx.x + 1] = t.l;\n"
+              "  }\n"
+              "}\n";
+        return os.str();
+    }
+};
+
+}  // namespace
+
+std::string generate_source(const Plan &p) {
+    Gen g(p);
+    return g.run();
+}
+
+}  // namespace permx

@@ -1,0 +1,86 @@
+// perm_internal.h -- host-side data structures of libperm_mi355x.
+//
+// The pipeline of one permanent (the paper's "input matrix -> generate ->
+// compile -> run -> output" script of Sec. VI-E, rebuilt as a library):
+//   validate + normalise CCS (Sec. II CSR/CSC definitions)
+//   structural check (a maximum matching; perm = 0 when it is not perfect)
+//   ordering (Alg. 4, or ascending column degree) and partition (Alg. 5)
+//   level plan for cached partial products (generalises Sec. V's cached
+//     global product)
+//   code generation (Sec. III-B, Listings 2-5, rebuilt for gfx950) + hipRTC
+//   chunk schedule (Theorem 1, Lemma 2; power-of-two aligned chunks)
+//   launch, per-workgroup double-double partials, fixed-order final sum.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "perm.h"
+
+namespace permx {
+
+// A validated CCS with explicit zeros removed.
+struct Ccs {
+    int n = 0;
+    std::vector<int32_t> colptr, rowidx;
+    std::vector<double> val;
+    int nnz() const { return (int)rowidx.size(); }
+};
+
+// ---- ccs.cpp ---------------------------------------------------------------
+perm_status normalize_ccs(const perm_csc *a, Ccs *out, std::string *err);
+// Size of a maximum matching between rows and columns (Hopcroft-Karp).
+int structural_rank(const Ccs &a);
+// B = A[rowPerm, colPerm] (position -> original index), rows ascending per column.
+Ccs permute(const Ccs &a, const std::vector<int> &rowPerm, const std::vector<int> &colPerm);
+
+// ---- preprocess.cpp --------------------------------------------------------
+// Alg. 4 (PermanentOrdering).
+void permanent_ordering(const Ccs &a, std::vector<int> &rowPerm, std::vector<int> &colPerm);
+// Columns by ascending nonzero count (stable), rows unchanged.
+void degree_ordering(const Ccs &a, std::vector<int> &rowPerm, std::vector<int> &colPerm);
+// Alg. 5 (Partitioning) on an ordered matrix.
+void partitioning(const Ccs &ordered, const double *tau, double gr_ratio, int *k, int *c);
+// gfx950 thread-count model: tau[r] for r = 0..2n registers of x per lane.
+std::vector<double> tau_model(int n, int base_vgprs);
+
+struct DeviceShape {
+    int cus = 256;          // compute units
+    int simds_per_cu = 4;
+    int vgprs_per_simd_lane = 512;
+    int max_waves_per_simd = 8;
+};
+const DeviceShape &device_shape();
+
+struct Plan {
+    int n = 0, nnz = 0, mode = PERM_MODE_AUTO;
+    std::vector<int> rowPerm, colPerm;  // ordered position -> original index
+    Ccs B;                              // the ordered matrix
+    int k = 0;                          // rows [0, k) in VGPRs, [k, n) in global memory
+    int c = 0;                          // flipped columns [0, c) touch only rows < k
+    // Cached product levels.  Level l holds rows whose first flipped column
+    // lies in [lev_begin[l], lev_begin[l+1]); the last level also holds rows
+    // touched only by the fixed column n-1.  S_l = product of x over levels
+    // >= l is kept for l >= 1.
+    int nlevels = 1;
+    std::vector<int> lev_begin;         // size nlevels + 1, lev_begin[nlevels] = n
+    std::vector<int> row_level;         // level of each ordered row
+    std::vector<int> col_top;           // highest level touched by each flipped column
+    bool cold = false;                  // last level lives in global memory (rows >= k)
+    int kappa = 0;                      // chunk = 2^kappa Gray steps per lane
+    int u = 0;                          // static unrolled block = 2^u steps
+    int block = 256;
+    double base_x_hi[PERM_MAX_N];       // x_r at Gray index 0 (Alg. 1 lines 1-5)
+    double ops_per_step = 0, flops_per_step = 0;
+    std::vector<double> ops_of_col;     // FP64 VALU ops of one step flipping column j
+};
+
+perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *err);
+
+// ---- codegen.cpp -----------------------------------------------------------
+std::string generate_source(const Plan &p);
+// Kernel entry point name inside every generated module.
+extern const char *const kGrayKernelName;
+
+}  // namespace permx

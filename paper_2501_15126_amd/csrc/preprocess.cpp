@@ -1,0 +1,294 @@
+// preprocess.cpp -- ordering (Alg. 4), partitioning (Alg. 5), the gfx950
+// thread-count model, the cached-product level plan and the chunk schedule.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+
+#include "perm_internal.h"
+
+namespace permx {
+
+const DeviceShape &device_shape() {
+    static DeviceShape s;  // MI355X: 256 CUs x 4 SIMDs, 512 VGPRs per lane per SIMD
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 4 (PermanentOrdering, Sec. V).  Repeatedly choose the column with the
+// fewest nonzeros in rows not yet ordered (lowest index on ties), then order
+// its not-yet-ordered rows (ascending row index).  Each newly ordered row
+// lowers the count of every not-yet-chosen column it touches.  Rows that no
+// column touches (empty rows) go last, ascending.
+// ---------------------------------------------------------------------------
+void permanent_ordering(const Ccs &a, std::vector<int> &rowPerm, std::vector<int> &colPerm) {
+    const int n = a.n;
+    // row -> columns (CSR pattern)
+    std::vector<int> rptr(n + 1, 0), cids(a.nnz());
+    for (int p = 0; p < a.nnz(); ++p) rptr[a.rowidx[p] + 1]++;
+    for (int i = 0; i < n; ++i) rptr[i + 1] += rptr[i];
+    {
+        std::vector<int> fill(rptr.begin(), rptr.end() - 1);
+        for (int j = 0; j < n; ++j)
+            for (int p = a.colptr[j]; p < a.colptr[j + 1]; ++p) cids[fill[a.rowidx[p]]++] = j;
+    }
+    std::vector<int> unordered_count(n);
+    std::vector<char> chosen(n, 0), ordered(n, 0);
+    for (int j = 0; j < n; ++j) unordered_count[j] = a.colptr[j + 1] - a.colptr[j];
+    rowPerm.clear();
+    colPerm.clear();
+    for (int step = 0; step < n; ++step) {
+        int best = -1;
+        for (int j = 0; j < n; ++j)
+            if (!chosen[j] && (best < 0 || unordered_count[j] < unordered_count[best])) best = j;
+        chosen[best] = 1;
+        colPerm.push_back(best);
+        for (int p = a.colptr[best]; p < a.colptr[best + 1]; ++p) {
+            const int r = a.rowidx[p];
+            if (ordered[r]) continue;
+            ordered[r] = 1;
+            rowPerm.push_back(r);
+            for (int q = rptr[r]; q < rptr[r + 1]; ++q)
+                if (!chosen[cids[q]]) unordered_count[cids[q]]--;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        if (!ordered[i]) rowPerm.push_back(i);
+}
+
+// Ascending column degree (the degree sort of Sec. VI-B), rows unchanged.
+void degree_ordering(const Ccs &a, std::vector<int> &rowPerm, std::vector<int> &colPerm) {
+    const int n = a.n;
+    rowPerm.resize(n);
+    colPerm.resize(n);
+    for (int i = 0; i < n; ++i) rowPerm[i] = colPerm[i] = i;
+    std::stable_sort(colPerm.begin(), colPerm.end(), [&](int x, int y) {
+        return a.colptr[x + 1] - a.colptr[x] < a.colptr[y + 1] - a.colptr[y];
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 5 (Partitioning, Sec. V).  For each prefix of columns 0..j: nrows is
+// the largest row index touched so far plus one, x needs 2*nrows 32-bit
+// registers, register updates cost 2*nrows*(1 - 2^-(j+1)), global updates
+// (n - nrows) * 2^-(j+1) * GRratio; the score is tau(registers) divided by
+// their sum.  A better score, or a column that adds no row (nrows == k),
+// moves the boundary to k = nrows, c = j + 1.
+// ---------------------------------------------------------------------------
+void partitioning(const Ccs &ordered, const double *tau, double gr_ratio, int *k_out, int *c_out) {
+    const int n = ordered.n;
+    int k = 0, c = 0, nrows = 0;
+    double best = 0.0;
+    for (int j = 0; j < n; ++j) {
+        int top = 0;
+        for (int p = ordered.colptr[j]; p < ordered.colptr[j + 1]; ++p) top = std::max(top, ordered.rowidx[p] + 1);
+        nrows = std::max(nrows, top);
+        const int regs = 2 * nrows;
+        const double freq = std::ldexp(1.0, -(j + 1));
+        const double reg_cost = regs * (1.0 - freq);
+        const double glob_cost = (n - nrows) * freq * gr_ratio;
+        const double score = tau[regs] / (reg_cost + glob_cost);
+        if (score > best || nrows == k) {
+            best = score;
+            k = nrows;
+            c = j + 1;
+        }
+    }
+    *k_out = k;
+    *c_out = c;
+}
+
+// CalculateNoThreads of Alg. 5 for gfx950: threads resident on the device when
+// each lane holds r registers of x on top of the kernel's other registers.
+// VGPRs are allocated in granules of 8; a SIMD holds 512 per lane and at most
+// 8 waves.
+std::vector<double> tau_model(int n, int base_vgprs) {
+    const DeviceShape &d = device_shape();
+    std::vector<double> tau(2 * n + 1);
+    for (int r = 0; r <= 2 * n; ++r) {
+        const int v = (base_vgprs + r + 7) / 8 * 8;
+        const int waves = std::min(d.max_waves_per_simd, d.vgprs_per_simd_lane / v);
+        tau[r] = (double)d.cus * d.simds_per_cu * waves * 64;
+    }
+    return tau;
+}
+
+namespace {
+
+// VGPRs a lane needs besides x and the cached products: two accumulators,
+// the lane sign, chunk index, temporaries of the product trees and the
+// reduction.  Used only by the plan's budget (the real count comes from the
+// compiled code object).
+constexpr int kBaseVgprs = 28;
+
+int auto_kappa(int n) {
+    const int total = n - 1;  // log2 of the number of Gray indices
+    // about 2^21 lanes (8 resident rounds of the 4096 wave slots at 4 waves
+    // per SIMD), chunks of at least 2^8 steps, at most 2^22
+    int kappa = total - 21;
+    kappa = std::max(kappa, std::min(total, 8));
+    kappa = std::min(kappa, 22);
+    return kappa;
+}
+
+}  // namespace
+
+perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *err) {
+    char buf[256];
+    const int n = a.n;
+    p->n = n;
+    p->nnz = a.nnz();
+    p->mode = o.mode;
+    if (o.mode < PERM_MODE_AUTO || o.mode > PERM_MODE_HYBRID) {
+        *err = "unknown mode";
+        return PERM_EINVAL;
+    }
+    if (o.mode == PERM_MODE_PURE)
+        degree_ordering(a, p->rowPerm, p->colPerm);
+    else
+        permanent_ordering(a, p->rowPerm, p->colPerm);
+    p->B = permute(a, p->rowPerm, p->colPerm);
+    const Ccs &B = p->B;
+
+    // first flipped column (0..n-2) touching each ordered row; n-1 if none
+    std::vector<int> first(n, n - 1);
+    for (int j = 0; j < n - 1; ++j)
+        for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) first[B.rowidx[q]] = std::min(first[B.rowidx[q]], j);
+
+    const double gr = o.gr_ratio > 0 ? o.gr_ratio : 16.0;
+    const int budget = o.vgpr_budget > 0 ? o.vgpr_budget : 128;
+    std::vector<double> tau = tau_model(n, kBaseVgprs);
+    int k5 = n, c5 = n;
+    partitioning(B, tau.data(), gr, &k5, &c5);
+
+    // ---- register / global split ----
+    int k = n, c = n - 1;
+    if (o.mode == PERM_MODE_HYBRID) {
+        k = k5;
+        c = std::min(c5, n - 1);
+        if (o.force_k > 0 || o.force_c > 0) {
+            if (o.force_k <= 0 || o.force_c <= 0 || o.force_k > n || o.force_c > n) {
+                *err = "force_k and force_c must both be in [1, n]";
+                return PERM_EINVAL;
+            }
+            k = o.force_k;
+            c = std::min(o.force_c, n - 1);
+        }
+    }
+    // AUTO keeps all of x in VGPRs: at n <= 64 that is at most 128 registers,
+    // which a gfx950 lane can hold with 3 or more waves per SIMD.
+    // every row touched by a register-only column must be a register row
+    for (int j = 0; j < c; ++j)
+        for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q)
+            if (B.rowidx[q] >= k) {
+                snprintf(buf, sizeof buf, "partition (k=%d, c=%d) invalid: column %d touches row %d", k, c, j,
+                         B.rowidx[q]);
+                *err = buf;
+                return PERM_EINVAL;
+            }
+    p->k = k;
+    p->c = c;
+    p->cold = k < n;
+
+    // ---- levels ----
+    // register rows [0, k) are grouped by the first flipped column that
+    // touches them; the cold rows, if any, form the last level.
+    std::vector<int> lev_begin;  // first column of each register level
+    if (o.mode == PERM_MODE_AUTO) {
+        std::vector<int> firsts;
+        for (int r = 0; r < k; ++r) firsts.push_back(std::min(first[r], c));
+        std::sort(firsts.begin(), firsts.end());
+        firsts.erase(std::unique(firsts.begin(), firsts.end()), firsts.end());
+        lev_begin = firsts;
+        if (lev_begin.empty() || lev_begin[0] != 0) lev_begin.insert(lev_begin.begin(), 0);
+        const int cold_levels = p->cold ? 1 : 0;
+        auto vgprs = [&](int nlev) { return 2 * k + 2 * (nlev + cold_levels - 1) + kBaseVgprs; };
+        int cap = o.max_levels > 0 ? o.max_levels : INT_MAX;
+        while ((int)lev_begin.size() > 1 && ((int)lev_begin.size() > cap || vgprs((int)lev_begin.size()) > budget))
+            lev_begin.pop_back();  // merge the two highest (least often touched) levels
+    } else {
+        lev_begin = {0};  // PURE, HYBRID: one register level (the paper's register product)
+    }
+    const int nreg_levels = (int)lev_begin.size();
+    p->nlevels = nreg_levels + (p->cold ? 1 : 0);
+    p->lev_begin = lev_begin;
+    if (p->cold) p->lev_begin.push_back(c);
+    p->lev_begin.push_back(n);
+    p->row_level.assign(n, 0);
+    for (int r = 0; r < n; ++r) {
+        if (r >= k) {
+            p->row_level[r] = p->nlevels - 1;
+            continue;
+        }
+        const int f = std::min(first[r], c);
+        int l = 0;
+        while (l + 1 < nreg_levels && lev_begin[l + 1] <= f) ++l;
+        p->row_level[r] = l;
+    }
+    p->col_top.assign(n, 0);
+    for (int j = 0; j < n - 1; ++j) {
+        int t = 0;
+        for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) t = std::max(t, p->row_level[B.rowidx[q]]);
+        p->col_top[j] = t;
+    }
+
+    // ---- x at Gray index 0 (Alg. 1 lines 1-5, with a_{i,n-1} = 0 when absent) ----
+    {
+        std::vector<long double> rowsum(n, 0.0L), last(n, 0.0L);
+        for (int j = 0; j < n; ++j)
+            for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) {
+                rowsum[B.rowidx[q]] += (long double)B.val[q];
+                if (j == n - 1) last[B.rowidx[q]] = (long double)B.val[q];
+            }
+        for (int r = 0; r < n; ++r) p->base_x_hi[r] = (double)(last[r] - rowsum[r] / 2);
+    }
+
+    // ---- schedule ----
+    const int total_log2 = n - 1;
+    p->kappa = o.chunk_log2 > 0 ? o.chunk_log2 : auto_kappa(n);
+    if (p->kappa > total_log2) p->kappa = total_log2;
+    if (p->kappa > 30) {
+        *err = "chunk_log2 must be <= 30";
+        return PERM_EINVAL;
+    }
+    if (total_log2 - p->kappa > 40) {
+        *err = "too many chunks: raise chunk_log2";
+        return PERM_ETOOBIG;
+    }
+    const int u_auto = 6;
+    p->u = o.unroll_log2 > 0 ? o.unroll_log2 : u_auto;
+    if (p->u > 9) {
+        *err = "unroll_log2 must be <= 9";
+        return PERM_EINVAL;
+    }
+    p->u = std::max(0, std::min(p->u, p->kappa - 1));
+    p->block = o.block > 0 ? o.block : 256;
+    if (p->block % 64 != 0 || p->block > 1024) {
+        *err = "block must be a multiple of 64 and at most 1024";
+        return PERM_EINVAL;
+    }
+
+    // ---- FP64 operations per step (matches what generate_source emits) ----
+    std::vector<int> level_size(p->nlevels, 0);
+    for (int r = 0; r < n; ++r) level_size[p->row_level[r]]++;
+    p->ops_of_col.assign(n, 0.0);
+    double ops = 0.0;
+    const double steps = std::ldexp(1.0, n - 1);
+    const int L = p->nlevels;
+    for (int j = 0; j < n - 1; ++j) {
+        const int t = p->col_top[j];
+        double oj = B.colptr[j + 1] - B.colptr[j];  // x updates
+        for (int l = 0; l <= t; ++l) oj += std::max(0, level_size[l] - 1);
+        for (int l = 1; l <= t; ++l)
+            if (l < L - 1) oj += 1;  // chain multiply by S_{l+1}
+        if (L > 1) oj += 1;          // accumulate: fma(P_0, S_1, acc)
+        p->ops_of_col[j] = oj;
+        ops += std::ldexp(1.0, n - j - 2) * oj;
+    }
+    p->ops_per_step = ops / steps;
+    // the accumulate FMA replaces a multiply and an add of Alg. 1 (counts 2)
+    p->flops_per_step = (ops + (steps - 1.0)) / steps;
+    return PERM_OK;
+}
+
+}  // namespace permx

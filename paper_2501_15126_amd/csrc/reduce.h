@@ -1,0 +1,12 @@
+// reduce.h -- launcher of the precompiled fixed-order final reduction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace permx {
+
+// out[0] + out[1] = double-double sum of partials[2b] + partials[2b+1],
+// b = 0..count-1, in an order fixed by b.  Asynchronous on `stream`.
+hipError_t launch_final_reduce(const double *partials, long long count, double *out, hipStream_t stream);
+
+}  // namespace permx

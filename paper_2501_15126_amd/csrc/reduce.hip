@@ -1,0 +1,83 @@
+// reduce.hip -- fixed-order double-double sum of per-workgroup partials.
+//
+// The paper adds per-thread partial permanents into a global variable
+// (Sec. II-A) in no stated order.  Here every workgroup of the Gray kernel
+// writes one double-double partial, and this single-workgroup kernel sums
+// them in an order fixed by the partial's index: thread t accumulates
+// partials t, t + 1024, t + 2048, ... and the 1024 results are combined by a
+// fixed binary tree in LDS.  The result does not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include "reduce.h"
+
+namespace {
+
+struct dd {
+    double h, l;
+};
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+    const double s = a + b;
+    const double bb = s - a;
+    dd r;
+    r.h = s;
+    r.l = (a - (s - bb)) + (b - bb);
+    return r;
+}
+
+__device__ __forceinline__ dd dd_add(dd x, dd y) {
+    const dd s = two_sum(x.h, y.h);
+    const double e = s.l + (x.l + y.l);
+    dd r;
+    r.h = s.h + e;
+    r.l = e - (r.h - s.h);
+    return r;
+}
+
+constexpr int kThreads = 1024;
+
+__global__ void __launch_bounds__(kThreads) final_reduce(const double *__restrict__ partials, long long count,
+                                                          double *__restrict__ out) {
+    __shared__ double sh[2 * kThreads];
+    const int t = threadIdx.x;
+    dd acc;
+    acc.h = 0.0;
+    acc.l = 0.0;
+    for (long long b = t; b < count; b += kThreads) {
+        dd v;
+        v.h = partials[2 * b];
+        v.l = partials[2 * b + 1];
+        acc = dd_add(acc, v);
+    }
+    sh[2 * t] = acc.h;
+    sh[2 * t + 1] = acc.l;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            dd a, b;
+            a.h = sh[2 * t];
+            a.l = sh[2 * t + 1];
+            b.h = sh[2 * (t + s)];
+            b.l = sh[2 * (t + s) + 1];
+            a = dd_add(a, b);
+            sh[2 * t] = a.h;
+            sh[2 * t + 1] = a.l;
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = sh[0];
+        out[1] = sh[1];
+    }
+}
+
+}  // namespace
+
+namespace permx {
+
+hipError_t launch_final_reduce(const double *partials, long long count, double *out, hipStream_t stream) {
+    hipLaunchKernelGGL(final_reduce, dim3(1), dim3(kThreads), 0, stream, partials, count, out);
+    return hipGetLastError();
+}
+
+}  // namespace permx

@@ -1,0 +1,349 @@
+// runtime.cpp -- the C ABI of libperm_mi355x (include/perm.h): device state,
+// launch of generated kernels, the fixed-order reduction and the
+// introspection entry points.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "jit.h"
+#include "perm_internal.h"
+#include "reduce.h"
+
+using namespace permx;
+
+namespace {
+
+thread_local std::string t_err = "no error";
+
+perm_status fail(perm_status s, const std::string &msg) {
+    t_err = msg;
+    return s;
+}
+
+#define HIP_TRY(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(PERM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+// Lanes per launch; larger jobs are split into several launches over
+// consecutive chunk ranges (each launch writes its own partials range).
+constexpr int64_t kMaxBlocksPerLaunch = 1 << 16;
+
+struct LoadedKernel {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    int waves_per_simd = 0;
+};
+
+struct DeviceState {
+    bool ready = false;
+    int device = -1;
+    std::string arch;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    double *partials = nullptr;
+    size_t partials_cap = 0;  // doubles
+    double *xg = nullptr;
+    size_t xg_cap = 0;        // doubles
+    double *out = nullptr;    // 2 doubles
+    std::unordered_map<std::string, LoadedKernel> kernels;  // source -> module
+};
+
+std::mutex g_mu;  // serialises device use (the library is thread-safe, not concurrent)
+DeviceState g_dev;
+
+perm_status ensure_device() {
+    if (g_dev.ready) return PERM_OK;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) return fail(PERM_EDEVICE, "no HIP device available");
+    HIP_TRY(hipGetDevice(&g_dev.device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, g_dev.device));
+    g_dev.arch = prop.gcnArchName;
+    if (g_dev.arch.compare(0, 6, "gfx950") != 0)
+        return fail(PERM_EDEVICE, "device " + g_dev.arch + " is not gfx950 (MI355X); kernels are built for gfx950 only");
+    HIP_TRY(hipStreamCreateWithFlags(&g_dev.stream, hipStreamNonBlocking));
+    for (auto &ev : g_dev.ev) HIP_TRY(hipEventCreate(&ev));
+    HIP_TRY(hipMalloc(&g_dev.out, 2 * sizeof(double)));
+    g_dev.ready = true;
+    return PERM_OK;
+}
+
+perm_status ensure_buffer(double **buf, size_t *cap, size_t need) {
+    if (need <= *cap) return PERM_OK;
+    if (*buf) HIP_TRY(hipFree(*buf));
+    *buf = nullptr;
+    *cap = 0;
+    size_t want = need + need / 4;
+    if (hipMalloc(buf, want * sizeof(double)) != hipSuccess) {
+        *buf = nullptr;
+        return fail(PERM_ENOMEM, "device allocation of " + std::to_string(want * 8) + " bytes failed");
+    }
+    *cap = want;
+    return PERM_OK;
+}
+
+perm_status load_kernel(const std::string &src, const CodeObject &co, int block, LoadedKernel **out) {
+    auto it = g_dev.kernels.find(src);
+    if (it == g_dev.kernels.end()) {
+        LoadedKernel k;
+        HIP_TRY(hipModuleLoadData(&k.mod, co.code.data()));
+        HIP_TRY(hipModuleGetFunction(&k.fn, k.mod, kGrayKernelName));
+        int blocks_per_cu = 0;
+        HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, k.fn, block, 0));
+        k.waves_per_simd = blocks_per_cu * (block / 64) / 4;
+        it = g_dev.kernels.emplace(src, k).first;
+    }
+    *out = &it->second;
+    return PERM_OK;
+}
+
+perm_opts defaults(const perm_opts *o) {
+    perm_opts d;
+    memset(&d, 0, sizeof d);
+    if (o) d = *o;
+    return d;
+}
+
+// Validation, structural check, plan and source: everything before the GPU.
+struct Prepared {
+    Ccs a;
+    int rank = 0;
+    bool singular = false;
+    Plan plan;
+    std::string src;
+    double host_ms = 0;
+};
+
+perm_status prepare(const perm_csc *m, const perm_opts &o, Prepared *p, bool want_source) {
+    auto t0 = std::chrono::steady_clock::now();
+    std::string err;
+    perm_status s = normalize_ccs(m, &p->a, &err);
+    if (s != PERM_OK) return fail(s, err);
+    p->rank = structural_rank(p->a);
+    p->singular = p->rank < p->a.n;
+    if (!p->singular || !want_source) {
+        s = make_plan(p->a, o, &p->plan, &err);
+        if (s != PERM_OK) return fail(s, err);
+        if (want_source && !p->singular) p->src = generate_source(p->plan);
+    }
+    p->host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return PERM_OK;
+}
+
+void fill_plan_stats(const Prepared &p, perm_stats *st) {
+    st->n = p.a.n;
+    st->nnz = p.a.nnz();
+    st->host_ms = p.host_ms;
+    st->steps = std::ldexp(1.0, p.a.n - 1);
+    st->singular = p.singular ? 1 : 0;
+    if (p.singular) return;
+    const Plan &pl = p.plan;
+    st->mode = pl.mode;
+    st->k = pl.k;
+    st->c = pl.c;
+    st->levels = pl.nlevels;
+    st->chunk_log2 = pl.kappa;
+    st->unroll_log2 = pl.u;
+    st->block = pl.block;
+    st->ops_per_step = pl.ops_per_step;
+    st->flops_per_step = pl.flops_per_step;
+    st->nchunks = (int64_t)1 << (pl.n - 1 - pl.kappa);
+    st->nblocks = (st->nchunks + pl.block - 1) / pl.block;
+}
+
+perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_stats *st_out) {
+    auto t0 = std::chrono::steady_clock::now();
+    perm_stats st;
+    memset(&st, 0, sizeof st);
+    const perm_opts o = defaults(opts);
+    Prepared p;
+    perm_status s = prepare(m, o, &p, true);
+    if (s != PERM_OK) return s;
+    fill_plan_stats(p, &st);
+    if (p.singular) {
+        *out = 0.0;  // no perfect matching: every permutation product has a zero factor
+        st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (st_out) *st_out = st;
+        return PERM_OK;
+    }
+    CodeObject co;
+    std::string err;
+    s = compile_source(p.src, &co, &err);
+    if (s != PERM_OK) return fail(s, err);
+    st.compile_ms = co.compile_ms;
+    st.cache_hit = co.cache_hit ? 1 : 0;
+    st.vgprs = co.vgprs;
+    st.sgprs = co.sgprs;
+    st.scratch_bytes = co.scratch_bytes;
+    st.lds_bytes = co.lds_bytes;
+
+    std::lock_guard<std::mutex> g(g_mu);
+    s = ensure_device();
+    if (s != PERM_OK) return s;
+    LoadedKernel *kern = nullptr;
+    s = load_kernel(p.src, co, p.plan.block, &kern);
+    if (s != PERM_OK) return s;
+    st.waves_per_simd = kern->waves_per_simd;
+
+    const Plan &pl = p.plan;
+    const int64_t nchunks = st.nchunks;
+    const int64_t nblocks = st.nblocks;
+    const int64_t launch_blocks = std::min<int64_t>(nblocks, kMaxBlocksPerLaunch);
+    s = ensure_buffer(&g_dev.partials, &g_dev.partials_cap, 2 * (size_t)nblocks);
+    if (s != PERM_OK) return s;
+    const uint64_t xs = (uint64_t)launch_blocks * pl.block;  // lanes of one launch
+    if (pl.cold) {
+        s = ensure_buffer(&g_dev.xg, &g_dev.xg_cap, (size_t)(pl.n - pl.k) * xs);
+        if (s != PERM_OK) return s;
+    }
+    hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : g_dev.stream;
+    HIP_TRY(hipEventRecord(g_dev.ev[0], stream));
+    for (int64_t b0 = 0; b0 < nblocks; b0 += launch_blocks) {
+        const int64_t nb = std::min<int64_t>(launch_blocks, nblocks - b0);
+        uint64_t chunk_begin = (uint64_t)b0 * pl.block;
+        uint64_t chunk_end = std::min<uint64_t>((uint64_t)nchunks, chunk_begin + (uint64_t)nb * pl.block);
+        double *part = g_dev.partials + 2 * b0;
+        double *xg = g_dev.xg;
+        uint64_t xs_arg = xs;
+        void *args[] = {&chunk_begin, &chunk_end, &part, &xg, &xs_arg};
+        HIP_TRY(hipModuleLaunchKernel(kern->fn, (unsigned)nb, 1, 1, (unsigned)pl.block, 1, 1, 0, stream, args,
+                                      nullptr));
+    }
+    HIP_TRY(hipEventRecord(g_dev.ev[1], stream));
+    HIP_TRY(launch_final_reduce(g_dev.partials, (long long)nblocks, g_dev.out, stream));
+    HIP_TRY(hipEventRecord(g_dev.ev[2], stream));
+    double hl[2];
+    HIP_TRY(hipMemcpyAsync(hl, g_dev.out, sizeof hl, hipMemcpyDeviceToHost, stream));
+    if (o.block_partials && o.block_partials_cap >= nblocks)
+        HIP_TRY(hipMemcpyAsync(o.block_partials, g_dev.partials, 2 * sizeof(double) * (size_t)nblocks,
+                               hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, g_dev.ev[0], g_dev.ev[1]));
+    st.kernel_ms = ms;
+    HIP_TRY(hipEventElapsedTime(&ms, g_dev.ev[1], g_dev.ev[2]));
+    st.reduce_ms = ms;
+    st.sum_hi = hl[0];
+    st.sum_lo = hl[1];
+    // final factor of Alg. 1: 4 (n mod 2) - 2 = (-1)^(n-1) * 2 (exact scaling)
+    const double f = (pl.n % 2 == 1) ? 2.0 : -2.0;
+    *out = (hl[0] + hl[1]) * f;
+    st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (st_out) *st_out = st;
+    return PERM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+double perm_sparse(int32_t n, const int32_t *colptr, const int32_t *rowidx, const double *val) {
+    perm_csc a{n, colptr, rowidx, val};
+    double out = 0.0;
+    if (run_one(&a, nullptr, &out, nullptr) != PERM_OK) return std::numeric_limits<double>::quiet_NaN();
+    return out;
+}
+
+perm_status perm_sparse_ex(const perm_csc *a, const perm_opts *opts, double *out, perm_stats *st) {
+    if (!out) return fail(PERM_EINVAL, "null output pointer");
+    return run_one(a, opts, out, st);
+}
+
+perm_status perm_batch(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out) {
+    if (count < 0 || (count > 0 && (!mats || !out))) return fail(PERM_EINVAL, "bad batch arguments");
+    for (int32_t i = 0; i < count; ++i) {
+        perm_status s = run_one(&mats[i], opts, &out[i], nullptr);
+        if (s != PERM_OK) return fail(s, "matrix " + std::to_string(i) + ": " + t_err);
+    }
+    return PERM_OK;
+}
+
+perm_status perm_plan(const perm_csc *a, const perm_opts *opts, int32_t *row_perm, int32_t *col_perm, double *tau,
+                      int32_t *k, int32_t *c, int32_t *levels, int32_t *rank) {
+    const perm_opts o = defaults(opts);
+    Prepared p;
+    perm_status s = prepare(a, o, &p, false);
+    if (s != PERM_OK) return s;
+    const int n = p.a.n;
+    if (rank) *rank = p.rank;
+    if (row_perm)
+        for (int i = 0; i < n; ++i) row_perm[i] = p.plan.rowPerm[i];
+    if (col_perm)
+        for (int i = 0; i < n; ++i) col_perm[i] = p.plan.colPerm[i];
+    if (tau) {
+        std::vector<double> t = tau_model(n, 28);
+        for (int i = 0; i <= 2 * n; ++i) tau[i] = t[i];
+    }
+    if (k) *k = p.plan.k;
+    if (c) *c = p.plan.c;
+    if (levels) *levels = p.plan.nlevels;
+    return PERM_OK;
+}
+
+perm_status perm_partition(const perm_csc *ordered, const double *tau, double gr_ratio, int32_t *k, int32_t *c) {
+    Ccs a;
+    std::string err;
+    perm_status s = normalize_ccs(ordered, &a, &err);
+    if (s != PERM_OK) return fail(s, err);
+    if (!tau || !k || !c) return fail(PERM_EINVAL, "null tau, k or c");
+    int kk = 0, cc = 0;
+    partitioning(a, tau, gr_ratio > 0 ? gr_ratio : 16.0, &kk, &cc);
+    *k = kk;
+    *c = cc;
+    return PERM_OK;
+}
+
+perm_status perm_codegen(const perm_csc *a, const perm_opts *opts, char *buf, size_t cap, size_t *len) {
+    const perm_opts o = defaults(opts);
+    Prepared p;
+    perm_status s = prepare(a, o, &p, true);
+    if (s != PERM_OK) return s;
+    if (p.singular) return fail(PERM_EINVAL, "structurally singular matrix: no kernel is generated");
+    if (len) *len = p.src.size();
+    if (buf && cap) {
+        size_t nc = std::min(cap - 1, p.src.size());
+        memcpy(buf, p.src.data(), nc);
+        buf[nc] = '\0';
+    }
+    return PERM_OK;
+}
+
+perm_status perm_compile_info(const perm_csc *a, const perm_opts *opts, perm_stats *st) {
+    const perm_opts o = defaults(opts);
+    Prepared p;
+    perm_status s = prepare(a, o, &p, true);
+    if (s != PERM_OK) return s;
+    if (!st) return fail(PERM_EINVAL, "null stats");
+    memset(st, 0, sizeof *st);
+    fill_plan_stats(p, st);
+    if (p.singular) return PERM_OK;
+    CodeObject co;
+    std::string err;
+    s = compile_source(p.src, &co, &err);
+    if (s != PERM_OK) return fail(s, err);
+    st->compile_ms = co.compile_ms;
+    st->cache_hit = co.cache_hit;
+    st->vgprs = co.vgprs;
+    st->sgprs = co.sgprs;
+    st->scratch_bytes = co.scratch_bytes;
+    st->lds_bytes = co.lds_bytes;
+    return PERM_OK;
+}
+
+const char *perm_last_error(void) { return t_err.c_str(); }
+
+const char *perm_version(void) { return "perm_mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,230 @@
+"""ctypes binding of libperm_mi355x.so (include/perm.h).
+
+Argument marshalling only: every step of the permanent (validation, the
+structural check, ordering, partitioning, code generation, hipRTC, the GPU
+kernels and the reduction) runs inside the C-ABI library.  If the library is
+not built, importing this module raises; there is no fallback.
+
+A matrix is a CCS tuple ``(n, colptr, rowidx, val)`` (int32, int32, float64
+arrays), as produced by ``paper_2501_15126_amd.workloads``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libperm_mi355x.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libperm_mi355x.so is not built: run __graft_entry__.build() "
+                      "(hipcc for gfx950) before using paper_2501_15126_amd.perm")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+PERM_OK, PERM_EINVAL, PERM_ETOOBIG, PERM_ENOMEM, PERM_EDEVICE, PERM_ECOMPILE, PERM_EAGAIN, \
+    PERM_ENOTREADY, PERM_ECANCELED = range(9)
+STATUS_NAMES = ["PERM_OK", "PERM_EINVAL", "PERM_ETOOBIG", "PERM_ENOMEM", "PERM_EDEVICE",
+                "PERM_ECOMPILE", "PERM_EAGAIN", "PERM_ENOTREADY", "PERM_ECANCELED"]
+MODES = {"auto": 0, "pure": 1, "hybrid": 2}
+MAX_N = 64
+
+
+class PermError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS_NAMES[status] if 0 <= status < 9 else status, message))
+        self.status = status
+
+
+class PermCsc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("colptr", ctypes.POINTER(ctypes.c_int32)),
+                ("rowidx", ctypes.POINTER(ctypes.c_int32)), ("val", ctypes.POINTER(ctypes.c_double))]
+
+
+class PermOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("chunk_log2", ctypes.c_int32), ("unroll_log2", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("vgpr_budget", ctypes.c_int32), ("force_k", ctypes.c_int32),
+                ("force_c", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("gr_ratio", ctypes.c_double),
+                ("hip_stream", ctypes.c_void_p), ("block_partials", ctypes.POINTER(ctypes.c_double)),
+                ("block_partials_cap", ctypes.c_int64)]
+
+
+class PermStats(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double), ("compile_ms", ctypes.c_double),
+                ("host_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("steps", ctypes.c_double),
+                ("ops_per_step", ctypes.c_double), ("flops_per_step", ctypes.c_double),
+                ("sum_hi", ctypes.c_double), ("sum_lo", ctypes.c_double),
+                ("nblocks", ctypes.c_int64), ("nchunks", ctypes.c_int64),
+                ("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("c", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("chunk_log2", ctypes.c_int32), ("unroll_log2", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("vgprs", ctypes.c_int32), ("sgprs", ctypes.c_int32), ("scratch_bytes", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("cache_hit", ctypes.c_int32),
+                ("singular", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_P = ctypes.POINTER
+_lib.perm_sparse.restype = ctypes.c_double
+_lib.perm_sparse.argtypes = [ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_double)]
+_lib.perm_sparse_ex.restype = ctypes.c_int
+_lib.perm_sparse_ex.argtypes = [_P(PermCsc), _P(PermOpts), _P(ctypes.c_double), _P(PermStats)]
+_lib.perm_batch.restype = ctypes.c_int
+_lib.perm_batch.argtypes = [ctypes.c_int32, _P(PermCsc), _P(PermOpts), _P(ctypes.c_double)]
+_lib.perm_plan.restype = ctypes.c_int
+_lib.perm_plan.argtypes = [_P(PermCsc), _P(PermOpts), _P(ctypes.c_int32), _P(ctypes.c_int32),
+                           _P(ctypes.c_double), _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32),
+                           _P(ctypes.c_int32)]
+_lib.perm_partition.restype = ctypes.c_int
+_lib.perm_partition.argtypes = [_P(PermCsc), _P(ctypes.c_double), ctypes.c_double, _P(ctypes.c_int32),
+                                _P(ctypes.c_int32)]
+_lib.perm_codegen.restype = ctypes.c_int
+_lib.perm_codegen.argtypes = [_P(PermCsc), _P(PermOpts), ctypes.c_char_p, ctypes.c_size_t,
+                              _P(ctypes.c_size_t)]
+_lib.perm_compile_info.restype = ctypes.c_int
+_lib.perm_compile_info.argtypes = [_P(PermCsc), _P(PermOpts), _P(PermStats)]
+_lib.perm_last_error.restype = ctypes.c_char_p
+_lib.perm_last_error.argtypes = []
+_lib.perm_version.restype = ctypes.c_char_p
+_lib.perm_version.argtypes = []
+
+# every symbol include/perm.h declares
+EXPORTED = ["perm_sparse", "perm_sparse_ex", "perm_batch", "perm_plan", "perm_partition", "perm_codegen",
+            "perm_compile_info", "perm_last_error", "perm_version"]
+
+
+def library():
+    return _lib
+
+
+def last_error() -> str:
+    return _lib.perm_last_error().decode()
+
+
+def version() -> str:
+    return _lib.perm_version().decode()
+
+
+class _Csc:
+    """Holds the arrays alive while the C struct points at them."""
+
+    def __init__(self, ccs):
+        n, colptr, rowidx, val = ccs
+        self.colptr = np.ascontiguousarray(colptr, dtype=np.int32)
+        self.rowidx = np.ascontiguousarray(rowidx, dtype=np.int32)
+        self.val = np.ascontiguousarray(val, dtype=np.float64)
+        if self.rowidx.size == 0:  # keep valid pointers for empty matrices
+            self.rowidx = np.zeros(1, np.int32)
+            self.val = np.zeros(1, np.float64)
+        self.c = PermCsc(int(n), self.colptr.ctypes.data_as(_P(ctypes.c_int32)),
+                         self.rowidx.ctypes.data_as(_P(ctypes.c_int32)),
+                         self.val.ctypes.data_as(_P(ctypes.c_double)))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):  # torch.cuda.Stream
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, force_k=0, force_c=0,
+              max_levels=0, gr_ratio=0.0, stream=None):
+    o = PermOpts()
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    o.chunk_log2, o.unroll_log2, o.block = chunk_log2, unroll_log2, block
+    o.vgpr_budget, o.force_k, o.force_c, o.max_levels = vgpr_budget, force_k, force_c, max_levels
+    o.gr_ratio = gr_ratio
+    o.hip_stream = _stream_handle(stream)
+    return o
+
+
+def _check(status):
+    if status != PERM_OK:
+        raise PermError(status, last_error())
+
+
+def perm_sparse(n, colptr, rowidx, val) -> float:
+    """Permanent (NaN on error, as the C call)."""
+    m = _Csc((n, colptr, rowidx, val))
+    return _lib.perm_sparse(m.c.n, m.c.colptr, m.c.rowidx, m.c.val)
+
+
+def perm_sparse_ex(ccs, block_partials=False, **opts):
+    """Returns (value, stats dict[, partials array (nblocks, 2)])."""
+    m = _Csc(ccs)
+    o = make_opts(**opts)
+    parts = None
+    if block_partials:
+        plan_stats = compile_plan_stats(ccs, **opts)
+        nb = max(1, int(plan_stats["nblocks"]))
+        parts = np.zeros((nb, 2), np.float64)
+        o.block_partials = parts.ctypes.data_as(_P(ctypes.c_double))
+        o.block_partials_cap = nb
+    out = ctypes.c_double()
+    st = PermStats()
+    _check(_lib.perm_sparse_ex(ctypes.byref(m.c), ctypes.byref(o), ctypes.byref(out), ctypes.byref(st)))
+    if block_partials:
+        return out.value, st.as_dict(), parts
+    return out.value, st.as_dict()
+
+
+def perm_batch(mats, **opts):
+    held = [_Csc(c) for c in mats]
+    arr = (PermCsc * max(1, len(held)))(*[h.c for h in held])
+    out = np.zeros(max(1, len(held)), np.float64)
+    o = make_opts(**opts)
+    _check(_lib.perm_batch(len(held), arr, ctypes.byref(o), out.ctypes.data_as(_P(ctypes.c_double))))
+    return out[:len(held)]
+
+
+def perm_plan(ccs, **opts):
+    m = _Csc(ccs)
+    n = int(ccs[0])
+    rp = np.zeros(n, np.int32)
+    cp = np.zeros(n, np.int32)
+    tau = np.zeros(2 * n + 1, np.float64)
+    k, c, lev, rank = (ctypes.c_int32() for _ in range(4))
+    o = make_opts(**opts)
+    _check(_lib.perm_plan(ctypes.byref(m.c), ctypes.byref(o), rp.ctypes.data_as(_P(ctypes.c_int32)),
+                          cp.ctypes.data_as(_P(ctypes.c_int32)), tau.ctypes.data_as(_P(ctypes.c_double)),
+                          ctypes.byref(k), ctypes.byref(c), ctypes.byref(lev), ctypes.byref(rank)))
+    return {"row_perm": rp.tolist(), "col_perm": cp.tolist(), "tau": tau, "k": k.value, "c": c.value,
+            "levels": lev.value, "structural_rank": rank.value}
+
+
+def perm_partition(ordered_ccs, tau, gr_ratio=16.0):
+    m = _Csc(ordered_ccs)
+    tau = np.ascontiguousarray(tau, np.float64)
+    k, c = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.perm_partition(ctypes.byref(m.c), tau.ctypes.data_as(_P(ctypes.c_double)), gr_ratio,
+                               ctypes.byref(k), ctypes.byref(c)))
+    return k.value, c.value
+
+
+def perm_codegen(ccs, **opts) -> str:
+    m = _Csc(ccs)
+    o = make_opts(**opts)
+    ln = ctypes.c_size_t()
+    _check(_lib.perm_codegen(ctypes.byref(m.c), ctypes.byref(o), None, 0, ctypes.byref(ln)))
+    buf = ctypes.create_string_buffer(ln.value + 1)
+    _check(_lib.perm_codegen(ctypes.byref(m.c), ctypes.byref(o), buf, ln.value + 1, ctypes.byref(ln)))
+    return buf.value.decode()
+
+
+def compile_info(ccs, **opts):
+    """hipRTC-compile the generated kernel (no GPU needed); plan + resources."""
+    m = _Csc(ccs)
+    o = make_opts(**opts)
+    st = PermStats()
+    _check(_lib.perm_compile_info(ctypes.byref(m.c), ctypes.byref(o), ctypes.byref(st)))
+    return st.as_dict()
+
+
+def compile_plan_stats(ccs, **opts):
+    return compile_info(ccs, **opts)

@@ -1,0 +1,17 @@
+// cpu_shim.h -- lets a generated gfx950 kernel source compile as plain C++ on
+// the host, so that its per-lane function perm_lane() can be run on the CPU in
+// tests of the code generator.  Only the per-lane arithmetic is exercised; the
+// cross-lane reduction of the kernel is compiled but never called.
+#include <cmath>
+#include <cstdint>
+#define __global__
+#define __device__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __restrict__
+#define __shared__ static
+struct cpu_dim3 { unsigned x, y, z; };
+static cpu_dim3 threadIdx, blockIdx;
+static inline void __syncthreads() {}
+static inline double __shfl_xor(double v, int, int) { return v; }
+using std::fma;

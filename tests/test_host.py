@@ -1,0 +1,254 @@
+"""CPU-only tests of the C-ABI library: exported symbols, input validation,
+the host-side steps (structural check, Alg. 4 ordering, Alg. 5 partition)
+against the oracle bit for bit, the chunk schedule, the code generator (hex
+literals, hipRTC resources) and the generated per-lane code run on the CPU.
+None of these launch a GPU kernel.
+"""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2501_15126_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SHIM = os.path.join(os.path.dirname(os.path.abspath(__file__)), "support", "cpu_shim.h")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2501_15126_amd.perm as P
+    return P
+
+
+def test_exports_every_declared_symbol(P):
+    with open(os.path.join(ROOT, "include", "perm.h")) as f:
+        hdr = f.read()
+    declared = set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(perm_\w+)\s*\(", hdr, re.M))
+    assert {"perm_sparse", "perm_sparse_ex", "perm_batch", "perm_plan", "perm_codegen"} <= declared
+    lib = ctypes.CDLL(P.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert set(P.EXPORTED) == declared
+    assert "gfx950" in P.version()
+
+
+def test_no_oracle_in_product_library(P):
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True, text=True).stdout
+    assert "oracle" not in out
+    for f in os.listdir(os.path.join(ROOT, "paper_2501_15126_amd", "csrc")):
+        with open(os.path.join(ROOT, "paper_2501_15126_amd", "csrc", f)) as fh:
+            assert "oracle" not in fh.read().lower(), f
+
+
+@pytest.mark.parametrize("bad,status", [
+    ((3, [1, 1, 2, 3], [0, 1, 2], [1.0, 1.0, 1.0]), "PERM_EINVAL"),        # colptr[0] != 0
+    ((3, [0, 2, 1, 3], [0, 1, 2], [1.0, 1.0, 1.0]), "PERM_EINVAL"),        # decreasing colptr
+    ((3, [0, 1, 2, 3], [0, 3, 2], [1.0, 1.0, 1.0]), "PERM_EINVAL"),        # row out of range
+    ((3, [0, 2, 3, 4], [1, 0, 1, 2], [1.0, 1.0, 1.0, 1.0]), "PERM_EINVAL"),  # unsorted rows
+    ((3, [0, 2, 3, 4], [1, 1, 1, 2], [1.0, 1.0, 1.0, 1.0]), "PERM_EINVAL"),  # duplicate row
+    ((3, [0, 1, 2, 3], [0, 1, 2], [1.0, np.nan, 1.0]), "PERM_EINVAL"),     # non-finite
+    ((3, [0, 1, 2, 3], [0, 1, 2], [1.0, np.inf, 1.0]), "PERM_EINVAL"),
+    ((0, [0], [], []), "PERM_EINVAL"),
+    ((65, list(range(66)), list(range(65)), [1.0] * 65), "PERM_ETOOBIG"),
+])
+def test_validation(P, bad, status):
+    n, cp, ri, v = bad
+    with pytest.raises(P.PermError) as e:
+        P.perm_plan((n, np.array(cp), np.array(ri), np.array(v)))
+    assert P.STATUS_NAMES[e.value.status] == status
+    assert P.last_error()
+
+
+def test_structural_rank_matches_oracle(P, oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(0)
+    for t in range(80):
+        n = int(rng.integers(1, 40))
+        ccs = W.random_sparse(n, float(rng.uniform(0.02, 0.3)), seed=t, kind="01", diag=bool(t % 2))
+        if len(ccs[1]) and ccs[1][-1] == 0:
+            continue
+        assert P.perm_plan(ccs)["structural_rank"] == O.structural_rank(ccs)
+
+
+def test_explicit_zeros_are_dropped(P, oracle_mod):
+    O = oracle_mod
+    A = np.eye(5)
+    A[0, 1] = 1.0
+    ccs = O.dense_to_ccs(A)
+    n, cp, ri, v = ccs
+    # same pattern plus explicit zeros in every column
+    Az = O.ccs_to_dense(ccs)
+    cols, rows, vals, ptr = [], [], [], [0]
+    for j in range(5):
+        for i in range(5):
+            if Az[i, j] != 0 or (i + j) % 2 == 0:
+                rows.append(i)
+                vals.append(Az[i, j])
+        ptr.append(len(rows))
+    z = (5, np.array(ptr), np.array(rows), np.array(vals))
+    pz, pc = P.perm_plan(z), P.perm_plan(ccs)
+    assert pz["row_perm"] == pc["row_perm"] and pz["col_perm"] == pc["col_perm"]
+    assert (pz["k"], pz["c"], pz["structural_rank"]) == (pc["k"], pc["c"], pc["structural_rank"])
+    assert P.perm_codegen(z) == P.perm_codegen(ccs)
+
+
+def test_ordering_matches_oracle_alg4(P, oracle_mod):
+    O = oracle_mod
+    for seed in range(40):
+        n = 8 + seed % 33
+        ccs = W.random_sparse(n, 0.05 + 0.01 * (seed % 20), seed=seed, kind="01")
+        if P.perm_plan(ccs)["structural_rank"] < n:
+            continue
+        plan = P.perm_plan(ccs, mode="auto")
+        rp, cp = O.permanent_ordering(ccs)
+        assert plan["row_perm"] == rp and plan["col_perm"] == cp, seed
+
+
+def test_partition_matches_oracle_alg5(P, oracle_mod):
+    """Alg. 5 of the library (with its gfx950 tau table) against the oracle's
+    Alg. 5 given the same table, on Alg. 4-ordered matrices."""
+    O = oracle_mod
+    for seed in range(30):
+        n = 10 + seed
+        ccs = W.single_01(n, 0.08 + 0.01 * (seed % 10), seed)
+        plan = P.perm_plan(ccs, mode="hybrid")
+        A = O.ccs_to_dense(ccs)
+        B = O.dense_to_ccs(A[np.ix_(plan["row_perm"], plan["col_perm"])])
+        for gr in (16.0, 4.0, 64.0):
+            k, c, _ = O.partitioning(B, plan["tau"], gr)
+            assert P.perm_partition(B, plan["tau"], gr) == (k, c)
+        k, c, _ = O.partitioning(B, plan["tau"], 16.0)
+        assert (plan["k"], plan["c"]) == (k, min(c, n - 1))
+
+
+def test_partition_paper_worked_example(P):
+    """The hand-worked 6x6 instance of Alg. 5 (see the oracle pins) through
+    the library's partition step."""
+    cols = [[0, 1], [1, 2], [0, 3], [2, 4], [3, 5], [4, 5]]
+    colptr = np.cumsum([0] + [len(c) for c in cols]).astype(np.int32)
+    rowidx = np.array(sum(cols, []), np.int32)
+    tau = [1200.0 / (r + 8) for r in range(13)]
+    assert P.perm_partition((6, colptr, rowidx, np.ones(len(rowidx))), tau, 16.0) == (4, 3)
+
+
+def test_tau_model_gfx950(P):
+    plan = P.perm_plan(W.single_01(40, 0.1, 1))
+    tau = plan["tau"]
+    # 256 CUs x 4 SIMDs x 64 lanes x waves; waves = min(8, 512 // vgprs)
+    assert tau[0] == 256 * 4 * 64 * 8
+    assert all(tau[i] >= tau[i + 1] for i in range(len(tau) - 1))
+    assert set(np.unique(tau)) <= {256 * 4 * 64 * w for w in range(1, 9)}
+
+
+def test_schedule_covers_range(P):
+    for n in (1, 2, 3, 9, 24, 36, 40, 52):
+        info = P.compile_info(W.single_01(n, 0.3, 2))
+        if info["singular"]:
+            continue
+        assert info["nchunks"] << info["chunk_log2"] == 1 << (n - 1)
+        assert info["nblocks"] * info["block"] >= info["nchunks"] > (info["nblocks"] - 1) * info["block"]
+        assert 0 <= info["unroll_log2"] <= max(0, info["chunk_log2"] - 1)
+
+
+def test_aligned_chunks_are_wave_uniform(oracle_mod):
+    """Lemma 2 on aligned power-of-two chunks: for 64 consecutive chunks (one
+    wave), local step l flips the same column in every lane; the direction is
+    the same except at l = 2^(kappa-1), where it is the chunk parity.  The
+    step l = 2^kappa (which would differ in column) belongs to the next chunk."""
+    O = oracle_mod
+    for kappa in (1, 3, 6):
+        D = 1 << kappa
+        for w in (0, 3):
+            for l in range(1, D):
+                js = set()
+                ss = set()
+                for lane in range(64):
+                    m = 64 * w + lane
+                    j, s = O.changed_bit(m * D + l)
+                    js.add(j)
+                    ss.add(s)
+                    if l == D // 2:
+                        assert s == (1 if m % 2 == 0 else -1)
+                assert js == {(l & -l).bit_length() - 1}
+                assert len(ss) == (2 if l == D // 2 else 1)
+
+
+def test_codegen_hex_literals_exact(P):
+    ccs = W.single_real(12, 0.4, 3)
+    src = P.perm_codegen(ccs)
+    lits = re.findall(r"-?0x[0-9a-f]\.?[0-9a-f]*p[+-]\d+", src)
+    vals = {float.fromhex(s) for s in lits}
+    fixed = P.perm_plan(ccs)["col_perm"][-1]  # the fixed column only enters the start values
+    n, cp, ri, v = ccs
+    for j in range(n):
+        if j == fixed:
+            continue
+        for q in range(cp[j], cp[j + 1]):
+            assert float(v[q]) in vals or -float(v[q]) in vals
+
+
+def test_codegen_resources_no_scratch(P):
+    """hipRTC (gfx950) compiles without a GPU; x must stay in VGPRs."""
+    for ccs in (W.single_01(40, 0.10, 1), W.single_real(36, 0.30, 1), W.single_01(24, 0.15, 1)):
+        for mode in ("auto", "pure", "hybrid"):
+            info = P.compile_info(ccs, mode=mode)
+            assert info["scratch_bytes"] == 0, (ccs[0], mode)
+            assert info["vgprs"] <= 256
+        assert P.compile_info(ccs)["vgprs"] <= 128
+
+
+def _emulate(P, ccs, **opts):
+    """Run the generated perm_lane() of every chunk on the CPU (g++)."""
+    src = P.perm_codegen(ccs, **opts)
+    info = P.compile_info(ccs, **opts)
+    d = tempfile.mkdtemp(prefix="permemu")
+    f = os.path.join(d, "g.cpp")
+    with open(f, "w") as fh:
+        fh.write(src + '\nextern "C" void cpu_lane(u64 m, double* xg, u64 xs, u64 lid, double* o)'
+                 ' { dd r = perm_lane(m, xg, xs, lid); o[0] = r.h; o[1] = r.l; }\n')
+    so = os.path.join(d, "g.so")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-include", SHIM,
+                    "-o", so, f], check=True)
+    lib = ctypes.CDLL(so)
+    lib.cpu_lane.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
+    n = ccs[0]
+    xg = np.zeros(max(1, n), np.float64)
+    o = np.zeros(2)
+    tot = 0.0
+    for m in range(info["nchunks"]):
+        lib.cpu_lane(m, xg.ctypes.data, 1, 0, o.ctypes.data)
+        tot += o[0] + o[1]
+    return tot * (2.0 if n % 2 else -2.0), info
+
+
+def test_generated_code_on_cpu_matches_oracle(P, oracle_mod):
+    """The generator's per-lane code (all three kernel families, several chunk
+    and unroll sizes) compiled for the host and summed over all chunks."""
+    O = oracle_mod
+    cases = [(W.random_sparse(10, 0.3, 0, kind="real"), 3, 1), (W.random_sparse(13, 0.25, 1, kind="signed"), 5, 2),
+             (W.single_01(16, 0.2, 2), 7, 3), (W.random_sparse(9, 0.5, 3, kind="real"), 8, 6),
+             (W.random_sparse(5, 0.6, 4, kind="signed"), 1, 1)]
+    for ccs, kappa, u in cases:
+        ref, abs_sum = O.perm_nw(ccs)
+        for mode in ("auto", "pure", "hybrid"):
+            got, info = _emulate(P, ccs, mode=mode, chunk_log2=kappa, unroll_log2=u)
+            assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12, (ccs[0], mode, kappa, u, got, ref)
+
+
+def test_generated_code_tiny_n_on_cpu(P, oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(6)
+    for n in range(1, 7):
+        A = rng.uniform(-1, 1, (n, n)) * (rng.random((n, n)) < 0.8)
+        A[np.arange(n), rng.permutation(n)] = rng.uniform(0.5, 1, n)
+        ref = O.perm_brute(A)
+        for kappa in sorted({1, n - 1}):
+            if n == 1:
+                kappa = 0
+            got, _ = _emulate(P, O.dense_to_ccs(A), chunk_log2=kappa)
+            assert got == pytest.approx(ref, rel=1e-12, abs=1e-14)
