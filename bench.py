@@ -50,6 +50,22 @@ def cpu_baseline(ccs, seconds_target=15.0):
                       % (int(math.log2(steps)), n - 1, dt)}
 
 
+def measured_traffic(src):
+    """HBM bytes per dispatch of this exact generated kernel, from the committed
+    rocprofv3 counter summary (None when the kernel source has changed)."""
+    import hashlib
+    import re
+    h = hashlib.sha256(src.encode()).hexdigest()[:16]
+    pdir = os.path.join(ROOT, "profiles")
+    for f in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
+        with open(os.path.join(pdir, f)) as fh:
+            for m in re.finditer(r"traffic: (\{.*\})", fh.read()):
+                rec = json.loads(m.group(1))
+                if rec.get("source_sha256_16") == h:
+                    return rec["bytes_per_dispatch"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,7 +75,18 @@ def main():
     ap.add_argument("--workload", default="n40_p0.10_01")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (torch), to scale HBM byte counters")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": src.numel() * 8, "dispatches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the permanent's chunk ranges would shard across GPUs with a "
               "16-byte gather per GPU, but this build runs and reports a single GPU only", file=sys.stderr)
@@ -107,7 +134,8 @@ def main():
                                % (n, args.seed), "n": n, "nnz": len(ccs[2]), "mode": args.mode,
                    "gray_steps_per_permanent": steps_per_perm},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": None},
+                     "frac": achieved_tflops / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(P.perm_codegen(ccs, mode=args.mode))},
         "kernel": {"name": "perm_gray", "avg_ms": avg_kernel_s * 1e3, "steps_per_s": steps_per_perm / avg_kernel_s,
                    "flops_per_step": st["flops_per_step"], "fp64_ops_per_step": st["ops_per_step"],
                    "fp64_issue_frac": ops_rate / 3.93216e13, "vgprs": st["vgprs"], "sgprs": st["sgprs"],
