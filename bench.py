@@ -74,6 +74,7 @@ def main():
     ap.add_argument("--mode", default="auto", choices=["auto", "pure", "hybrid"])
     ap.add_argument("--workload", default="n40_p0.10_01")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--zero-skip", default="auto", choices=["auto", "on", "off"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (torch), to scale HBM byte counters")
@@ -95,19 +96,20 @@ def main():
     import paper_2501_15126_amd.perm as P
     from paper_2501_15126_amd import workloads as W
 
+    zs = {"auto": "auto", "on": True, "off": False}[args.zero_skip]
     ccs = W.WORKLOADS[args.workload](args.seed)
     n = ccs[0]
     print("bench: workload %s seed %d n=%d nnz=%d mode %s" % (args.workload, args.seed, n, len(ccs[2]), args.mode),
           file=sys.stderr, flush=True)
     first = None
     for _ in range(args.warmup):
-        v, st = P.perm_sparse_ex(ccs, mode=args.mode)
+        v, st = P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=zs)
         first = st if first is None else first
     kernel_ms = []
     values = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        v, st = P.perm_sparse_ex(ccs, mode=args.mode)  # synchronous: result on the host
+        v, st = P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=zs)  # synchronous: result on the host
         kernel_ms.append(st["kernel_ms"])
         values.append(v)
     elapsed = time.perf_counter() - t0
@@ -132,10 +134,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single sparse 0/1 matrix n=%d, permutation pattern OR Bernoulli(0.10), seed %d"
                                % (n, args.seed), "n": n, "nnz": len(ccs[2]), "mode": args.mode,
+                   "zero_skip": args.zero_skip,
                    "gray_steps_per_permanent": steps_per_perm},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(P.perm_codegen(ccs, mode=args.mode))},
+                     "traffic": measured_traffic(P.perm_codegen(ccs, mode=args.mode, zero_skip=zs))},
         "kernel": {"name": "perm_gray", "avg_ms": avg_kernel_s * 1e3, "steps_per_s": steps_per_perm / avg_kernel_s,
                    "flops_per_step": st["flops_per_step"], "fp64_ops_per_step": st["ops_per_step"],
                    "fp64_issue_frac": ops_rate / 3.93216e13, "vgprs": st["vgprs"], "sgprs": st["sgprs"],

@@ -83,6 +83,16 @@ typedef struct {
     int32_t force_k;       /* > 0: override Alg. 5's k (HYBRID only), with force_c */
     int32_t force_c;       /* > 0: override Alg. 5's c (HYBRID only) */
     int32_t max_levels;    /* > 0: cap on cached product levels (AUTO); 0 = budget-driven */
+    int32_t zero_skip;     /* zero-aware skipping (exact): a wave skips a chunk, or a
+                              block of 2^(u+1) - 1 steps, whose terms all contain a
+                              factor that is exactly 0 in every lane.  0 = auto (on
+                              when every value is an integer, where such zeros are
+                              common), 1 = on, -1 = off */
+    int32_t batch_mode;    /* perm_batch: 0 = the whole batch as one captured graph of
+                              launches (default); 1 = the same launches without a
+                              graph; 2 = one matrix per launch, synchronised after
+                              each (the sequential baseline) */
+    int32_t batch_kappa_shift; /* perm_batch: added to the default chunk log2 */
     double gr_ratio;       /* Alg. 5 global/register update cost ratio; 0 = 16 */
     void *hip_stream;      /* hipStream_t to launch on; NULL = the library's stream */
     /* Optional host output: per-workgroup partial sums of the Gray-term sum
@@ -128,10 +138,30 @@ double perm_sparse(int32_t n, const int32_t *colptr, const int32_t *rowidx, cons
  * st may be NULL.  Synchronous: returns after the result is on the host. */
 perm_status perm_sparse_ex(const perm_csc *a, const perm_opts *opts, double *out, perm_stats *st);
 
-/* Permanents of `count` matrices (any mix of sizes), out[i] for mats[i].
- * Synchronous.  Each result equals perm_sparse_ex's for that matrix alone,
- * bitwise, with the same options. */
+/* Permanents of `count` matrices (any mix of sizes n <= 64), out[i] for
+ * mats[i].  Synchronous.  Uses kernels compiled into the library (no per-matrix
+ * hipRTC): x in registers as 4-row groups, each matrix's columns as data, 64
+ * chunks of one matrix per wave, all matrices in one graph of launches.  A
+ * matrix's result depends only on that matrix and the options, not on the
+ * rest of the batch (bitwise).  Results agree with perm_sparse_ex within the
+ * FP64 tolerance, not bitwise (different kernels).  Any invalid matrix fails
+ * the whole call (PERM_EINVAL, perm_last_error names its index). */
 perm_status perm_batch(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out);
+
+typedef struct {
+    double wall_ms;        /* whole call */
+    double prep_ms;        /* host preparation of all matrices */
+    double kernel_ms;      /* device time of the launches (events on the stream) */
+    double steps;          /* Gray-code steps of the nonsingular matrices */
+    int32_t count;         /* matrices */
+    int32_t singular;      /* answered 0 by the structural check */
+    int32_t launches;      /* kernel launches issued */
+    int32_t pad;
+} perm_batch_stats;
+
+/* perm_batch with statistics (st may be NULL). */
+perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out,
+                          perm_batch_stats *st);
 
 /* ---- Introspection of the host-side steps (used by tests) -------------- */
 

@@ -1,0 +1,28 @@
+// batch_types.h -- plain data shared by the batch kernels and their host code.
+#pragma once
+
+#include <cstdint>
+
+namespace permx {
+
+// Descriptor of one matrix of a batch (device-resident).
+struct BatchMat {
+    int32_t n, ng, kappa;           // size, 4-row groups of x, chunk log2
+    int32_t zero_skip, chunk_top;   // zero-aware skipping on; highest group any in-chunk column touches
+    int32_t pad;
+    uint64_t nchunks;               // 2^(n-1-kappa)
+    uint64_t col_off;               // doubles: column groups [j][g][4]
+    uint64_t base_off;              // doubles: x at Gray index 0, 4*ng values (padding rows 1.0)
+    uint64_t top_off;               // int32: top group of each flipped column
+};
+
+// One wave of work: 64 consecutive chunks of one matrix.
+struct BatchItem {
+    int32_t mat;
+    int32_t pad;
+    uint64_t chunk0;
+};
+
+constexpr int kBatchMaxNG = 16;  // n <= 64
+
+}  // namespace permx

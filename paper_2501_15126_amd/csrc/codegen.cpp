@@ -236,12 +236,39 @@ struct Gen {
         // ---- Gray loop over local steps 1 .. 2^kappa - 1 ----
         if (kappa >= 1) {
             os << "  const double lsgn = (m & 1ull) ? -1.0 : 1.0;  // direction at local step 2^(kappa-1)\n";
+            // Zero-aware skipping (exact): a product with a factor that is
+            // exactly 0 adds exactly 0.  Rows on levels above every level the
+            // chunk's columns touch stay constant for the whole chunk; when
+            // their cached product is 0 in all 64 lanes the wave skips the chunk.
+            int chunk_top = 0;
+            for (int j = 0; j < kappa; ++j) chunk_top = std::max(chunk_top, p.col_top[j]);
+            const bool skip_chunk = p.zero_skip && chunk_top + 1 <= L - 1;
+            if (skip_chunk) os << "  if (!__all(S" << chunk_top + 1 << " == 0.0)) {\n";
             os << "#pragma clang loop unroll(disable)\n";
             os << "  for (u32 base = 0; base < " << DELTA << "u; base += " << 2 * U << "u) {\n";
-            static_block(false, "    ");
             // local step base + 2^u flips column u; its direction is bit u+1
             // of the local index (uniform), or the chunk parity when u+1 = kappa
             const int term_u = (u == 0) ? -1 : 1;
+            // The same for one pair of static blocks (2^(u+1) - 1 steps touching
+            // columns 0..u only): when the rows above those columns' levels
+            // have a zero product in every lane, all those terms are 0 and the
+            // blocks reduce to their net effect on x, one flip of column u.
+            int block_top = 0;
+            for (int j = 0; j <= u; ++j) block_top = std::max(block_top, p.col_top[j]);
+            const bool skip_block = p.zero_skip && u >= 1 && block_top + 1 <= L - 1;
+            if (skip_block) {
+                os << "    if (__all(S" << block_top + 1 << " == 0.0)) {\n";
+                std::map<int, std::string> cur;
+                if (u + 1 == kappa) {
+                    update(u, Sign::Lane, cur, "      ");
+                } else {
+                    os << "      const bool neg = (base >> " << (u + 1) << ") & 1u;\n";
+                    update(u, Sign::Uniform, cur, "      ");
+                }
+                for (int l = block_top; l >= 1; --l) refresh_level(l, cur, "      ");
+                os << "    } else {\n";
+            }
+            static_block(false, "    ");
             if (u + 1 == kappa) {
                 step(u, Sign::Lane, term_u, 0, "    ");
             } else {
@@ -250,6 +277,7 @@ struct Gen {
                 os << "    }\n";
             }
             static_block(true, "    ");
+            if (skip_block) os << "    }\n";
             // local step base + 2^(u+1): column jj = ctz >= u + 1, the same in
             // every lane.  Branch-free: for each row that one of these columns
             // touches, a scalar select picks that column's entry (0 when row r
@@ -295,6 +323,7 @@ struct Gen {
                 os << "    }\n";
             }
             os << "  }\n";
+            if (skip_chunk) os << "  }\n";
         }
         os << "  return two_sum(acc0, acc1);\n}\n";
         // ---- the kernel: one chunk per lane, then a deterministic reduction

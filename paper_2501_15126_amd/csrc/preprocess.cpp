@@ -263,6 +263,18 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
     }
     p->u = std::max(0, std::min(p->u, p->kappa - 1));
     p->block = o.block > 0 ? o.block : 256;
+    if (o.zero_skip > 0) {
+        p->zero_skip = true;
+    } else if (o.zero_skip < 0) {
+        p->zero_skip = false;
+    } else {
+        // x_i is an exact zero at many Gray indices only when the values are
+        // integers (then 2 x_i is an integer); real-valued inputs almost never
+        // produce one, and the checks would only cost registers.
+        p->zero_skip = true;
+        for (double v : B.val)
+            if (v != std::floor(v)) p->zero_skip = false;
+    }
     if (p->block % 64 != 0 || p->block > 1024) {
         *err = "block must be a multiple of 64 and at most 1024";
         return PERM_EINVAL;

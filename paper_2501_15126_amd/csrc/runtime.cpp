@@ -13,6 +13,7 @@
 #include <string>
 #include <unordered_map>
 
+#include "batch_host.h"
 #include "jit.h"
 #include "perm_internal.h"
 #include "reduce.h"
@@ -61,6 +62,9 @@ struct DeviceState {
 
 std::mutex g_mu;  // serialises device use (the library is thread-safe, not concurrent)
 DeviceState g_dev;
+// device buffers and graph of perm_batch (used under g_mu); never destroyed,
+// so that no HIP call runs during static destruction at process exit
+BatchJob &g_batch_job = *new BatchJob;
 
 perm_status ensure_device() {
     if (g_dev.ready) return PERM_OK;
@@ -261,13 +265,65 @@ perm_status perm_sparse_ex(const perm_csc *a, const perm_opts *opts, double *out
     return run_one(a, opts, out, st);
 }
 
-perm_status perm_batch(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out) {
+perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out,
+                          perm_batch_stats *st) {
+    auto t0 = std::chrono::steady_clock::now();
     if (count < 0 || (count > 0 && (!mats || !out))) return fail(PERM_EINVAL, "bad batch arguments");
+    const perm_opts o = defaults(opts);
+    if (o.batch_mode < 0 || o.batch_mode > 2) return fail(PERM_EINVAL, "batch_mode must be 0, 1 or 2");
+    BatchOptions bo;
+    bo.zero_skip = o.zero_skip;
+    bo.kappa_shift = o.batch_kappa_shift;
+    std::vector<PreparedMatrix> prep(count);
+    std::string err;
+    double steps = 0.0;
+    int singular = 0;
     for (int32_t i = 0; i < count; ++i) {
-        perm_status s = run_one(&mats[i], opts, &out[i], nullptr);
-        if (s != PERM_OK) return fail(s, "matrix " + std::to_string(i) + ": " + t_err);
+        perm_status s = prepare_batch_matrix(&mats[i], bo, &prep[i], &err);
+        if (s != PERM_OK) return fail(s, "matrix " + std::to_string(i) + ": " + err);
+        if (prep[i].singular)
+            ++singular;
+        else
+            steps += std::ldexp(1.0, prep[i].n - 1);
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> g(g_mu);
+    perm_status s = ensure_device();
+    if (s != PERM_OK) return s;
+    hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : g_dev.stream;
+    double kms = 0.0;
+    int launches = 0;
+    if (o.batch_mode == 2) {
+        for (int32_t i = 0; i < count; ++i) {
+            std::vector<const PreparedMatrix *> one{&prep[i]};
+            double k1 = 0.0;
+            s = g_batch_job.run(one, &out[i], stream, false, &k1, &err);
+            if (s != PERM_OK) return fail(s, err);
+            kms += k1;
+            launches += prep[i].singular ? 0 : 2;
+        }
+    } else {
+        std::vector<const PreparedMatrix *> all;
+        for (auto &pm : prep) all.push_back(&pm);
+        s = g_batch_job.run(all, out, stream, o.batch_mode == 0, &kms, &err);
+        if (s != PERM_OK) return fail(s, err);
+        launches = -1;
+    }
+    if (st) {
+        memset(st, 0, sizeof *st);
+        st->prep_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        st->kernel_ms = kms;
+        st->steps = steps;
+        st->count = count;
+        st->singular = singular;
+        st->launches = launches;
     }
     return PERM_OK;
+}
+
+perm_status perm_batch(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out) {
+    return perm_batch_ex(count, mats, opts, out, nullptr);
 }
 
 perm_status perm_plan(const perm_csc *a, const perm_opts *opts, int32_t *row_perm, int32_t *col_perm, double *tau,

@@ -46,9 +46,20 @@ class PermCsc(ctypes.Structure):
 class PermOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("chunk_log2", ctypes.c_int32), ("unroll_log2", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("vgpr_budget", ctypes.c_int32), ("force_k", ctypes.c_int32),
-                ("force_c", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("gr_ratio", ctypes.c_double),
+                ("force_c", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("zero_skip", ctypes.c_int32),
+                ("batch_mode", ctypes.c_int32), ("batch_kappa_shift", ctypes.c_int32),
+                ("gr_ratio", ctypes.c_double),
                 ("hip_stream", ctypes.c_void_p), ("block_partials", ctypes.POINTER(ctypes.c_double)),
                 ("block_partials_cap", ctypes.c_int64)]
+
+
+class PermBatchStats(ctypes.Structure):
+    _fields_ = [("wall_ms", ctypes.c_double), ("prep_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("steps", ctypes.c_double), ("count", ctypes.c_int32), ("singular", ctypes.c_int32),
+                ("launches", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
 
 
 class PermStats(ctypes.Structure):
@@ -75,6 +86,8 @@ _lib.perm_sparse_ex.restype = ctypes.c_int
 _lib.perm_sparse_ex.argtypes = [_P(PermCsc), _P(PermOpts), _P(ctypes.c_double), _P(PermStats)]
 _lib.perm_batch.restype = ctypes.c_int
 _lib.perm_batch.argtypes = [ctypes.c_int32, _P(PermCsc), _P(PermOpts), _P(ctypes.c_double)]
+_lib.perm_batch_ex.restype = ctypes.c_int
+_lib.perm_batch_ex.argtypes = [ctypes.c_int32, _P(PermCsc), _P(PermOpts), _P(ctypes.c_double), _P(PermBatchStats)]
 _lib.perm_plan.restype = ctypes.c_int
 _lib.perm_plan.argtypes = [_P(PermCsc), _P(PermOpts), _P(ctypes.c_int32), _P(ctypes.c_int32),
                            _P(ctypes.c_double), _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32),
@@ -93,7 +106,7 @@ _lib.perm_version.restype = ctypes.c_char_p
 _lib.perm_version.argtypes = []
 
 # every symbol include/perm.h declares
-EXPORTED = ["perm_sparse", "perm_sparse_ex", "perm_batch", "perm_plan", "perm_partition", "perm_codegen",
+EXPORTED = ["perm_sparse", "perm_sparse_ex", "perm_batch", "perm_batch_ex", "perm_plan", "perm_partition", "perm_codegen",
             "perm_compile_info", "perm_last_error", "perm_version"]
 
 
@@ -134,12 +147,16 @@ def _stream_handle(stream):
 
 
 def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, force_k=0, force_c=0,
-              max_levels=0, gr_ratio=0.0, stream=None):
+              max_levels=0, gr_ratio=0.0, stream=None, zero_skip="auto", batch_mode="graph",
+              batch_kappa_shift=0):
     o = PermOpts()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.chunk_log2, o.unroll_log2, o.block = chunk_log2, unroll_log2, block
     o.vgpr_budget, o.force_k, o.force_c, o.max_levels = vgpr_budget, force_k, force_c, max_levels
     o.gr_ratio = gr_ratio
+    o.zero_skip = {"auto": 0, True: 1, False: -1}[zero_skip]
+    o.batch_mode = {"graph": 0, "launches": 1, "sequential": 2}[batch_mode]
+    o.batch_kappa_shift = batch_kappa_shift
     o.hip_stream = _stream_handle(stream)
     return o
 
@@ -175,12 +192,19 @@ def perm_sparse_ex(ccs, block_partials=False, **opts):
 
 
 def perm_batch(mats, **opts):
+    return perm_batch_ex(mats, **opts)[0]
+
+
+def perm_batch_ex(mats, **opts):
+    """Returns (results array, batch stats dict)."""
     held = [_Csc(c) for c in mats]
     arr = (PermCsc * max(1, len(held)))(*[h.c for h in held])
     out = np.zeros(max(1, len(held)), np.float64)
     o = make_opts(**opts)
-    _check(_lib.perm_batch(len(held), arr, ctypes.byref(o), out.ctypes.data_as(_P(ctypes.c_double))))
-    return out[:len(held)]
+    st = PermBatchStats()
+    _check(_lib.perm_batch_ex(len(held), arr, ctypes.byref(o), out.ctypes.data_as(_P(ctypes.c_double)),
+                              ctypes.byref(st)))
+    return out[:len(held)], st.as_dict()
 
 
 def perm_plan(ccs, **opts):

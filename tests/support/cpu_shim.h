@@ -14,4 +14,6 @@ struct cpu_dim3 { unsigned x, y, z; };
 static cpu_dim3 threadIdx, blockIdx;
 static inline void __syncthreads() {}
 static inline double __shfl_xor(double v, int, int) { return v; }
+// one emulated lane is the whole "wave"
+static inline int __all(int p) { return p; }
 using std::fma;

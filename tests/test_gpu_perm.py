@@ -181,9 +181,10 @@ def test_n36_full_vs_oracle(P):
     rec = g[key]
     ccs = W.single_real(36, 0.30, 1)
     ref = rec["perm_ld_hi"] + rec["perm_ld_lo"]
-    got, st = P.perm_sparse_ex(ccs)
-    print("n36", got, ref, st["kernel_ms"])
-    assert abs(got - ref) <= _tol(36, ref, rec["abs_sum"])
+    for mode in ("auto", "pure", "hybrid"):
+        got, st = P.perm_sparse_ex(ccs, mode=mode)
+        print("n36", mode, got, ref, abs(got - ref) / abs(ref), st["kernel_ms"])
+        assert abs(got - ref) <= 1e-9 * abs(ref)
 
 
 def test_n40_full_exact(P):
@@ -192,6 +193,35 @@ def test_n40_full_exact(P):
     if key not in g:
         pytest.skip("stored n=40 oracle value not generated")
     ccs = W.single_01(40, 0.10, 1)
-    got, st = P.perm_sparse_ex(ccs)
-    print("n40", got, st["kernel_ms"], st["vgprs"], st["waves_per_simd"])
-    assert got == float(int(g[key]["perm_exact"]))
+    exact = int(g[key]["perm_exact"])
+    for mode, zs in (("auto", "auto"), ("auto", False), ("pure", "auto"), ("hybrid", "auto")):
+        got, st = P.perm_sparse_ex(ccs, mode=mode, zero_skip=zs)
+        print("n40", mode, zs, got, exact, st["kernel_ms"], st["vgprs"], st["waves_per_simd"])
+        # products of 40 half-integers can exceed 2^53, so single terms are
+        # rounded; the FP64 result must still round to the exact count
+        assert abs(got - exact) < 0.5 and round(got) == exact
+
+
+def test_zero_skip_is_exact(P, oracle_mod):
+    """Skipping chunks/blocks whose terms are exactly 0 leaves every result
+    unchanged (0/1 and integer matrices, several chunk and unroll sizes)."""
+    O = oracle_mod
+    for seed in range(4):
+        for n, p in ((18, 0.12), (22, 0.1), (26, 0.12)):
+            ccs = W.single_01(n, p, 100 * seed + n)
+            exact = float(O.perm_int(ccs))
+            for kappa, u in ((0, 0), (8, 3), (11, 6)):
+                on, st_on = P.perm_sparse_ex(ccs, zero_skip=True, chunk_log2=kappa, unroll_log2=u)
+                off, _ = P.perm_sparse_ex(ccs, zero_skip=False, chunk_log2=kappa, unroll_log2=u)
+                assert on == off == exact, (seed, n, kappa, u, on, off, exact)
+    # integer values other than 0/1, and a real matrix forced through the skipping code
+    A = np.where(np.random.default_rng(1).random((20, 20)) < 0.2, 2.0, 0.0) + np.eye(20) * 3.0
+    ccs = O.dense_to_ccs(A)
+    ref, abs_sum = O.perm_nw(ccs)
+    on, _ = P.perm_sparse_ex(ccs, zero_skip=True)
+    off, _ = P.perm_sparse_ex(ccs, zero_skip=False)
+    assert on == off and abs(on - ref) <= _tol(20, ref, abs_sum)
+    ccs = W.single_real(20, 0.3, 4)
+    ref, abs_sum = O.perm_nw(ccs)
+    on, _ = P.perm_sparse_ex(ccs, zero_skip=True)
+    assert abs(on - ref) <= _tol(20, ref, abs_sum)

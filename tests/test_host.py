@@ -233,11 +233,13 @@ def test_generated_code_on_cpu_matches_oracle(P, oracle_mod):
     cases = [(W.random_sparse(10, 0.3, 0, kind="real"), 3, 1), (W.random_sparse(13, 0.25, 1, kind="signed"), 5, 2),
              (W.single_01(16, 0.2, 2), 7, 3), (W.random_sparse(9, 0.5, 3, kind="real"), 8, 6),
              (W.random_sparse(5, 0.6, 4, kind="signed"), 1, 1)]
+    cases += [(W.single_01(18, 0.12, 5), 9, 3), (W.single_01(20, 0.1, 6), 12, 4)]
     for ccs, kappa, u in cases:
         ref, abs_sum = O.perm_nw(ccs)
         for mode in ("auto", "pure", "hybrid"):
-            got, info = _emulate(P, ccs, mode=mode, chunk_log2=kappa, unroll_log2=u)
-            assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12, (ccs[0], mode, kappa, u, got, ref)
+            for zs in (True, False):
+                got, info = _emulate(P, ccs, mode=mode, chunk_log2=kappa, unroll_log2=u, zero_skip=zs)
+                assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12, (ccs[0], mode, kappa, u, zs, got, ref)
 
 
 def test_generated_code_tiny_n_on_cpu(P, oracle_mod):
