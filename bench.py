@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -50,6 +52,109 @@ def cpu_baseline(ccs, seconds_target=15.0):
                       % (int(math.log2(steps)), n - 1, dt)}
 
 
+def batch_bench(seed=1, count=2000, reps=3):
+    """The batch workload (2000 matrices, n ~ U{16..30}, density ~ U[0.15, 0.40],
+    U(-1,1) values): one call of perm_batch (the whole batch as one graph of
+    launches, host preparation included) against one matrix per launch,
+    synchronised after each, with the same kernels."""
+    import paper_2501_15126_amd.perm as P
+    from paper_2501_15126_amd import workloads as W
+    mats = W.batch(seed, count)
+    P.perm_batch(mats)  # warm-up: device buffers, graph
+    best = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out, st = P.perm_batch_ex(mats)
+        dt = time.perf_counter() - t0
+        best = (dt, st, out) if best is None or dt < best[0] else best
+    t0 = time.perf_counter()
+    out_seq, st_seq = P.perm_batch_ex(mats, batch_mode="sequential")
+    dt_seq = time.perf_counter() - t0
+    dt, st, out = best
+    return {"workload": "%d sparse real matrices, n ~ U{16..30}, density ~ U[0.15,0.40], U(-1,1), seed %d"
+                        % (count, seed),
+            "permanents_per_s": count / dt, "wall_ms": dt * 1e3, "kernel_ms": st["kernel_ms"],
+            "prep_ms": st["prep_ms"], "gray_steps": st["steps"], "gray_steps_per_s": st["steps"] / dt,
+            "structurally_singular": st["singular"],
+            "sequential_permanents_per_s": count / dt_seq, "sequential_wall_ms": dt_seq * 1e3,
+            "speedup_vs_sequential": dt_seq / dt,
+            "bitwise_equal_to_sequential": bool(np.array_equal(out, out_seq))}
+
+
+def serving_bench(duration_s=20.0, rate_hz=200.0, seed=1, compare_fifo=True):
+    """Poisson arrivals at rate_hz of requests with n ~ U{12..36}, density ~
+    U[0.10,0.35], 70 % 0/1 else U(0,1).  Latency = time the result is seen by
+    the client minus the scheduled arrival time (queueing included)."""
+    import threading
+    import paper_2501_15126_amd.perm as P
+    from paper_2501_15126_amd import workloads as W
+    arrivals = W.serving_trace(seed, rate_hz, duration_s)
+    reqs = [W.serving_request(seed, i) for i in range(len(arrivals))]
+    steps = sum(2.0 ** (r[0] - 1) for r in reqs)
+
+    def run_server():
+        srv = P.Server()
+        srv.wait(srv.submit(reqs[0]))  # warm-up
+        tickets = [None] * len(reqs)
+        done = [None] * len(reqs)
+        t0 = time.perf_counter() + 0.05
+
+        def submitter():
+            for i, a in enumerate(arrivals):
+                d = t0 + a - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(reqs[i])
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        pending = set()
+        nxt = 0
+        while nxt < len(reqs) or pending:
+            while nxt < len(reqs) and tickets[nxt] is not None:
+                pending.add(nxt)
+                nxt += 1
+            now = time.perf_counter()
+            for i in list(pending):
+                if srv.poll(tickets[i]) is not None:
+                    done[i] = now
+                    pending.discard(i)
+            time.sleep(0.0002)
+        th.join()
+        st = srv.stats()
+        srv.close()
+        lat = np.array([done[i] - (t0 + arrivals[i]) for i in range(len(reqs))]) * 1e3
+        span = max(done) - t0
+        return lat, span, st
+
+    def run_fifo():
+        # the sequential baseline: one request at a time, in arrival order
+        t0 = time.perf_counter() + 0.05
+        done = []
+        for i, a in enumerate(arrivals):
+            d = t0 + a - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            P.perm_batch([reqs[i]], batch_mode="sequential")
+            done.append(time.perf_counter())
+        lat = np.array([done[i] - (t0 + arrivals[i]) for i in range(len(reqs))]) * 1e3
+        return lat, done[-1] - t0
+
+    lat, span, st = run_server()
+    out = {"workload": "Poisson %.0f req/s for %.0f s, n ~ U{12..36}, density ~ U[0.10,0.35], 70%% 0/1 else U(0,1), "
+                       "seed %d" % (rate_hz, duration_s, seed),
+           "requests": len(reqs), "offered_gray_steps_per_s": steps / duration_s,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+           "permanents_per_s": len(reqs) / span, "rounds": st["rounds"], "arena_peak_bytes": st["arena_peak"],
+           "server_busy_fraction": st["busy_ms"] / 1e3 / span}
+    if compare_fifo:
+        flat, fspan = run_fifo()
+        out["fifo_sequential"] = {"p50_ms": float(np.percentile(flat, 50)), "p99_ms": float(np.percentile(flat, 99)),
+                                  "permanents_per_s": len(reqs) / fspan}
+    return out
+
+
 def measured_traffic(src):
     """HBM bytes per dispatch of this exact generated kernel, from the committed
     rocprofv3 counter summary (None when the kernel source has changed)."""
@@ -76,6 +181,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--zero-skip", default="auto", choices=["auto", "on", "off"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch-workload measurement")
+    ap.add_argument("--serving-seconds", type=float, default=20.0,
+                    help="length of the Poisson serving run (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (torch), to scale HBM byte counters")
     args = ap.parse_args()
@@ -106,19 +214,24 @@ def main():
         v, st = P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=zs)
         first = st if first is None else first
     kernel_ms = []
+    evaluated = []
     values = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         v, st = P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=zs)  # synchronous: result on the host
         kernel_ms.append(st["kernel_ms"])
+        evaluated.append(st["evaluated_steps"])
         values.append(v)
     elapsed = time.perf_counter() - t0
     steps_per_perm = 2.0 ** (n - 1)
     value = steps_per_perm * args.steps / elapsed
     avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
-    flops = st["flops_per_step"] * steps_per_perm
+    # algorithmic work of one launch = the Gray steps whose product the kernel
+    # evaluated (all of them without zero-aware skipping) x FP64 flops per step
+    eval_steps = sum(evaluated) / len(evaluated)
+    flops = st["flops_per_step"] * eval_steps
     achieved_tflops = flops / avg_kernel_s / 1e12
-    ops_rate = st["ops_per_step"] * steps_per_perm / avg_kernel_s
+    ops_rate = st["ops_per_step"] * eval_steps / avg_kernel_s
     out = {
         "metric": METRIC,
         "value": value,
@@ -145,10 +258,16 @@ def main():
                    "scratch_bytes": st["scratch_bytes"], "waves_per_simd": st["waves_per_simd"],
                    "chunk_log2": st["chunk_log2"], "unroll_log2": st["unroll_log2"], "levels": st["levels"],
                    "k": st["k"], "c": st["c"], "nblocks": st["nblocks"], "reduce_ms": st["reduce_ms"],
-                   "host_ms": st["host_ms"], "compile_ms_cold": first["compile_ms"] if first else None},
+                   "host_ms": st["host_ms"], "compile_ms_cold": first["compile_ms"] if first else None,
+                   "evaluated_steps_per_launch": eval_steps,
+                   "skipped_fraction": 1.0 - eval_steps / steps_per_perm},
         "permanent": values[-1],
         "deterministic": all(x == values[0] for x in values),
     }
+    if not args.no_batch:
+        out["batch"] = batch_bench()
+    if args.serving_seconds > 0:
+        out["serving"] = serving_bench(args.serving_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ccs)
     print(json.dumps(out), flush=True)

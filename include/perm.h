@@ -117,6 +117,9 @@ typedef struct {
     double flops_per_step;  /* same, counting an FMA that replaces a multiply
                                and an add the method needs as 2 */
     double sum_hi, sum_lo;  /* the Gray-term sum before the final factor */
+    double evaluated_steps; /* lane-steps whose product the kernel evaluated, over
+                               all launched lanes (inactive padding lanes included);
+                               below steps when zero-aware skipping removed work */
     int64_t nblocks;        /* workgroups launched */
     int64_t nchunks;        /* lane chunks (2^(n-1-chunk_log2)) */
     int32_t n, nnz;         /* after dropping explicit zeros */
@@ -163,6 +166,46 @@ typedef struct {
 perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out,
                           perm_batch_stats *st);
 
+/* ---- Serving: submit / poll with continuous batching ------------------- */
+
+/* A server owns a scheduler thread, a device-memory arena of
+ * `device_mem_budget` bytes (0 = 1 GiB) and at most `max_inflight` requests
+ * that were submitted and not yet collected (0 = 4096).  Requests use the
+ * precompiled batch kernels (no per-request hipRTC) with opts' zero_skip and
+ * batch_kappa_shift.  Admission is in arrival order, as arena memory frees;
+ * every scheduling round gives each admitted request a share of the device
+ * work, so requests that arrive while others run overlap with them on the
+ * GPU.  A request's result is bitwise the same whether it runs alone or in
+ * any mix.  Returns NULL on error (perm_last_error). */
+typedef struct perm_server perm_server;
+perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget, int32_t max_inflight);
+
+/* Validates and copies the matrix, answers structurally singular ones at once
+ * (0), and queues the rest.  *ticket identifies the request.  PERM_EAGAIN when
+ * max_inflight requests are outstanding; PERM_ETOOBIG when the request alone
+ * needs more than the arena.  Thread-safe. */
+perm_status perm_submit(perm_server *s, const perm_csc *a, uint64_t *ticket);
+
+/* PERM_ENOTREADY while the request runs; PERM_OK with *out once it is done
+ * (the ticket is then released); PERM_EINVAL for an unknown ticket;
+ * PERM_EDEVICE if the device failed.  Non-blocking, thread-safe. */
+perm_status perm_poll(perm_server *s, uint64_t ticket, double *out);
+
+/* perm_poll that blocks until the request is done. */
+perm_status perm_wait(perm_server *s, uint64_t ticket, double *out);
+
+typedef struct {
+    uint64_t submitted, completed, rounds;
+    uint64_t pending, active;       /* queued (not admitted) / admitted, running */
+    uint64_t arena_bytes, arena_used, arena_peak;
+    double busy_ms;                 /* scheduler time spent in device rounds */
+} perm_server_stats;
+perm_status perm_server_get_stats(perm_server *s, perm_server_stats *st);
+
+/* Finishes all submitted work, stops the scheduler and frees the server.
+ * Results not collected are discarded. */
+void perm_server_destroy(perm_server *s);
+
 /* ---- Introspection of the host-side steps (used by tests) -------------- */
 
 /* The preprocessing decisions for a matrix without running it.
@@ -190,6 +233,15 @@ perm_status perm_codegen(const perm_csc *a, const perm_opts *opts, char *buf, si
  * needed) without launching it, and report the plan and the code object's
  * resources (vgprs, sgprs, scratch_bytes, lds_bytes, compile_ms) in *st. */
 perm_status perm_compile_info(const perm_csc *a, const perm_opts *opts, perm_stats *st);
+
+/* The data the precompiled batch kernels use for one matrix (introspection
+ * for tests): desc[0..5] = n, ng (4-row groups), chunk log2, zero-skip flag,
+ * highest group of the in-chunk columns, structurally singular flag;
+ * vals (cap doubles) = column groups [j][ng][4] for flipped columns j, then
+ * the 4*ng starting values of x; tops (cap ints) = highest group per flipped
+ * column.  *nvals / *ntops receive the needed sizes. */
+perm_status perm_batch_describe(const perm_csc *a, const perm_opts *opts, int32_t desc[6], double *vals,
+                                size_t vals_cap, size_t *nvals, int32_t *tops, size_t tops_cap, size_t *ntops);
 
 /* Description of the last error on the calling thread (never NULL; valid
  * until the next library call on that thread). */

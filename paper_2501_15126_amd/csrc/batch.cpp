@@ -130,7 +130,7 @@ BatchJob::~BatchJob() {
     if (d_items) (void)hipFree(d_items);
     if (d_vals) (void)hipFree(d_vals);
     if (d_tops) (void)hipFree(d_tops);
-    if (d_first) (void)hipFree(d_first);
+    if (d_fin) (void)hipFree(d_fin);
     if (d_partials) (void)hipFree(d_partials);
     if (d_out) (void)hipFree(d_out);
     if (h_stage) (void)hipHostFree(h_stage);
@@ -159,7 +159,7 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
     }
     std::vector<BatchMat> hm(nm);
     std::vector<BatchItem> hitems;
-    std::vector<int64_t> first(nm + 1, 0);
+    std::vector<FinishDesc> fin(nm);
     size_t nvals = 0, ntops = 0;
     for (int k = 0; k < nm; ++k) {
         const PreparedMatrix &pm = *mats[order[k]];
@@ -176,22 +176,24 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
         d.top_off = ntops;
         nvals += pm.vals.size();
         ntops += pm.tops.size();
-        first[k] = (int64_t)hitems.size();
-        for (uint64_t c = 0; c < pm.nchunks; c += 64) hitems.push_back(BatchItem{k, 0, c});
+        fin[k].part = hitems.size();
+        fin[k].n = pm.n;
+        fin[k].pad = 0;
+        for (uint64_t c = 0; c < pm.nchunks; c += 64) hitems.push_back(BatchItem{k, 0, c, (uint64_t)hitems.size()});
+        fin[k].count = hitems.size() - fin[k].part;
     }
-    first[nm] = (int64_t)hitems.size();
     const size_t nitems = hitems.size();
     perm_status s;
     if ((s = grow(&d_mats, &cap_mats, (size_t)nm, err)) != PERM_OK) return s;
     if ((s = grow(&d_items, &cap_items, nitems, err)) != PERM_OK) return s;
     if ((s = grow(&d_vals, &cap_vals, nvals, err)) != PERM_OK) return s;
     if ((s = grow(&d_tops, &cap_tops, ntops, err)) != PERM_OK) return s;
-    if ((s = grow(&d_first, &cap_first, (size_t)nm + 1, err)) != PERM_OK) return s;
+    if ((s = grow(&d_fin, &cap_fin, (size_t)nm, err)) != PERM_OK) return s;
     if ((s = grow(&d_partials, &cap_partials, 2 * nitems, err)) != PERM_OK) return s;
     if ((s = grow(&d_out, &cap_out, (size_t)nm, err)) != PERM_OK) return s;
     // one pinned staging buffer for all inputs
     const size_t bytes = nm * sizeof(BatchMat) + nitems * sizeof(BatchItem) + nvals * sizeof(double) +
-                         ntops * sizeof(int32_t) + (nm + 1) * sizeof(int64_t) + 64;
+                         ntops * sizeof(int32_t) + nm * sizeof(FinishDesc) + 64;
     if ((s = grow_host(&h_stage, &cap_stage, bytes, err)) != PERM_OK) return s;
     if ((s = grow_host(&h_out, &cap_hout, (size_t)nm, err)) != PERM_OK) return s;
     char *p = h_stage;
@@ -216,13 +218,13 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
         p += pm.tops.size() * sizeof(int32_t);
     }
     p = s_tops + (ntops * sizeof(int32_t) + 7) / 8 * 8;
-    char *s_first = stage(first.data(), (nm + 1) * sizeof(int64_t));
+    char *s_fin = stage(fin.data(), nm * sizeof(FinishDesc));
 
     HIP_OK(hipMemcpyAsync(d_mats, s_mats, nm * sizeof(BatchMat), hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemcpyAsync(d_items, s_items, nitems * sizeof(BatchItem), hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemcpyAsync(d_vals, s_vals, nvals * sizeof(double), hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemcpyAsync(d_tops, s_tops, ntops * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-    HIP_OK(hipMemcpyAsync(d_first, s_first, (nm + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipMemcpyAsync(d_fin, s_fin, nm * sizeof(FinishDesc), hipMemcpyHostToDevice, stream));
 
     if (!ev0) {
         HIP_OK(hipEventCreate(&ev0));
@@ -237,10 +239,10 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
             size_t i1 = i0;
             while (i1 < nitems && hm[hitems[i1].mat].ng == d0.ng) ++i1;
             HIP_OK(launch_batch_items(d0.ng, d_items + i0, (int64_t)(i1 - i0), d_mats, d_vals, d_tops,
-                                      d_partials + 2 * i0, stream));
+                                      d_partials, stream));
             i0 = i1;
         }
-        HIP_OK(launch_batch_finish(d_first, d_mats, nm, d_partials, d_out, stream));
+        HIP_OK(launch_batch_finish(d_fin, nm, d_partials, d_out, stream));
         return PERM_OK;
     };
     if (use_graph) {

@@ -18,14 +18,14 @@
 namespace permx {
 
 // Launches the batch kernel for items [0, nitems) whose matrices all have ng
-// groups.  Writes one double-double partial per item to partials[2*i], [2*i+1].
+// groups.  Item i writes its double-double partial to partials[2*items[i].out].
 hipError_t launch_batch_items(int ng, const BatchItem *items, int64_t nitems, const BatchMat *mats,
                               const double *vals, const int32_t *tops, double *partials, hipStream_t stream);
 
-// out[i] = factor(n_i) * (sum of partials of matrix i's items), items of
-// matrix i being [first[i], first[i+1]), summed in order in double-double.
-hipError_t launch_batch_finish(const int64_t *first, const BatchMat *mats, int nmats, const double *partials,
-                               double *out, hipStream_t stream);
+// out[i] = (4 (n mod 2) - 2) * (partials of d[i], added in order in
+// double-double), i = 0..count-1.
+hipError_t launch_batch_finish(const FinishDesc *d, int count, const double *partials, double *out,
+                               hipStream_t stream);
 
 // Resources of the compiled batch kernel for ng groups (VGPRs, scratch).
 int batch_kernel_attributes(int ng, int *vgprs, int *scratch);

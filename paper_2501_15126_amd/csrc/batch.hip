@@ -53,26 +53,26 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchItem *__restrict_
         cs = dd_add(cs, o);
     }
     if (lane == 0) {
-        partials[2 * item] = cs.h;
-        partials[2 * item + 1] = cs.l;
+        partials[2 * it.out] = cs.h;
+        partials[2 * it.out + 1] = cs.l;
     }
 }
 
-__global__ void __launch_bounds__(256) batch_finish(const int64_t *__restrict__ first,
-                                                    const BatchMat *__restrict__ mats, int nmats,
+__global__ void __launch_bounds__(256) batch_finish(const FinishDesc *__restrict__ d, int count,
                                                     const double *__restrict__ partials, double *__restrict__ out) {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= nmats) return;
+    if (i >= count) return;
     dd acc;
     acc.h = 0.0;
     acc.l = 0.0;
-    for (int64_t k = first[i]; k < first[i + 1]; ++k) {
+    const uint64_t p0 = d[i].part;
+    for (uint64_t k = 0; k < d[i].count; ++k) {
         dd v;
-        v.h = partials[2 * k];
-        v.l = partials[2 * k + 1];
+        v.h = partials[2 * (p0 + k)];
+        v.l = partials[2 * (p0 + k) + 1];
         acc = dd_add(acc, v);
     }
-    const double f = (mats[i].n % 2 == 1) ? 2.0 : -2.0;  // 4 (n mod 2) - 2
+    const double f = (d[i].n % 2 == 1) ? 2.0 : -2.0;  // 4 (n mod 2) - 2
     out[i] = (acc.h + acc.l) * f;
 }
 
@@ -112,11 +112,10 @@ hipError_t launch_batch_items(int ng, const BatchItem *items, int64_t nitems, co
 #undef PERM_CASE
 }
 
-hipError_t launch_batch_finish(const int64_t *first, const BatchMat *mats, int nmats, const double *partials,
-                               double *out, hipStream_t stream) {
-    if (nmats <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_finish, dim3((nmats + 255) / 256), dim3(256), 0, stream, first, mats, nmats, partials,
-                       out);
+hipError_t launch_batch_finish(const FinishDesc *d, int count, const double *partials, double *out,
+                               hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_finish, dim3((count + 255) / 256), dim3(256), 0, stream, d, count, partials, out);
     return hipGetLastError();
 }
 

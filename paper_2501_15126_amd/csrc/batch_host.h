@@ -39,10 +39,10 @@ struct BatchJob {
     BatchItem *d_items = nullptr;
     double *d_vals = nullptr;
     int32_t *d_tops = nullptr;
-    int64_t *d_first = nullptr;
+    FinishDesc *d_fin = nullptr;
     double *d_partials = nullptr;
     double *d_out = nullptr;
-    size_t cap_mats = 0, cap_items = 0, cap_vals = 0, cap_tops = 0, cap_first = 0, cap_partials = 0, cap_out = 0;
+    size_t cap_mats = 0, cap_items = 0, cap_vals = 0, cap_tops = 0, cap_fin = 0, cap_partials = 0, cap_out = 0;
     char *h_stage = nullptr;
     size_t cap_stage = 0;
     double *h_out = nullptr;

@@ -16,11 +16,22 @@ struct BatchMat {
     uint64_t top_off;               // int32: top group of each flipped column
 };
 
-// One wave of work: 64 consecutive chunks of one matrix.
+// One wave of work: 64 consecutive chunks of one matrix, whose double-double
+// partial goes to partials[2*out], [2*out+1].
 struct BatchItem {
     int32_t mat;
     int32_t pad;
     uint64_t chunk0;
+    uint64_t out;
+};
+
+// A matrix's final sum: partials part .. part+count-1 added in order, times
+// the final factor 4 (n mod 2) - 2.
+struct FinishDesc {
+    uint64_t part;
+    uint64_t count;
+    int32_t n;
+    int32_t pad;
 };
 
 constexpr int kBatchMaxNG = 16;  // n <= 64

@@ -200,8 +200,11 @@ struct Gen {
               "  dd r; r.h = s.h + e; r.l = e - (r.h - s.h); return r; }\n";
         // perm_lane: the Gray-term sum of chunk m (one lane's work); cold rows
         // of this lane live at xg[(r - k) * xs + lid].
+        // `ev` counts the terms whose product this lane actually evaluates
+        // (skipped ones excluded), for the device-work statistics.
         os << "__device__ __forceinline__ dd perm_lane(const u64 m, double* __restrict__ xg, const u64 xs,\n"
-              "                                        const u64 lid) {\n";
+              "                                        const u64 lid, u32 &ev) {\n";
+        os << "  ev = 1u;\n";
         os << "  const u64 g0 = m << "
            << kappa
            << ";\n"
@@ -268,6 +271,7 @@ struct Gen {
                 for (int l = block_top; l >= 1; --l) refresh_level(l, cur, "      ");
                 os << "    } else {\n";
             }
+            os << "    ev += " << (2 * U - 1) << "u;\n";
             static_block(false, "    ");
             if (u + 1 == kappa) {
                 step(u, Sign::Lane, term_u, 0, "    ");
@@ -323,6 +327,7 @@ struct Gen {
                 os << "    }\n";
             }
             os << "  }\n";
+            os << "  ev += " << (DELTA / (2 * U) - 1) << "u;  // the dynamic steps\n";
             if (skip_chunk) os << "  }\n";
         }
         os << "  return two_sum(acc0, acc1);\n}\n";
@@ -331,23 +336,28 @@ struct Gen {
         const int nw = p.block / 64;
         os << "extern \"C\" __global__ void __launch_bounds__(" << p.block << ") " << kGrayKernelName
            << "(const u64 chunk_begin, const u64 chunk_end, double* __restrict__ partials,\n"
-              "    double* __restrict__ xg, const u64 xs) {\n";
+              "    u64* __restrict__ counts, double* __restrict__ xg, const u64 xs) {\n";
         os << "  const u64 lid = (u64)blockIdx.x * " << p.block << "u + threadIdx.x;\n"
               "  const bool active = chunk_begin + lid < chunk_end;\n"
               "  // an inactive lane (past the last chunk) replays a valid chunk and contributes 0\n"
               "  const u64 m = active ? chunk_begin + lid : chunk_begin;\n"
-              "  dd cs = perm_lane(m, xg, xs, lid);\n"
+              "  u32 ev = 0u;\n"
+              "  dd cs = perm_lane(m, xg, xs, lid, ev);\n"
               "  if (!active) { cs.h = 0.0; cs.l = 0.0; }\n"
               "  for (int off = 32; off > 0; off >>= 1) {\n"
               "    dd o; o.h = __shfl_xor(cs.h, off, 64); o.l = __shfl_xor(cs.l, off, 64);\n"
               "    cs = dd_add(cs, o);\n"
               "  }\n";
         os << "  __shared__ double wsum[" << 2 * nw << "];\n"
-              "  if ((threadIdx.x & 63u) == 0) { wsum[2 * (threadIdx.x >> 6)] = cs.h; wsum[2 * (threadIdx.x >> 6) + 1] = cs.l; }\n"
+              "  __shared__ u32 wev[" << nw << "];\n"
+              "  if ((threadIdx.x & 63u) == 0) { wsum[2 * (threadIdx.x >> 6)] = cs.h; wsum[2 * (threadIdx.x >> 6) + 1] = cs.l;\n"
+              "                                 wev[threadIdx.x >> 6] = ev; }\n"
               "  __syncthreads();\n"
               "  if (threadIdx.x == 0) {\n"
               "    dd t; t.h = wsum[0]; t.l = wsum[1];\n";
         os << "    for (int w = 1; w < " << nw << "; ++w) { dd o; o.h = wsum[2 * w]; o.l = wsum[2 * w + 1]; t = dd_add(t, o); }\n";
+        os << "    u64 te = 0;\n    for (int w = 0; w < " << nw << "; ++w) te += 64ull * wev[w];  // lanes x terms\n";
+        os << "    counts[blockIdx.x] = te;\n";
         os << "    partials[2 * (u64)blockIdx.x] = t.h;\n"
               "    partials[2 * (u64)blockIdx.x + 1] = t.l;\n"
               "  }\n"

@@ -79,6 +79,10 @@ struct Plan {
 
 perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *err);
 
+// ---- runtime.cpp -----------------------------------------------------------
+// Sets the calling thread's perm_last_error() text.
+void set_last_error(const std::string &msg);
+
 // ---- codegen.cpp -----------------------------------------------------------
 std::string generate_source(const Plan &p);
 // Kernel entry point name inside every generated module.

@@ -6,7 +6,9 @@
 namespace permx {
 
 // out[0] + out[1] = double-double sum of partials[2b] + partials[2b+1],
-// b = 0..count-1, in an order fixed by b.  Asynchronous on `stream`.
-hipError_t launch_final_reduce(const double *partials, long long count, double *out, hipStream_t stream);
+// b = 0..count-1, in an order fixed by b; count_out[0] = sum of counts[b].
+// Asynchronous on `stream`.
+hipError_t launch_final_reduce(const double *partials, const unsigned long long *counts, long long count,
+                               double *out, unsigned long long *count_out, hipStream_t stream);
 
 }  // namespace permx

@@ -3,7 +3,8 @@
 // The paper adds per-thread partial permanents into a global variable
 // (Sec. II-A) in no stated order.  Here every workgroup of the Gray kernel
 // writes one double-double partial, and this single-workgroup kernel sums
-// them in an order fixed by the partial's index: thread t accumulates
+// them in an order fixed by the partial's index (and adds the workgroups'
+// evaluated-term counts): thread t accumulates
 // partials t, t + 1024, t + 2048, ... and the 1024 results are combined by a
 // fixed binary tree in LDS.  The result does not depend on scheduling.
 #include <hip/hip_runtime.h>
@@ -36,21 +37,27 @@ __device__ __forceinline__ dd dd_add(dd x, dd y) {
 
 constexpr int kThreads = 1024;
 
-__global__ void __launch_bounds__(kThreads) final_reduce(const double *__restrict__ partials, long long count,
-                                                          double *__restrict__ out) {
+__global__ void __launch_bounds__(kThreads) final_reduce(const double *__restrict__ partials,
+                                                          const unsigned long long *__restrict__ counts,
+                                                          long long count, double *__restrict__ out,
+                                                          unsigned long long *__restrict__ count_out) {
     __shared__ double sh[2 * kThreads];
+    __shared__ unsigned long long shc[kThreads];
     const int t = threadIdx.x;
     dd acc;
     acc.h = 0.0;
     acc.l = 0.0;
+    unsigned long long c = 0;
     for (long long b = t; b < count; b += kThreads) {
         dd v;
         v.h = partials[2 * b];
         v.l = partials[2 * b + 1];
         acc = dd_add(acc, v);
+        c += counts[b];
     }
     sh[2 * t] = acc.h;
     sh[2 * t + 1] = acc.l;
+    shc[t] = c;
     __syncthreads();
     for (int s = kThreads / 2; s > 0; s >>= 1) {
         if (t < s) {
@@ -62,12 +69,14 @@ __global__ void __launch_bounds__(kThreads) final_reduce(const double *__restric
             a = dd_add(a, b);
             sh[2 * t] = a.h;
             sh[2 * t + 1] = a.l;
+            shc[t] += shc[t + s];
         }
         __syncthreads();
     }
     if (t == 0) {
         out[0] = sh[0];
         out[1] = sh[1];
+        count_out[0] = shc[0];
     }
 }
 
@@ -75,8 +84,9 @@ __global__ void __launch_bounds__(kThreads) final_reduce(const double *__restric
 
 namespace permx {
 
-hipError_t launch_final_reduce(const double *partials, long long count, double *out, hipStream_t stream) {
-    hipLaunchKernelGGL(final_reduce, dim3(1), dim3(kThreads), 0, stream, partials, count, out);
+hipError_t launch_final_reduce(const double *partials, const unsigned long long *counts, long long count,
+                               double *out, unsigned long long *count_out, hipStream_t stream) {
+    hipLaunchKernelGGL(final_reduce, dim3(1), dim3(kThreads), 0, stream, partials, counts, count, out, count_out);
     return hipGetLastError();
 }
 

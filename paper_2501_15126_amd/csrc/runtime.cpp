@@ -56,7 +56,9 @@ struct DeviceState {
     size_t partials_cap = 0;  // doubles
     double *xg = nullptr;
     size_t xg_cap = 0;        // doubles
-    double *out = nullptr;    // 2 doubles
+    unsigned long long *counts = nullptr;  // evaluated terms per workgroup
+    size_t counts_cap = 0;
+    double *out = nullptr;    // 2 doubles, then the evaluated-term total (u64)
     std::unordered_map<std::string, LoadedKernel> kernels;  // source -> module
 };
 
@@ -79,7 +81,7 @@ perm_status ensure_device() {
         return fail(PERM_EDEVICE, "device " + g_dev.arch + " is not gfx950 (MI355X); kernels are built for gfx950 only");
     HIP_TRY(hipStreamCreateWithFlags(&g_dev.stream, hipStreamNonBlocking));
     for (auto &ev : g_dev.ev) HIP_TRY(hipEventCreate(&ev));
-    HIP_TRY(hipMalloc(&g_dev.out, 2 * sizeof(double)));
+    HIP_TRY(hipMalloc(&g_dev.out, 4 * sizeof(double)));
     g_dev.ready = true;
     return PERM_OK;
 }
@@ -207,6 +209,8 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
     const int64_t launch_blocks = std::min<int64_t>(nblocks, kMaxBlocksPerLaunch);
     s = ensure_buffer(&g_dev.partials, &g_dev.partials_cap, 2 * (size_t)nblocks);
     if (s != PERM_OK) return s;
+    s = ensure_buffer(reinterpret_cast<double **>(&g_dev.counts), &g_dev.counts_cap, (size_t)nblocks);
+    if (s != PERM_OK) return s;
     const uint64_t xs = (uint64_t)launch_blocks * pl.block;  // lanes of one launch
     if (pl.cold) {
         s = ensure_buffer(&g_dev.xg, &g_dev.xg_cap, (size_t)(pl.n - pl.k) * xs);
@@ -219,16 +223,18 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
         uint64_t chunk_begin = (uint64_t)b0 * pl.block;
         uint64_t chunk_end = std::min<uint64_t>((uint64_t)nchunks, chunk_begin + (uint64_t)nb * pl.block);
         double *part = g_dev.partials + 2 * b0;
+        unsigned long long *cnt = g_dev.counts + b0;
         double *xg = g_dev.xg;
         uint64_t xs_arg = xs;
-        void *args[] = {&chunk_begin, &chunk_end, &part, &xg, &xs_arg};
+        void *args[] = {&chunk_begin, &chunk_end, &part, &cnt, &xg, &xs_arg};
         HIP_TRY(hipModuleLaunchKernel(kern->fn, (unsigned)nb, 1, 1, (unsigned)pl.block, 1, 1, 0, stream, args,
                                       nullptr));
     }
     HIP_TRY(hipEventRecord(g_dev.ev[1], stream));
-    HIP_TRY(launch_final_reduce(g_dev.partials, (long long)nblocks, g_dev.out, stream));
+    unsigned long long *count_out = reinterpret_cast<unsigned long long *>(g_dev.out + 2);
+    HIP_TRY(launch_final_reduce(g_dev.partials, g_dev.counts, (long long)nblocks, g_dev.out, count_out, stream));
     HIP_TRY(hipEventRecord(g_dev.ev[2], stream));
-    double hl[2];
+    double hl[3];
     HIP_TRY(hipMemcpyAsync(hl, g_dev.out, sizeof hl, hipMemcpyDeviceToHost, stream));
     if (o.block_partials && o.block_partials_cap >= nblocks)
         HIP_TRY(hipMemcpyAsync(o.block_partials, g_dev.partials, 2 * sizeof(double) * (size_t)nblocks,
@@ -241,6 +247,11 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
     st.reduce_ms = ms;
     st.sum_hi = hl[0];
     st.sum_lo = hl[1];
+    {
+        unsigned long long ev = 0;
+        memcpy(&ev, &hl[2], sizeof ev);
+        st.evaluated_steps = (double)ev;
+    }
     // final factor of Alg. 1: 4 (n mod 2) - 2 = (-1)^(n-1) * 2 (exact scaling)
     const double f = (pl.n % 2 == 1) ? 2.0 : -2.0;
     *out = (hl[0] + hl[1]) * f;
@@ -250,6 +261,8 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
 }
 
 }  // namespace
+
+void permx::set_last_error(const std::string &msg) { t_err = msg; }
 
 extern "C" {
 
@@ -395,6 +408,30 @@ perm_status perm_compile_info(const perm_csc *a, const perm_opts *opts, perm_sta
     st->sgprs = co.sgprs;
     st->scratch_bytes = co.scratch_bytes;
     st->lds_bytes = co.lds_bytes;
+    return PERM_OK;
+}
+
+perm_status perm_batch_describe(const perm_csc *a, const perm_opts *opts, int32_t desc[6], double *vals,
+                                size_t vals_cap, size_t *nvals, int32_t *tops, size_t tops_cap, size_t *ntops) {
+    const perm_opts o = defaults(opts);
+    BatchOptions bo;
+    bo.zero_skip = o.zero_skip;
+    bo.kappa_shift = o.batch_kappa_shift;
+    PreparedMatrix pm;
+    std::string err;
+    perm_status s = prepare_batch_matrix(a, bo, &pm, &err);
+    if (s != PERM_OK) return fail(s, err);
+    if (!desc) return fail(PERM_EINVAL, "null desc");
+    desc[0] = pm.n;
+    desc[1] = pm.ng;
+    desc[2] = pm.kappa;
+    desc[3] = pm.zero_skip ? 1 : 0;
+    desc[4] = pm.chunk_top;
+    desc[5] = pm.singular ? 1 : 0;
+    if (nvals) *nvals = pm.vals.size();
+    if (ntops) *ntops = pm.tops.size();
+    if (vals && vals_cap >= pm.vals.size()) memcpy(vals, pm.vals.data(), pm.vals.size() * sizeof(double));
+    if (tops && tops_cap >= pm.tops.size()) memcpy(tops, pm.tops.data(), pm.tops.size() * sizeof(int32_t));
     return PERM_OK;
 }
 

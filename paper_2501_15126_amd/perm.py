@@ -66,7 +66,7 @@ class PermStats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double), ("compile_ms", ctypes.c_double),
                 ("host_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("steps", ctypes.c_double),
                 ("ops_per_step", ctypes.c_double), ("flops_per_step", ctypes.c_double),
-                ("sum_hi", ctypes.c_double), ("sum_lo", ctypes.c_double),
+                ("sum_hi", ctypes.c_double), ("sum_lo", ctypes.c_double), ("evaluated_steps", ctypes.c_double),
                 ("nblocks", ctypes.c_int64), ("nchunks", ctypes.c_int64),
                 ("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("k", ctypes.c_int32), ("c", ctypes.c_int32), ("levels", ctypes.c_int32),
@@ -100,13 +100,41 @@ _lib.perm_codegen.argtypes = [_P(PermCsc), _P(PermOpts), ctypes.c_char_p, ctypes
                               _P(ctypes.c_size_t)]
 _lib.perm_compile_info.restype = ctypes.c_int
 _lib.perm_compile_info.argtypes = [_P(PermCsc), _P(PermOpts), _P(PermStats)]
+_lib.perm_batch_describe.restype = ctypes.c_int
+_lib.perm_batch_describe.argtypes = [_P(PermCsc), _P(PermOpts), _P(ctypes.c_int32), _P(ctypes.c_double),
+                                     ctypes.c_size_t, _P(ctypes.c_size_t), _P(ctypes.c_int32), ctypes.c_size_t,
+                                     _P(ctypes.c_size_t)]
 _lib.perm_last_error.restype = ctypes.c_char_p
 _lib.perm_last_error.argtypes = []
 _lib.perm_version.restype = ctypes.c_char_p
 _lib.perm_version.argtypes = []
 
+class PermServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("pending", ctypes.c_uint64), ("active", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("arena_used", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64), ("busy_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib.perm_server_create.restype = ctypes.c_void_p
+_lib.perm_server_create.argtypes = [_P(PermOpts), ctypes.c_size_t, ctypes.c_int32]
+_lib.perm_submit.restype = ctypes.c_int
+_lib.perm_submit.argtypes = [ctypes.c_void_p, _P(PermCsc), _P(ctypes.c_uint64)]
+_lib.perm_poll.restype = ctypes.c_int
+_lib.perm_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, _P(ctypes.c_double)]
+_lib.perm_wait.restype = ctypes.c_int
+_lib.perm_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, _P(ctypes.c_double)]
+_lib.perm_server_get_stats.restype = ctypes.c_int
+_lib.perm_server_get_stats.argtypes = [ctypes.c_void_p, _P(PermServerStats)]
+_lib.perm_server_destroy.restype = None
+_lib.perm_server_destroy.argtypes = [ctypes.c_void_p]
+
 # every symbol include/perm.h declares
-EXPORTED = ["perm_sparse", "perm_sparse_ex", "perm_batch", "perm_batch_ex", "perm_plan", "perm_partition", "perm_codegen",
+EXPORTED = ["perm_sparse", "perm_sparse_ex", "perm_batch", "perm_batch_ex", "perm_server_create", "perm_submit",
+            "perm_poll", "perm_wait", "perm_server_get_stats", "perm_server_destroy", "perm_batch_describe",
+            "perm_plan", "perm_partition", "perm_codegen",
             "perm_compile_info", "perm_last_error", "perm_version"]
 
 
@@ -250,5 +278,79 @@ def compile_info(ccs, **opts):
     return st.as_dict()
 
 
+def batch_describe(ccs, **opts):
+    """The batch kernels' data for one matrix (see perm_batch_describe)."""
+    m = _Csc(ccs)
+    o = make_opts(**opts)
+    desc = (ctypes.c_int32 * 6)()
+    nv, nt = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.perm_batch_describe(ctypes.byref(m.c), ctypes.byref(o), desc, None, 0, ctypes.byref(nv), None, 0,
+                                    ctypes.byref(nt)))
+    vals = np.zeros(max(1, nv.value), np.float64)
+    tops = np.zeros(max(1, nt.value), np.int32)
+    _check(_lib.perm_batch_describe(ctypes.byref(m.c), ctypes.byref(o), desc,
+                                    vals.ctypes.data_as(_P(ctypes.c_double)), vals.size, ctypes.byref(nv),
+                                    tops.ctypes.data_as(_P(ctypes.c_int32)), tops.size, ctypes.byref(nt)))
+    keys = ["n", "ng", "kappa", "zero_skip", "chunk_top", "singular"]
+    return dict(zip(keys, list(desc))), vals[:nv.value], tops[:nt.value]
+
+
 def compile_plan_stats(ccs, **opts):
     return compile_info(ccs, **opts)
+
+
+class Server:
+    """Submit/poll permanent server (perm_server_*)."""
+
+    def __init__(self, device_mem_budget=0, max_inflight=0, **opts):
+        self._opts = make_opts(**opts)
+        h = _lib.perm_server_create(ctypes.byref(self._opts), device_mem_budget, max_inflight)
+        if not h:
+            raise PermError(PERM_EDEVICE, last_error())
+        self._h = ctypes.c_void_p(h)
+
+    def submit(self, ccs) -> int:
+        m = _Csc(ccs)
+        t = ctypes.c_uint64()
+        _check(_lib.perm_submit(self._h, ctypes.byref(m.c), ctypes.byref(t)))
+        return t.value
+
+    def try_submit(self, ccs):
+        """Ticket, or None when the server is full (PERM_EAGAIN)."""
+        m = _Csc(ccs)
+        t = ctypes.c_uint64()
+        st = _lib.perm_submit(self._h, ctypes.byref(m.c), ctypes.byref(t))
+        if st == PERM_EAGAIN:
+            return None
+        _check(st)
+        return t.value
+
+    def poll(self, ticket):
+        """The result, or None while the request is not done."""
+        out = ctypes.c_double()
+        st = _lib.perm_poll(self._h, ticket, ctypes.byref(out))
+        if st == PERM_ENOTREADY:
+            return None
+        _check(st)
+        return out.value
+
+    def wait(self, ticket) -> float:
+        out = ctypes.c_double()
+        _check(_lib.perm_wait(self._h, ticket, ctypes.byref(out)))
+        return out.value
+
+    def stats(self):
+        st = PermServerStats()
+        _check(_lib.perm_server_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            _lib.perm_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,122 @@
+"""GPU tests of the submit/poll server: results against the oracle, the same
+result alone and in a mix (bitwise), memory-based admission, back-pressure,
+and continuous batching (a small request that arrives with a large one
+finishes first)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2501_15126_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2501_15126_amd.perm as P
+    return P
+
+
+def _tol(n, ref, abs_sum):
+    return max(1e-9 * abs(ref), (2 * n + 2) * 2.0 ** -53 * abs_sum)
+
+
+def test_server_results_vs_oracle(P, oracle_mod):
+    O = oracle_mod
+    reqs = [W.serving_request(3, i) for i in range(40)]
+    reqs = [r for r in reqs if r[0] <= 22]
+    with P.Server() as srv:
+        tickets = [srv.submit(r) for r in reqs]
+        got = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert st["completed"] == len(reqs)
+    for ccs, g in zip(reqs, got):
+        n = ccs[0]
+        if O.structural_rank(ccs) < n:
+            assert g == 0.0
+        elif (ccs[3] == 1.0).all():
+            e = O.perm_int(ccs)
+            _, abs_sum = O.perm_nw(ccs)
+            assert abs(g - e) <= max(0.49, _tol(n, e, abs_sum))
+        else:
+            ref, abs_sum = O.perm_nw(ccs)
+            assert abs(g - ref) <= _tol(n, ref, abs_sum)
+
+
+def test_server_alone_equals_in_mix(P):
+    probe = [W.single_real(24, 0.3, 11), W.single_01(26, 0.15, 12), W.random_sparse(20, 0.3, 13, kind="signed")]
+    others = [W.serving_request(5, i) for i in range(30)]
+    alone = []
+    with P.Server() as srv:
+        for q in probe:
+            alone.append(srv.wait(srv.submit(q)))
+    with P.Server() as srv:
+        tickets = []
+        for i, o in enumerate(others):
+            tickets.append(srv.submit(o))
+            if i in (3, 11, 20):
+                tickets.append(("probe", srv.submit(probe[(3, 11, 20).index(i)])))
+            if i % 7 == 0:
+                time.sleep(0.002)
+        mixed = [srv.wait(t[1]) for t in tickets if isinstance(t, tuple)]
+        for t in tickets:
+            if not isinstance(t, tuple):
+                srv.wait(t)
+    assert mixed == alone
+    assert list(P.perm_batch(probe)) == alone
+
+
+def test_server_memory_admission_and_backpressure(P):
+    reqs = [W.single_01(22, 0.2, 30 + i) for i in range(12)]
+    with P.Server(device_mem_budget=64 * 1024, max_inflight=64) as srv:
+        tickets = [srv.submit(r) for r in reqs]
+        res = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+        assert st["arena_peak"] <= 64 * 1024
+        assert st["completed"] == 12
+        big = W.single_real(40, 0.3, 1)
+        with pytest.raises(P.PermError) as e:
+            srv.submit(big)
+        assert e.value.status == P.PERM_ETOOBIG
+    assert list(P.perm_batch(reqs)) == res
+    with P.Server(max_inflight=3) as srv:
+        t = [srv.submit(reqs[i]) for i in range(3)]
+        assert srv.try_submit(reqs[3]) is None  # three outstanding tickets
+        srv.wait(t[0])
+        t4 = srv.try_submit(reqs[3])
+        assert t4 is not None
+        for x in t[1:] + [t4]:
+            srv.wait(x)
+
+
+def test_server_continuous_batching(P):
+    """A small request submitted right after a large one is admitted with it,
+    shares the rounds, and completes while the large one is still running."""
+    large = W.single_real(34, 0.3, 2)
+    small = W.single_real(14, 0.3, 3)
+    with P.Server() as srv:
+        tl = srv.submit(large)
+        ts = srv.submit(small)
+        vs = srv.wait(ts)
+        assert srv.poll(tl) is None, "the large request should still be running"
+        vl = srv.wait(tl)
+        st = srv.stats()
+    assert st["rounds"] >= 2
+    assert vs == P.perm_batch([small])[0]
+    assert vl == P.perm_batch([large])[0]
+
+
+def test_server_errors(P):
+    with P.Server() as srv:
+        with pytest.raises(P.PermError) as e:
+            srv.submit((3, np.array([0, 1, 2, 3]), np.array([0, 3, 1]), np.ones(3)))
+        assert e.value.status == P.PERM_EINVAL
+        with pytest.raises(P.PermError) as e:
+            srv.poll(123456)
+        assert e.value.status == P.PERM_EINVAL
+        singular = np.ones((4, 4))
+        singular[:, 0] = 0
+        from oracle import oracle as O
+        t = srv.submit(O.dense_to_ccs(singular))
+        assert srv.poll(t) == 0.0

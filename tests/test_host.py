@@ -210,7 +210,7 @@ def _emulate(P, ccs, **opts):
     f = os.path.join(d, "g.cpp")
     with open(f, "w") as fh:
         fh.write(src + '\nextern "C" void cpu_lane(u64 m, double* xg, u64 xs, u64 lid, double* o)'
-                 ' { dd r = perm_lane(m, xg, xs, lid); o[0] = r.h; o[1] = r.l; }\n')
+                 ' { u32 ev = 0; dd r = perm_lane(m, xg, xs, lid, ev); o[0] = r.h; o[1] = r.l; }\n')
     so = os.path.join(d, "g.so")
     subprocess.run(["g++", "-O1", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-include", SHIM,
                     "-o", so, f], check=True)
@@ -254,3 +254,53 @@ def test_generated_code_tiny_n_on_cpu(P, oracle_mod):
                 kappa = 0
             got, _ = _emulate(P, O.dense_to_ccs(A), chunk_log2=kappa)
             assert got == pytest.approx(ref, rel=1e-12, abs=1e-14)
+
+
+def _batch_lane_lib():
+    d = tempfile.mkdtemp(prefix="permbatch")
+    so = os.path.join(d, "bl.so")
+    csrc = os.path.join(ROOT, "paper_2501_15126_amd", "csrc")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-include", SHIM,
+                    "-I", csrc, "-o", so, os.path.join(os.path.dirname(SHIM), "batch_lane_cpu.cpp")], check=True)
+    lib = ctypes.CDLL(so)
+    lib.cpu_batch_lane.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                   ctypes.c_uint64, ctypes.c_void_p]
+    return lib
+
+
+def _batch_emulate(P, lib, ccs, **opts):
+    info, vals, tops = P.batch_describe(ccs, **opts)
+    if info["singular"]:
+        return 0.0
+    desc = np.array([info[k] for k in ("n", "ng", "kappa", "zero_skip", "chunk_top", "singular")], np.int32)
+    o = np.zeros(2)
+    tot = 0.0
+    for m in range(1 << (info["n"] - 1 - info["kappa"])):
+        assert lib.cpu_batch_lane(desc.ctypes.data, vals.ctypes.data, vals.size, tops.ctypes.data, m,
+                                  o.ctypes.data) == 0
+        tot += o[0] + o[1]
+    return tot * (2.0 if info["n"] % 2 else -2.0)
+
+
+def test_batch_lane_code_on_cpu_matches_oracle(P, oracle_mod):
+    """The batch kernels' per-lane code (compiled for the host) summed over all
+    chunks, for many sizes, groups, chunk sizes and zero-skip settings."""
+    O = oracle_mod
+    lib = _batch_lane_lib()
+    rng = np.random.default_rng(21)
+    for t in range(40):
+        n = int(rng.integers(1, 19))
+        kind = ("real", "signed", "01")[t % 3]
+        ccs = W.random_sparse(n, float(rng.uniform(0.15, 0.6)), seed=500 + t, kind=kind)
+        for shift in (0, -3):
+            got = _batch_emulate(P, lib, ccs, batch_kappa_shift=shift)
+            if O.structural_rank(ccs) < n:
+                assert got == 0.0
+                continue
+            ref, abs_sum = O.perm_nw(ccs)
+            assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12, (t, n, kind, shift, got, ref)
+    for seed in range(3):
+        ccs = W.single_01(20, 0.12, 900 + seed)
+        exact = O.perm_int(ccs)
+        for zs in (True, False):
+            assert _batch_emulate(P, lib, ccs, zero_skip=zs) == exact
