@@ -54,9 +54,9 @@ def cpu_baseline(ccs, seconds_target=15.0):
 
 def batch_bench(seed=1, count=2000, reps=3):
     """The batch workload (2000 matrices, n ~ U{16..30}, density ~ U[0.15, 0.40],
-    U(-1,1) values): one call of perm_batch (the whole batch as one graph of
-    launches, host preparation included) against one matrix per launch,
-    synchronised after each, with the same kernels."""
+    U(-1,1) values): one call of perm_batch (one launch per kernel instance on
+    its class stream, host preparation included) against one matrix per
+    launch, synchronised after each, with the same kernels."""
     import paper_2501_15126_amd.perm as P
     from paper_2501_15126_amd import workloads as W
     mats = W.batch(seed, count)
@@ -81,7 +81,7 @@ def batch_bench(seed=1, count=2000, reps=3):
             "bitwise_equal_to_sequential": bool(np.array_equal(out, out_seq))}
 
 
-def serving_bench(duration_s=20.0, rate_hz=200.0, seed=1, compare_fifo=True):
+def serving_bench(duration_s=20.0, rate_hz=200.0, seed=1, compare_fifo=True, round_steps=0.0):
     """Poisson arrivals at rate_hz of requests with n ~ U{12..36}, density ~
     U[0.10,0.35], 70 % 0/1 else U(0,1).  Latency = time the result is seen by
     the client minus the scheduled arrival time (queueing included)."""
@@ -93,7 +93,7 @@ def serving_bench(duration_s=20.0, rate_hz=200.0, seed=1, compare_fifo=True):
     steps = sum(2.0 ** (r[0] - 1) for r in reqs)
 
     def run_server():
-        srv = P.Server()
+        srv = P.Server(round_steps=round_steps)
         srv.wait(srv.submit(reqs[0]))  # warm-up
         tickets = [None] * len(reqs)
         done = [None] * len(reqs)

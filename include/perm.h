@@ -88,10 +88,12 @@ typedef struct {
                               factor that is exactly 0 in every lane.  0 = auto (on
                               when every value is an integer, where such zeros are
                               common), 1 = on, -1 = off */
-    int32_t batch_mode;    /* perm_batch: 0 = the whole batch as one captured graph of
-                              launches (default); 1 = the same launches without a
-                              graph; 2 = one matrix per launch, synchronised after
-                              each (the sequential baseline) */
+    int32_t batch_mode;    /* perm_batch: 0 = one launch per kernel instance, each on
+                              its own class stream so instances overlap (default);
+                              1 = the same launches on one stream, captured as a graph
+                              and launched; 2 = one matrix per launch, synchronised
+                              after each (the sequential baseline); 3 = the launches of
+                              0 on one stream */
     int32_t batch_kappa_shift; /* perm_batch: added to the default chunk log2 */
     double gr_ratio;       /* Alg. 5 global/register update cost ratio; 0 = 16 */
     void *hip_stream;      /* hipStream_t to launch on; NULL = the library's stream */
@@ -172,13 +174,18 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
  * `device_mem_budget` bytes (0 = 1 GiB) and at most `max_inflight` requests
  * that were submitted and not yet collected (0 = 4096).  Requests use the
  * precompiled batch kernels (no per-request hipRTC) with opts' zero_skip and
- * batch_kappa_shift.  Admission is in arrival order, as arena memory frees;
- * every scheduling round gives each admitted request a share of the device
- * work, so requests that arrive while others run overlap with them on the
- * GPU.  A request's result is bitwise the same whether it runs alone or in
- * any mix.  Returns NULL on error (perm_last_error). */
+ * batch_kappa_shift.  Admission is in arrival order, as arena memory frees.
+ * Every scheduling round shares `round_steps` Gray steps (0 = 8e9, about
+ * 10 ms of device work) among the admitted requests by water-filling (a
+ * request that needs less than an equal share leaves the rest to the
+ * others); two rounds are in flight, so requests that arrive while others
+ * run overlap with them on the GPU.  Each kernel instance (ng) has its own
+ * stream.  A request's result is bitwise the same whether it runs alone or
+ * in any mix, and equals perm_batch's with the same options.  Returns NULL on
+ * error (perm_last_error).  The server uses the device current at creation. */
 typedef struct perm_server perm_server;
-perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget, int32_t max_inflight);
+perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget, int32_t max_inflight,
+                                double round_steps);
 
 /* Validates and copies the matrix, answers structurally singular ones at once
  * (0), and queues the rest.  *ticket identifies the request.  PERM_EAGAIN when
@@ -198,7 +205,7 @@ typedef struct {
     uint64_t submitted, completed, rounds;
     uint64_t pending, active;       /* queued (not admitted) / admitted, running */
     uint64_t arena_bytes, arena_used, arena_peak;
-    double busy_ms;                 /* scheduler time spent in device rounds */
+    double busy_ms;                 /* wall time with at least one round in flight */
 } perm_server_stats;
 perm_status perm_server_get_stats(perm_server *s, perm_server_stats *st);
 

@@ -1,7 +1,8 @@
 // batch.cpp -- host side of the precompiled batch kernels: per-matrix
 // preparation (validation, structural check, Alg. 4 ordering, pre-signed
 // 4-row column groups, chunk plan) and the device job that runs a whole
-// batch as one captured graph of launches.
+// batch: one launch per kernel instance, each on its class stream (or all on
+// one stream, optionally captured as a graph), then one finish launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,9 +21,11 @@ namespace permx {
 int batch_kappa(int n, int shift) {
     const int total = n - 1;
     if (total <= 0) return 0;
-    // about 2^7 chunks (two waves) per matrix at n <= 24, chunks of 2^16
-    // steps above; at least 2^5 steps per chunk when n allows it
-    int kappa = std::min(std::max(total - 7 + shift, std::min(total, 5)), 16 + shift);
+    // about 2^9 chunks (eight waves) per matrix up to n = 23, chunks of 2^13
+    // steps above (a wave then runs well under a millisecond, the grain at
+    // which the server interleaves requests); at least 2^5 steps per chunk
+    // when n allows it
+    int kappa = std::min(std::max(total - 9 + shift, std::min(total, 5)), 13 + shift);
     return std::max(0, std::min(kappa, total));
 }
 
@@ -125,9 +128,33 @@ perm_status grow_host(T **p, size_t *cap, size_t need, std::string *err) {
 
 }  // namespace
 
+void WavePlan::add(int32_t mat, uint64_t item0, uint64_t count, uint64_t out0) {
+    const int32_t r = (int32_t)ranges.size();
+    ranges.push_back(BatchRange{mat, 0, nwaves, item0, out0});
+    // workgroups whose first wave (4b) lies in [nwaves, nwaves + count)
+    const uint64_t b1 = (nwaves + count + 3) / 4;
+    while (blk_first.size() < b1) blk_first.push_back(r);
+    nwaves += count;
+}
+
+hipError_t batch_class_streams(hipStream_t out[kBatchStreams]) {
+    static hipStream_t streams[kBatchStreams] = {};
+    static bool made = false;
+    if (!made) {
+        for (int i = 0; i < kBatchStreams; ++i) {
+            const hipError_t e = hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+        }
+        made = true;
+    }
+    for (int i = 0; i < kBatchStreams; ++i) out[i] = streams[i];
+    return hipSuccess;
+}
+
 BatchJob::~BatchJob() {
     if (d_mats) (void)hipFree(d_mats);
-    if (d_items) (void)hipFree(d_items);
+    if (d_ranges) (void)hipFree(d_ranges);
+    if (d_blk) (void)hipFree(d_blk);
     if (d_vals) (void)hipFree(d_vals);
     if (d_tops) (void)hipFree(d_tops);
     if (d_fin) (void)hipFree(d_fin);
@@ -140,15 +167,16 @@ BatchJob::~BatchJob() {
 }
 
 perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, double *out, hipStream_t stream,
-                          bool use_graph, double *kernel_ms, std::string *err) {
+                          BatchLaunch how, double *kernel_ms, std::string *err) {
     const int count = (int)mats.size();
-    // order the matrices by kernel instance (ng) so that each instance's
-    // items are contiguous; results go back to the caller's order
+    // order the matrices by kernel instance (ng), largest work first within
+    // an instance; results go back to the caller's order
     std::vector<int> order;
     for (int i = 0; i < count; ++i)
         if (!mats[i]->singular) order.push_back(i);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return mats[x]->ng < mats[y]->ng;
+        if (mats[x]->ng != mats[y]->ng) return mats[x]->ng < mats[y]->ng;
+        return mats[x]->n > mats[y]->n;
     });
     for (int i = 0; i < count; ++i)
         if (mats[i]->singular) out[i] = 0.0;
@@ -158,9 +186,10 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
         return PERM_OK;
     }
     std::vector<BatchMat> hm(nm);
-    std::vector<BatchItem> hitems;
     std::vector<FinishDesc> fin(nm);
+    std::vector<WavePlan> plans;
     size_t nvals = 0, ntops = 0;
+    uint64_t nparts = 0;
     for (int k = 0; k < nm; ++k) {
         const PreparedMatrix &pm = *mats[order[k]];
         BatchMat &d = hm[k];
@@ -176,35 +205,51 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
         d.top_off = ntops;
         nvals += pm.vals.size();
         ntops += pm.tops.size();
-        fin[k].part = hitems.size();
-        fin[k].n = pm.n;
-        fin[k].pad = 0;
-        for (uint64_t c = 0; c < pm.nchunks; c += 64) hitems.push_back(BatchItem{k, 0, c, (uint64_t)hitems.size()});
-        fin[k].count = hitems.size() - fin[k].part;
+        const uint64_t items = (pm.nchunks + 63) / 64;
+        if (plans.empty() || plans.back().ng != pm.ng) {
+            plans.emplace_back();
+            plans.back().ng = pm.ng;
+        }
+        plans.back().add(k, 0, items, nparts);
+        fin[k] = FinishDesc{nparts, items, pm.n, 0};
+        nparts += items;
     }
-    const size_t nitems = hitems.size();
+    size_t nranges = 0, nblk = 0;
+    for (const WavePlan &w : plans) {
+        nranges += w.ranges.size();
+        nblk += w.blk_first.size();
+    }
     perm_status s;
     if ((s = grow(&d_mats, &cap_mats, (size_t)nm, err)) != PERM_OK) return s;
-    if ((s = grow(&d_items, &cap_items, nitems, err)) != PERM_OK) return s;
+    if ((s = grow(&d_ranges, &cap_ranges, nranges, err)) != PERM_OK) return s;
+    if ((s = grow(&d_blk, &cap_blk, nblk, err)) != PERM_OK) return s;
     if ((s = grow(&d_vals, &cap_vals, nvals, err)) != PERM_OK) return s;
     if ((s = grow(&d_tops, &cap_tops, ntops, err)) != PERM_OK) return s;
     if ((s = grow(&d_fin, &cap_fin, (size_t)nm, err)) != PERM_OK) return s;
-    if ((s = grow(&d_partials, &cap_partials, 2 * nitems, err)) != PERM_OK) return s;
+    if ((s = grow(&d_partials, &cap_partials, 2 * nparts, err)) != PERM_OK) return s;
     if ((s = grow(&d_out, &cap_out, (size_t)nm, err)) != PERM_OK) return s;
     // one pinned staging buffer for all inputs
-    const size_t bytes = nm * sizeof(BatchMat) + nitems * sizeof(BatchItem) + nvals * sizeof(double) +
-                         ntops * sizeof(int32_t) + nm * sizeof(FinishDesc) + 64;
+    const size_t bytes = nm * sizeof(BatchMat) + nranges * sizeof(BatchRange) + nblk * sizeof(int32_t) +
+                         nvals * sizeof(double) + ntops * sizeof(int32_t) + nm * sizeof(FinishDesc) + 64;
     if ((s = grow_host(&h_stage, &cap_stage, bytes, err)) != PERM_OK) return s;
     if ((s = grow_host(&h_out, &cap_hout, (size_t)nm, err)) != PERM_OK) return s;
     char *p = h_stage;
-    auto stage = [&](const void *src, size_t n) {
-        char *at = p;
-        memcpy(p, src, n);
-        p += (n + 7) / 8 * 8;
-        return at;
-    };
-    char *s_mats = stage(hm.data(), nm * sizeof(BatchMat));
-    char *s_items = stage(hitems.data(), nitems * sizeof(BatchItem));
+    auto align8 = [&]() { p = h_stage + ((size_t)(p - h_stage) + 7) / 8 * 8; };
+    char *s_mats = p;
+    memcpy(p, hm.data(), nm * sizeof(BatchMat));
+    p += nm * sizeof(BatchMat);
+    align8();
+    char *s_ranges = p;
+    for (const WavePlan &w : plans) {
+        memcpy(p, w.ranges.data(), w.ranges.size() * sizeof(BatchRange));
+        p += w.ranges.size() * sizeof(BatchRange);
+    }
+    char *s_blk = p;
+    for (const WavePlan &w : plans) {
+        memcpy(p, w.blk_first.data(), w.blk_first.size() * sizeof(int32_t));
+        p += w.blk_first.size() * sizeof(int32_t);
+    }
+    align8();
     char *s_vals = p;
     for (int k = 0; k < nm; ++k) {
         const PreparedMatrix &pm = *mats[order[k]];
@@ -217,11 +262,13 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
         memcpy(p, pm.tops.data(), pm.tops.size() * sizeof(int32_t));
         p += pm.tops.size() * sizeof(int32_t);
     }
-    p = s_tops + (ntops * sizeof(int32_t) + 7) / 8 * 8;
-    char *s_fin = stage(fin.data(), nm * sizeof(FinishDesc));
+    align8();
+    char *s_fin = p;
+    memcpy(p, fin.data(), nm * sizeof(FinishDesc));
 
     HIP_OK(hipMemcpyAsync(d_mats, s_mats, nm * sizeof(BatchMat), hipMemcpyHostToDevice, stream));
-    HIP_OK(hipMemcpyAsync(d_items, s_items, nitems * sizeof(BatchItem), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipMemcpyAsync(d_ranges, s_ranges, nranges * sizeof(BatchRange), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipMemcpyAsync(d_blk, s_blk, nblk * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemcpyAsync(d_vals, s_vals, nvals * sizeof(double), hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemcpyAsync(d_tops, s_tops, ntops * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemcpyAsync(d_fin, s_fin, nm * sizeof(FinishDesc), hipMemcpyHostToDevice, stream));
@@ -229,23 +276,37 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
     if (!ev0) {
         HIP_OK(hipEventCreate(&ev0));
         HIP_OK(hipEventCreate(&ev1));
+        for (int i = 0; i < kBatchStreams; ++i) HIP_OK(hipEventCreateWithFlags(&ev_join[i], hipEventDisableTiming));
     }
     HIP_OK(hipEventRecord(ev0, stream));
+    hipStream_t cls[kBatchStreams];
+    if (how == BatchLaunch::Streams) HIP_OK(batch_class_streams(cls));
     // the launches: one per kernel instance, then the per-matrix finish
     auto enqueue = [&]() -> perm_status {
-        size_t i0 = 0;
-        while (i0 < nitems) {
-            const BatchMat &d0 = hm[hitems[i0].mat];
-            size_t i1 = i0;
-            while (i1 < nitems && hm[hitems[i1].mat].ng == d0.ng) ++i1;
-            HIP_OK(launch_batch_items(d0.ng, d_items + i0, (int64_t)(i1 - i0), d_mats, d_vals, d_tops,
-                                      d_partials, stream));
-            i0 = i1;
+        bool used[kBatchStreams] = {};
+        size_t r0 = 0, b0 = 0;
+        for (const WavePlan &w : plans) {
+            hipStream_t st = stream;
+            if (how == BatchLaunch::Streams) {
+                const int c = w.ng % kBatchStreams;
+                st = cls[c];
+                if (!used[c]) HIP_OK(hipStreamWaitEvent(st, ev0, 0));
+                used[c] = true;
+            }
+            HIP_OK(launch_batch_ranges(w.ng, d_ranges + r0, (int)w.ranges.size(), d_blk + b0, (int64_t)w.nwaves,
+                                       d_mats, d_vals, d_tops, d_partials, st));
+            r0 += w.ranges.size();
+            b0 += w.blk_first.size();
         }
+        for (int c = 0; c < kBatchStreams; ++c)
+            if (used[c]) {
+                HIP_OK(hipEventRecord(ev_join[c], cls[c]));
+                HIP_OK(hipStreamWaitEvent(stream, ev_join[c], 0));
+            }
         HIP_OK(launch_batch_finish(d_fin, nm, d_partials, d_out, stream));
         return PERM_OK;
     };
-    if (use_graph) {
+    if (how == BatchLaunch::Graph) {
         if (graph_exec) {
             hipGraphExecDestroy(graph_exec);
             graph_exec = nullptr;

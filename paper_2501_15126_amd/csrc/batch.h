@@ -17,13 +17,15 @@
 
 namespace permx {
 
-// Launches the batch kernel for items [0, nitems) whose matrices all have ng
-// groups.  Item i writes its double-double partial to partials[2*items[i].out].
-hipError_t launch_batch_items(int ng, const BatchItem *items, int64_t nitems, const BatchMat *mats,
-                              const double *vals, const int32_t *tops, double *partials, hipStream_t stream);
+// Launches the batch kernel for waves [0, nwaves) described by ranges[0,
+// nranges) (sorted by wave0, each non-empty, ranges[0].wave0 = 0) whose
+// matrices all have ng groups; blk_first[b] is the range holding wave 4b.
+hipError_t launch_batch_ranges(int ng, const BatchRange *ranges, int nranges, const int32_t *blk_first,
+                               int64_t nwaves, const BatchMat *mats, const double *vals, const int32_t *tops,
+                               double *partials, hipStream_t stream);
 
-// out[i] = (4 (n mod 2) - 2) * (partials of d[i], added in order in
-// double-double), i = 0..count-1.
+// out[i] = (4 (n mod 2) - 2) * (partials of d[i], double-double, in an order
+// fixed by the partials' count), i = 0..count-1.
 hipError_t launch_batch_finish(const FinishDesc *d, int count, const double *partials, double *out,
                                hipStream_t stream);
 

@@ -26,21 +26,28 @@ namespace {
 using namespace batch_detail;
 
 template <int NG>
-__global__ void __launch_bounds__(256) batch_kernel(const BatchItem *__restrict__ items, long long nitems,
+__global__ void __launch_bounds__(256) batch_kernel(const BatchRange *__restrict__ ranges, int nranges,
+                                                    const int32_t *__restrict__ blk_first, long long nwaves,
                                                     const BatchMat *__restrict__ mats,
                                                     const double *__restrict__ vals,
                                                     const int32_t *__restrict__ tops_all,
                                                     double *__restrict__ partials) {
     // the wave's index is uniform: readfirstlane lets the compiler keep the
-    // item, the matrix descriptor and the column data in scalar registers
-    const long long item = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (item >= nitems) return;  // the whole wave leaves together
-    const BatchItem it = items[item];
-    const BatchMat md = mats[it.mat];
+    // range, the matrix descriptor and the column data in scalar registers
+    const long long w = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= nwaves) return;  // the whole wave leaves together
+    // blk_first holds the range of the workgroup's first wave; ranges are
+    // non-empty, so the other three waves are at most three ranges further
+    int r = blk_first[blockIdx.x];
+    while (r + 1 < nranges && (long long)ranges[r + 1].wave0 <= w) ++r;
+    const BatchRange rg = ranges[r];
+    const u64 k = (u64)(w - (long long)rg.wave0);
+    const BatchMat md = mats[rg.mat];
     const int lane = threadIdx.x & 63;
-    const u64 m0 = it.chunk0 + (u64)lane;
+    const u64 chunk0 = (rg.item0 + k) * 64;
+    const u64 m0 = chunk0 + (u64)lane;
     const bool active = m0 < md.nchunks;
-    const u64 m = active ? m0 : it.chunk0;  // inactive lanes replay a valid chunk and add nothing
+    const u64 m = active ? m0 : chunk0;  // inactive lanes replay a valid chunk and add nothing
     dd cs = batch_lane<NG>(md, vals, tops_all, m);
     if (!active) {
         cs.h = 0.0;
@@ -53,35 +60,58 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchItem *__restrict_
         cs = dd_add(cs, o);
     }
     if (lane == 0) {
-        partials[2 * it.out] = cs.h;
-        partials[2 * it.out + 1] = cs.l;
+        const u64 out = rg.out0 + k;
+        partials[2 * out] = cs.h;
+        partials[2 * out + 1] = cs.l;
     }
 }
 
-__global__ void __launch_bounds__(256) batch_finish(const FinishDesc *__restrict__ d, int count,
+// One workgroup per matrix: thread t adds partials t, t + 256, ... and a
+// fixed binary tree in LDS combines the 256 sums, so the order depends only
+// on the number of partials.
+__global__ void __launch_bounds__(256) batch_finish(const FinishDesc *__restrict__ d,
                                                     const double *__restrict__ partials, double *__restrict__ out) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= count) return;
+    __shared__ double sh[2 * 256];
+    const FinishDesc fd = d[blockIdx.x];
+    const int t = threadIdx.x;
     dd acc;
     acc.h = 0.0;
     acc.l = 0.0;
-    const uint64_t p0 = d[i].part;
-    for (uint64_t k = 0; k < d[i].count; ++k) {
+    for (u64 k = t; k < fd.count; k += 256) {
         dd v;
-        v.h = partials[2 * (p0 + k)];
-        v.l = partials[2 * (p0 + k) + 1];
+        v.h = partials[2 * (fd.part + k)];
+        v.l = partials[2 * (fd.part + k) + 1];
         acc = dd_add(acc, v);
     }
-    const double f = (d[i].n % 2 == 1) ? 2.0 : -2.0;  // 4 (n mod 2) - 2
-    out[i] = (acc.h + acc.l) * f;
+    sh[2 * t] = acc.h;
+    sh[2 * t + 1] = acc.l;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) {
+            dd a, b;
+            a.h = sh[2 * t];
+            a.l = sh[2 * t + 1];
+            b.h = sh[2 * (t + s)];
+            b.l = sh[2 * (t + s) + 1];
+            a = dd_add(a, b);
+            sh[2 * t] = a.h;
+            sh[2 * t + 1] = a.l;
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double f = (fd.n % 2 == 1) ? 2.0 : -2.0;  // 4 (n mod 2) - 2
+        out[blockIdx.x] = (sh[0] + sh[1]) * f;
+    }
 }
 
 template <int NG>
-hipError_t launch_t(const BatchItem *items, int64_t nitems, const BatchMat *mats, const double *vals,
-                    const int32_t *tops, double *partials, hipStream_t stream) {
-    const unsigned blocks = (unsigned)((nitems + 3) / 4);
-    hipLaunchKernelGGL((batch_kernel<NG>), dim3(blocks), dim3(256), 0, stream, items, (long long)nitems, mats,
-                       vals, tops, partials);
+hipError_t launch_t(const BatchRange *ranges, int nranges, const int32_t *blk_first, int64_t nwaves,
+                    const BatchMat *mats, const double *vals, const int32_t *tops, double *partials,
+                    hipStream_t stream) {
+    const unsigned blocks = (unsigned)((nwaves + 3) / 4);
+    hipLaunchKernelGGL((batch_kernel<NG>), dim3(blocks), dim3(256), 0, stream, ranges, nranges, blk_first,
+                       (long long)nwaves, mats, vals, tops, partials);
     return hipGetLastError();
 }
 
@@ -98,12 +128,14 @@ void attrs_t(int *vgprs, int *scratch) {
 
 }  // namespace
 
-hipError_t launch_batch_items(int ng, const BatchItem *items, int64_t nitems, const BatchMat *mats,
-                              const double *vals, const int32_t *tops, double *partials, hipStream_t stream) {
-    if (nitems <= 0) return hipSuccess;
+hipError_t launch_batch_ranges(int ng, const BatchRange *ranges, int nranges, const int32_t *blk_first,
+                               int64_t nwaves, const BatchMat *mats, const double *vals, const int32_t *tops,
+                               double *partials, hipStream_t stream) {
+    if (nwaves <= 0) return hipSuccess;
+    if (nranges <= 0 || (nwaves + 3) / 4 > 0x7fffffff) return hipErrorInvalidValue;
 #define PERM_CASE(NGV) \
     case NGV:          \
-        return launch_t<NGV>(items, nitems, mats, vals, tops, partials, stream);
+        return launch_t<NGV>(ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
     switch (ng) {
         PERM_NG_TABLE(PERM_CASE)
         default:
@@ -115,7 +147,7 @@ hipError_t launch_batch_items(int ng, const BatchItem *items, int64_t nitems, co
 hipError_t launch_batch_finish(const FinishDesc *d, int count, const double *partials, double *out,
                                hipStream_t stream) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_finish, dim3((count + 255) / 256), dim3(256), 0, stream, d, count, partials, out);
+    hipLaunchKernelGGL(batch_finish, dim3(count), dim3(256), 0, stream, d, partials, out);
     return hipGetLastError();
 }
 

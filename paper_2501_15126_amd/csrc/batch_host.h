@@ -33,29 +33,61 @@ struct PreparedMatrix {
 int batch_kappa(int n, int shift);
 perm_status prepare_batch_matrix(const perm_csc *m, const BatchOptions &bo, PreparedMatrix *pm, std::string *err);
 
+// The waves of one kernel instance (ng) of a launch, as ranges plus the
+// per-workgroup first-range table the kernel starts its search from.
+struct WavePlan {
+    int ng = 0;
+    std::vector<BatchRange> ranges;
+    std::vector<int32_t> blk_first;
+    uint64_t nwaves = 0;
+    // appends waves for items item0 .. item0 + count - 1 of matrix `mat`,
+    // whose partials go to out0 .. out0 + count - 1 (count > 0)
+    void add(int32_t mat, uint64_t item0, uint64_t count, uint64_t out0);
+    void clear() {
+        ranges.clear();
+        blk_first.clear();
+        nwaves = 0;
+    }
+};
+
+// The library's kernel-class streams (kernel instance ng runs on stream
+// ng % kBatchStreams), created on first use on the current device.  Default
+// priority, non-blocking.
+hipError_t batch_class_streams(hipStream_t out[kBatchStreams]);
+
+// How perm_batch issues its launches.
+enum class BatchLaunch {
+    Streams,  // each kernel instance on its class stream, forked from and joined to the caller's stream
+    Graph,    // all launches on the caller's stream, captured into one graph and launched
+    Single,   // all launches on the caller's stream
+};
+
 // Device buffers and a captured graph for running prepared matrices.
 struct BatchJob {
     BatchMat *d_mats = nullptr;
-    BatchItem *d_items = nullptr;
+    BatchRange *d_ranges = nullptr;
+    int32_t *d_blk = nullptr;
     double *d_vals = nullptr;
     int32_t *d_tops = nullptr;
     FinishDesc *d_fin = nullptr;
     double *d_partials = nullptr;
     double *d_out = nullptr;
-    size_t cap_mats = 0, cap_items = 0, cap_vals = 0, cap_tops = 0, cap_fin = 0, cap_partials = 0, cap_out = 0;
+    size_t cap_mats = 0, cap_ranges = 0, cap_blk = 0, cap_vals = 0, cap_tops = 0, cap_fin = 0, cap_partials = 0,
+           cap_out = 0;
     char *h_stage = nullptr;
     size_t cap_stage = 0;
     double *h_out = nullptr;
     size_t cap_hout = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev_join[kBatchStreams] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
 
     ~BatchJob();
     // Runs all matrices (singular ones are answered 0 without work) and writes
     // out[i] for mats[i].  Synchronous on `stream`.
-    perm_status run(const std::vector<const PreparedMatrix *> &mats, double *out, hipStream_t stream, bool use_graph,
-                    double *kernel_ms, std::string *err);
+    perm_status run(const std::vector<const PreparedMatrix *> &mats, double *out, hipStream_t stream,
+                    BatchLaunch how, double *kernel_ms, std::string *err);
 };
 
 }  // namespace permx

@@ -16,17 +16,20 @@ struct BatchMat {
     uint64_t top_off;               // int32: top group of each flipped column
 };
 
-// One wave of work: 64 consecutive chunks of one matrix, whose double-double
-// partial goes to partials[2*out], [2*out+1].
-struct BatchItem {
+// Consecutive waves of one launch that work on one matrix: wave w of the
+// launch, wave0 <= w < the next range's wave0, takes the 64 chunks of item
+// item0 + (w - wave0) (chunks 64 item .. 64 item + 63) and writes its
+// double-double partial to partials[2 (out0 + w - wave0)], [.. + 1].
+struct BatchRange {
     int32_t mat;
     int32_t pad;
-    uint64_t chunk0;
-    uint64_t out;
+    uint64_t wave0;
+    uint64_t item0;
+    uint64_t out0;
 };
 
-// A matrix's final sum: partials part .. part+count-1 added in order, times
-// the final factor 4 (n mod 2) - 2.
+// A matrix's final sum: partials part .. part+count-1 added in an order fixed
+// by their index, times the final factor 4 (n mod 2) - 2.
 struct FinishDesc {
     uint64_t part;
     uint64_t count;
@@ -35,5 +38,6 @@ struct FinishDesc {
 };
 
 constexpr int kBatchMaxNG = 16;  // n <= 64
+constexpr int kBatchStreams = 4;  // kernel instances ng run on stream ng % kBatchStreams
 
 }  // namespace permx

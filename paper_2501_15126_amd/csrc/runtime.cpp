@@ -283,7 +283,7 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
     auto t0 = std::chrono::steady_clock::now();
     if (count < 0 || (count > 0 && (!mats || !out))) return fail(PERM_EINVAL, "bad batch arguments");
     const perm_opts o = defaults(opts);
-    if (o.batch_mode < 0 || o.batch_mode > 2) return fail(PERM_EINVAL, "batch_mode must be 0, 1 or 2");
+    if (o.batch_mode < 0 || o.batch_mode > 3) return fail(PERM_EINVAL, "batch_mode must be 0, 1, 2 or 3");
     BatchOptions bo;
     bo.zero_skip = o.zero_skip;
     bo.kappa_shift = o.batch_kappa_shift;
@@ -310,7 +310,7 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
         for (int32_t i = 0; i < count; ++i) {
             std::vector<const PreparedMatrix *> one{&prep[i]};
             double k1 = 0.0;
-            s = g_batch_job.run(one, &out[i], stream, false, &k1, &err);
+            s = g_batch_job.run(one, &out[i], stream, BatchLaunch::Single, &k1, &err);
             if (s != PERM_OK) return fail(s, err);
             kms += k1;
             launches += prep[i].singular ? 0 : 2;
@@ -318,7 +318,10 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
     } else {
         std::vector<const PreparedMatrix *> all;
         for (auto &pm : prep) all.push_back(&pm);
-        s = g_batch_job.run(all, out, stream, o.batch_mode == 0, &kms, &err);
+        const BatchLaunch how = o.batch_mode == 0   ? BatchLaunch::Streams
+                                : o.batch_mode == 1 ? BatchLaunch::Graph
+                                                    : BatchLaunch::Single;
+        s = g_batch_job.run(all, out, stream, how, &kms, &err);
         if (s != PERM_OK) return fail(s, err);
         launches = -1;
     }

@@ -2,14 +2,19 @@
 //
 // Requests are validated and prepared for the precompiled batch kernels on
 // the submitting thread.  A scheduler thread admits them in arrival order as
-// device memory (one arena of `device_mem_budget` bytes) frees up, keeps each
-// admitted request's matrix data and partial sums resident in the arena, and
-// runs rounds: every round takes a share of 64-chunk work items from every
-// active request (so a request that arrives while others run joins the next
-// round instead of waiting for them to finish), launches the batch kernels on
-// all of them together, and finishes the requests whose last items ran.  A
-// request's result depends only on its own items and their fixed-order sum,
-// so it is bitwise the same alone and in any mix.
+// device memory frees up (one arena of `device_mem_budget` bytes holds each
+// admitted request's matrix data and partial sums) and runs rounds.  A round
+// gives every active request a share of Gray steps (water-filling: a request
+// that needs less than an equal share leaves the rest to the others), as
+// 64-chunk work items, and issues them as one launch per kernel instance on
+// that instance's class stream; the requests whose last items are in the
+// round are finished on the same stream.  Two rounds are in flight: while the
+// GPU runs one, the scheduler publishes the previous one's results, admits new
+// requests and issues the next, so a request that arrives while others run
+// joins the next round and the GPU does not wait for the host between rounds.
+// A request's upload, items and finish all run on its class stream, in order,
+// and its result depends only on its own items and their fixed-order sum, so
+// it is bitwise the same alone and in any mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -134,6 +139,40 @@ bool grow_host(T **p, size_t *cap, size_t need) {
 
 }  // namespace
 
+// One class stream's share of a round slot: descriptor buffers, pinned
+// staging and the event that marks the stream's part of the round done.
+struct ClassBuf {
+    BatchMat *d_mats = nullptr;
+    BatchRange *d_ranges = nullptr;
+    int32_t *d_blk = nullptr;
+    FinishDesc *d_fin = nullptr;
+    double *d_out = nullptr;
+    size_t cap_mats = 0, cap_ranges = 0, cap_blk = 0, cap_fin = 0, cap_out = 0;
+    char *h_stage = nullptr;
+    size_t cap_stage = 0;
+    double *h_out = nullptr;
+    size_t cap_hout = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+    std::vector<Request *> finishing;
+
+    void release() {
+        if (d_mats) (void)hipFree(d_mats);
+        if (d_ranges) (void)hipFree(d_ranges);
+        if (d_blk) (void)hipFree(d_blk);
+        if (d_fin) (void)hipFree(d_fin);
+        if (d_out) (void)hipFree(d_out);
+        if (h_stage) (void)hipHostFree(h_stage);
+        if (h_out) (void)hipHostFree(h_out);
+        if (done) (void)hipEventDestroy(done);
+    }
+};
+
+struct Slot {
+    ClassBuf cls[kBatchStreams];
+    bool busy = false;
+};
+
 struct perm_server {
     perm_opts opts;
     BatchOptions bo;
@@ -155,28 +194,23 @@ struct perm_server {
     uint64_t n_submitted = 0, n_completed = 0, n_rounds = 0;
     size_t peak_bytes = 0;
     double busy_ms = 0.0;
+    Clock::time_point busy_since;
 
     // device side (worker thread only, after creation)
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t streams[kBatchStreams] = {};
     char *arena = nullptr;
     Arena alloc;
-    BatchMat *d_mats = nullptr;
-    BatchItem *d_items = nullptr;
-    FinishDesc *d_fin = nullptr;
-    double *d_out = nullptr;
-    size_t cap_mats = 0, cap_items = 0, cap_fin = 0, cap_out = 0;
-    char *h_stage = nullptr;
-    size_t cap_stage = 0;
-    double *h_out = nullptr;
-    size_t cap_hout = 0;
+    Slot slots[2];
 
     void run();
-    bool admit(std::vector<Request *> &newly, std::string *err);
-    bool round(std::string *err);
+    void admit(std::vector<Request *> &newly);
+    bool dispatchable() const;
+    bool issue(Slot &slot, const std::vector<Request *> &newly, std::string *err);
+    bool complete(Slot &slot, std::string *err);
 };
 
-bool perm_server::admit(std::vector<Request *> &newly, std::string *err) {
+void perm_server::admit(std::vector<Request *> &newly) {
     // in arrival order while the arena has room (no overtaking)
     while (!pending.empty()) {
         Request *r = pending.front();
@@ -187,159 +221,245 @@ bool perm_server::admit(std::vector<Request *> &newly, std::string *err) {
         newly.push_back(r);
     }
     peak_bytes = std::max(peak_bytes, alloc.used());
-    (void)err;
-    return true;
 }
 
-bool perm_server::round(std::string *err) {
-    // ---- pick work items: an equal share per active request, oldest first ----
-    std::vector<Request *> act = active;
-    const double share_steps = round_steps / std::max<size_t>(1, act.size());
-    std::vector<BatchMat> mats;
-    std::vector<BatchItem> items;
-    std::vector<FinishDesc> fin;
-    std::vector<Request *> finishing;
-    for (Request *r : act) {
-        const PreparedMatrix &pm = r->pm;
-        const double item_steps = std::ldexp(64.0, pm.kappa);
-        const uint64_t share = std::max<uint64_t>(1, (uint64_t)(share_steps / item_steps));
-        const uint64_t take = std::min<uint64_t>(share, r->items_total - r->next_item);
-        if (take == 0) continue;
-        BatchMat d;
-        d.n = pm.n;
-        d.ng = pm.ng;
-        d.kappa = pm.kappa;
-        d.zero_skip = pm.zero_skip ? 1 : 0;
-        d.chunk_top = pm.chunk_top;
-        d.pad = 0;
-        d.nchunks = pm.nchunks;
-        d.col_off = r->arena_off / sizeof(double);
-        d.base_off = d.col_off + pm.base_index;
-        d.top_off = (r->arena_off + r->vals_bytes) / sizeof(int32_t);
-        const int mi = (int)mats.size();
-        mats.push_back(d);
-        const size_t tops_bytes = (pm.tops.size() * sizeof(int32_t) + kAlign - 1) / kAlign * kAlign;
-        const uint64_t part0 = (r->arena_off + r->vals_bytes + tops_bytes) / (2 * sizeof(double));
-        for (uint64_t k = 0; k < take; ++k) {
-            const uint64_t it = r->next_item + k;
-            items.push_back(BatchItem{mi, 0, it * 64, part0 + it});
-        }
-        r->next_item += take;
-        if (r->next_item == r->items_total) {
-            fin.push_back(FinishDesc{part0, r->items_total, pm.n, 0});
-            finishing.push_back(r);
-        }
-    }
-    // items grouped by kernel instance (ng), stable within a group
-    std::stable_sort(items.begin(), items.end(),
-                     [&](const BatchItem &a, const BatchItem &b) { return mats[a.mat].ng < mats[b.mat].ng; });
-    const size_t nm = mats.size(), ni = items.size(), nf = fin.size();
-    if (!grow_dev(&d_mats, &cap_mats, std::max<size_t>(nm, 1)) ||
-        !grow_dev(&d_items, &cap_items, std::max<size_t>(ni, 1)) ||
-        !grow_dev(&d_fin, &cap_fin, std::max<size_t>(nf, 1)) || !grow_dev(&d_out, &cap_out, std::max<size_t>(nf, 1))) {
-        *err = "device allocation for a round failed";
-        return false;
-    }
-    const size_t bytes = nm * sizeof(BatchMat) + ni * sizeof(BatchItem) + nf * sizeof(FinishDesc) + 64;
-    if (!grow_host(&h_stage, &cap_stage, bytes) || !grow_host(&h_out, &cap_hout, std::max<size_t>(nf, 1))) {
-        *err = "pinned host allocation for a round failed";
-        return false;
-    }
-    char *p = h_stage;
-    memcpy(p, mats.data(), nm * sizeof(BatchMat));
-    char *s_items = p + (nm * sizeof(BatchMat) + 15) / 16 * 16;
-    memcpy(s_items, items.data(), ni * sizeof(BatchItem));
-    char *s_fin = s_items + (ni * sizeof(BatchItem) + 15) / 16 * 16;
-    memcpy(s_fin, fin.data(), nf * sizeof(FinishDesc));
-#define SRV_HIP(call)                                                            \
-    do {                                                                         \
-        hipError_t e_ = (call);                                                  \
-        if (e_ != hipSuccess) {                                                  \
-            *err = std::string(#call) + ": " + hipGetErrorString(e_);            \
-            return false;                                                        \
-        }                                                                        \
+bool perm_server::dispatchable() const {
+    for (const Request *r : active)
+        if (r->next_item < r->items_total) return true;
+    return false;
+}
+
+#define SRV_HIP(call)                                                 \
+    do {                                                              \
+        hipError_t e_ = (call);                                       \
+        if (e_ != hipSuccess) {                                       \
+            *err = std::string(#call) + ": " + hipGetErrorString(e_); \
+            return false;                                             \
+        }                                                             \
     } while (0)
-    SRV_HIP(hipMemcpyAsync(d_mats, p, nm * sizeof(BatchMat), hipMemcpyHostToDevice, stream));
-    SRV_HIP(hipMemcpyAsync(d_items, s_items, ni * sizeof(BatchItem), hipMemcpyHostToDevice, stream));
-    if (nf) SRV_HIP(hipMemcpyAsync(d_fin, s_fin, nf * sizeof(FinishDesc), hipMemcpyHostToDevice, stream));
+
+bool perm_server::issue(Slot &slot, const std::vector<Request *> &newly, std::string *err) {
+    if (!slots[0].busy && !slots[1].busy) busy_since = Clock::now();
+    // ---- shares: water-filling of round_steps over the requests with work left ----
+    struct Take {
+        Request *r;
+        uint64_t items;
+    };
+    std::vector<std::pair<double, Request *>> cand;
+    for (Request *r : active)
+        if (r->next_item < r->items_total)
+            cand.emplace_back((double)(r->items_total - r->next_item) * std::ldexp(64.0, r->pm.kappa), r);
+    std::stable_sort(cand.begin(), cand.end(),
+                     [](const std::pair<double, Request *> &x, const std::pair<double, Request *> &y) {
+                         return x.first < y.first;
+                     });
+    std::vector<Take> takes[kBatchStreams];
+    double left = round_steps;
+    size_t k = cand.size();
+    for (auto &c : cand) {
+        Request *r = c.second;
+        const double item_steps = std::ldexp(64.0, r->pm.kappa);
+        const double give = std::min(c.first, std::max(0.0, left) / (double)k--);
+        const uint64_t rem = r->items_total - r->next_item;
+        const uint64_t t = std::min<uint64_t>(rem, std::max<uint64_t>(1, (uint64_t)(give / item_steps)));
+        left -= (double)t * item_steps;
+        takes[r->pm.ng % kBatchStreams].push_back(Take{r, t});
+    }
+    // ---- per class stream: stage, upload, launch, finish ----
     const double *vals = reinterpret_cast<const double *>(arena);
     const int32_t *tops = reinterpret_cast<const int32_t *>(arena);
     double *parts = reinterpret_cast<double *>(arena);
-    size_t i0 = 0;
-    while (i0 < ni) {
-        const int ng = mats[items[i0].mat].ng;
-        size_t i1 = i0;
-        while (i1 < ni && mats[items[i1].mat].ng == ng) ++i1;
-        SRV_HIP(launch_batch_items(ng, d_items + i0, (int64_t)(i1 - i0), d_mats, vals, tops, parts, stream));
-        i0 = i1;
+    for (int c = 0; c < kBatchStreams; ++c) {
+        ClassBuf &cb = slot.cls[c];
+        cb.used = false;
+        cb.finishing.clear();
+        std::vector<Request *> up;
+        for (Request *r : newly)
+            if (r->pm.ng % kBatchStreams == c) up.push_back(r);
+        if (takes[c].empty() && up.empty()) continue;
+        // launches ordered by kernel instance, larger instances first
+        std::stable_sort(takes[c].begin(), takes[c].end(),
+                         [](const Take &x, const Take &y) { return x.r->pm.ng > y.r->pm.ng; });
+        std::vector<BatchMat> mats;
+        std::vector<WavePlan> plans;
+        std::vector<FinishDesc> fin;
+        for (const Take &t : takes[c]) {
+            Request *r = t.r;
+            const PreparedMatrix &pm = r->pm;
+            BatchMat d;
+            d.n = pm.n;
+            d.ng = pm.ng;
+            d.kappa = pm.kappa;
+            d.zero_skip = pm.zero_skip ? 1 : 0;
+            d.chunk_top = pm.chunk_top;
+            d.pad = 0;
+            d.nchunks = pm.nchunks;
+            d.col_off = r->arena_off / sizeof(double);
+            d.base_off = d.col_off + pm.base_index;
+            d.top_off = (r->arena_off + r->vals_bytes) / sizeof(int32_t);
+            const int32_t mi = (int32_t)mats.size();
+            mats.push_back(d);
+            const size_t tops_bytes = (pm.tops.size() * sizeof(int32_t) + kAlign - 1) / kAlign * kAlign;
+            const uint64_t part0 = (r->arena_off + r->vals_bytes + tops_bytes) / (2 * sizeof(double));
+            if (plans.empty() || plans.back().ng != pm.ng) {
+                plans.emplace_back();
+                plans.back().ng = pm.ng;
+            }
+            plans.back().add(mi, r->next_item, t.items, part0 + r->next_item);
+            r->next_item += t.items;
+            if (r->next_item == r->items_total) {
+                fin.push_back(FinishDesc{part0, r->items_total, pm.n, 0});
+                cb.finishing.push_back(r);
+            }
+        }
+        size_t nranges = 0, nblk = 0, up_bytes = 0;
+        for (const WavePlan &w : plans) {
+            nranges += w.ranges.size();
+            nblk += w.blk_first.size();
+        }
+        for (Request *r : up) up_bytes += r->vals_bytes + r->pm.tops.size() * sizeof(int32_t) + kAlign;
+        const size_t nm = mats.size(), nf = fin.size();
+        if (!grow_dev(&cb.d_mats, &cb.cap_mats, std::max<size_t>(nm, 1)) ||
+            !grow_dev(&cb.d_ranges, &cb.cap_ranges, std::max<size_t>(nranges, 1)) ||
+            !grow_dev(&cb.d_blk, &cb.cap_blk, std::max<size_t>(nblk, 1)) ||
+            !grow_dev(&cb.d_fin, &cb.cap_fin, std::max<size_t>(nf, 1)) ||
+            !grow_dev(&cb.d_out, &cb.cap_out, std::max<size_t>(nf, 1))) {
+            *err = "device allocation for a round failed";
+            return false;
+        }
+        const size_t bytes = nm * sizeof(BatchMat) + nranges * sizeof(BatchRange) + nblk * sizeof(int32_t) +
+                             nf * sizeof(FinishDesc) + up_bytes + 256;
+        if (!grow_host(&cb.h_stage, &cb.cap_stage, bytes) || !grow_host(&cb.h_out, &cb.cap_hout, std::max<size_t>(nf, 1))) {
+            *err = "pinned host allocation for a round failed";
+            return false;
+        }
+        if (!cb.done) SRV_HIP(hipEventCreateWithFlags(&cb.done, hipEventDisableTiming));
+        hipStream_t st = streams[c];
+        // every host buffer goes through pinned staging so the copies are
+        // truly asynchronous; the staging is reused only after `done`
+        char *p = cb.h_stage;
+        auto put = [&](const void *src, size_t n) {
+            char *at = p;
+            memcpy(p, src, n);
+            p += (n + 15) / 16 * 16;
+            return at;
+        };
+        for (Request *r : up) {
+            const PreparedMatrix &pm = r->pm;
+            char *sv = put(pm.vals.data(), pm.vals.size() * sizeof(double));
+            SRV_HIP(hipMemcpyAsync(arena + r->arena_off, sv, pm.vals.size() * sizeof(double), hipMemcpyHostToDevice, st));
+            char *stp = put(pm.tops.data(), pm.tops.size() * sizeof(int32_t));
+            SRV_HIP(hipMemcpyAsync(arena + r->arena_off + r->vals_bytes, stp, pm.tops.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, st));
+        }
+        if (nm) {
+            char *sm = put(mats.data(), nm * sizeof(BatchMat));
+            SRV_HIP(hipMemcpyAsync(cb.d_mats, sm, nm * sizeof(BatchMat), hipMemcpyHostToDevice, st));
+            char *sr = p;
+            for (const WavePlan &w : plans) {
+                memcpy(p, w.ranges.data(), w.ranges.size() * sizeof(BatchRange));
+                p += w.ranges.size() * sizeof(BatchRange);
+            }
+            SRV_HIP(hipMemcpyAsync(cb.d_ranges, sr, nranges * sizeof(BatchRange), hipMemcpyHostToDevice, st));
+            char *sb = p;
+            for (const WavePlan &w : plans) {
+                memcpy(p, w.blk_first.data(), w.blk_first.size() * sizeof(int32_t));
+                p += w.blk_first.size() * sizeof(int32_t);
+            }
+            p = cb.h_stage + ((size_t)(p - cb.h_stage) + 15) / 16 * 16;
+            SRV_HIP(hipMemcpyAsync(cb.d_blk, sb, nblk * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            if (nf) {
+                char *sf = put(fin.data(), nf * sizeof(FinishDesc));
+                SRV_HIP(hipMemcpyAsync(cb.d_fin, sf, nf * sizeof(FinishDesc), hipMemcpyHostToDevice, st));
+            }
+            size_t r0 = 0, b0 = 0;
+            for (const WavePlan &w : plans) {
+                SRV_HIP(launch_batch_ranges(w.ng, cb.d_ranges + r0, (int)w.ranges.size(), cb.d_blk + b0,
+                                            (int64_t)w.nwaves, cb.d_mats, vals, tops, parts, st));
+                r0 += w.ranges.size();
+                b0 += w.blk_first.size();
+            }
+            if (nf) {
+                SRV_HIP(launch_batch_finish(cb.d_fin, (int)nf, parts, cb.d_out, st));
+                SRV_HIP(hipMemcpyAsync(cb.h_out, cb.d_out, nf * sizeof(double), hipMemcpyDeviceToHost, st));
+            }
+        }
+        SRV_HIP(hipEventRecord(cb.done, st));
+        cb.used = true;
     }
-    if (nf) {
-        SRV_HIP(launch_batch_finish(d_fin, (int)nf, parts, d_out, stream));
-        SRV_HIP(hipMemcpyAsync(h_out, d_out, nf * sizeof(double), hipMemcpyDeviceToHost, stream));
-    }
-    SRV_HIP(hipStreamSynchronize(stream));
-#undef SRV_HIP
-    const auto now = Clock::now();
-    std::lock_guard<std::mutex> g(mu);
-    for (size_t i = 0; i < nf; ++i) {
-        Request *r = finishing[i];
-        r->result = h_out[i];
-        r->state = State::Done;
-        r->t_done = now;
-        alloc.release(r->arena_off, r->bytes);
-        active.erase(std::find(active.begin(), active.end(), r));
-        ++n_completed;
-    }
+    slot.busy = true;
     ++n_rounds;
-    if (nf) cv_done.notify_all();
     return true;
 }
 
+bool perm_server::complete(Slot &slot, std::string *err) {
+    for (int c = 0; c < kBatchStreams; ++c)
+        if (slot.cls[c].used) SRV_HIP(hipEventSynchronize(slot.cls[c].done));
+    const auto now = Clock::now();
+    std::lock_guard<std::mutex> g(mu);
+    bool any = false;
+    for (int c = 0; c < kBatchStreams; ++c) {
+        ClassBuf &cb = slot.cls[c];
+        if (!cb.used) continue;
+        for (size_t i = 0; i < cb.finishing.size(); ++i) {
+            Request *r = cb.finishing[i];
+            r->result = cb.h_out[i];
+            r->state = State::Done;
+            r->t_done = now;
+            alloc.release(r->arena_off, r->bytes);
+            active.erase(std::find(active.begin(), active.end(), r));
+            ++n_completed;
+            any = true;
+        }
+        cb.finishing.clear();
+        cb.used = false;
+    }
+    slot.busy = false;
+    if (!slots[0].busy && !slots[1].busy)
+        busy_ms += std::chrono::duration<double, std::milli>(now - busy_since).count();
+    if (any) cv_done.notify_all();
+    return true;
+}
+
+#undef SRV_HIP
+
 void perm_server::run() {
     std::string err;
-    if (hipSetDevice(device) != hipSuccess) {
-        std::lock_guard<std::mutex> g(mu);
-        fatal = "hipSetDevice failed in the server thread";
-    }
-    for (;;) {
+    bool ok = hipSetDevice(device) == hipSuccess;
+    if (!ok) err = "hipSetDevice failed in the server thread";
+    int cur = 0;  // the slot the next round goes to; when both are busy it holds the older round
+    while (ok) {
         std::vector<Request *> newly;
+        bool work;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv_work.wait(lk, [&] { return stop || !pending.empty() || !active.empty() || !fatal.empty(); });
-            if (!fatal.empty() || (stop && pending.empty() && active.empty())) break;
-            admit(newly, &err);
-        }
-        // upload the newly admitted requests' data into the arena
-        bool ok = true;
-        for (Request *r : newly) {
-            const PreparedMatrix &pm = r->pm;
-            if (hipMemcpyAsync(arena + r->arena_off, pm.vals.data(), pm.vals.size() * sizeof(double),
-                               hipMemcpyHostToDevice, stream) != hipSuccess ||
-                hipMemcpyAsync(arena + r->arena_off + r->vals_bytes, pm.tops.data(), pm.tops.size() * sizeof(int32_t),
-                               hipMemcpyHostToDevice, stream) != hipSuccess) {
-                ok = false;
-                err = "upload of an admitted request failed";
-            }
-        }
-        {
-            std::lock_guard<std::mutex> g(mu);
+            cv_work.wait(lk, [&] {
+                return stop || !pending.empty() || dispatchable() || slots[0].busy || slots[1].busy;
+            });
+            if (stop && pending.empty() && active.empty() && !slots[0].busy && !slots[1].busy) break;
+            admit(newly);
             for (Request *r : newly) {
                 r->state = State::Active;
                 active.push_back(r);
             }
+            work = dispatchable();
         }
-        const auto t0 = Clock::now();
-        if (ok) ok = round(&err);
-        busy_ms += std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
-        if (!ok) {
-            std::lock_guard<std::mutex> g(mu);
-            fatal = err;
-            break;
+        const bool idle = !slots[0].busy && !slots[1].busy;
+        if (work) {
+            if (slots[cur].busy) ok = complete(slots[cur], &err);
+            if (ok) {
+                ok = issue(slots[cur], newly, &err);
+                cur ^= 1;
+            }
+        } else if (!idle) {
+            Slot &old = slots[cur].busy ? slots[cur] : slots[cur ^ 1];
+            ok = complete(old, &err);
         }
     }
     // on a device error every unfinished request fails
     std::lock_guard<std::mutex> g(mu);
-    if (!fatal.empty()) {
+    if (!ok) {
+        fatal = err;
         for (auto &kv : tickets)
             if (kv.second->state != State::Done) {
                 kv.second->state = State::Done;
@@ -360,7 +480,8 @@ perm_status sfail(perm_status s, const std::string &m) {
 
 extern "C" {
 
-perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget, int32_t max_inflight) {
+perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget, int32_t max_inflight,
+                                double round_steps) {
     std::unique_ptr<perm_server> s(new perm_server);
     memset(&s->opts, 0, sizeof s->opts);
     if (opts) s->opts = *opts;
@@ -368,7 +489,12 @@ perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget,
     s->bo.kappa_shift = s->opts.batch_kappa_shift;
     s->budget = device_mem_budget ? device_mem_budget : ((size_t)1 << 30);
     s->max_inflight = max_inflight > 0 ? max_inflight : 4096;
-    s->round_steps = 4.0e9;  // a few milliseconds of device work per round
+    if (!(round_steps >= 0.0)) {
+        set_last_error("round_steps must be >= 0");
+        return nullptr;
+    }
+    // default: about 10 ms of the device's Gray-step throughput per round
+    s->round_steps = round_steps > 0.0 ? round_steps : 8.0e9;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
         set_last_error("no HIP device available");
@@ -383,12 +509,14 @@ perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget,
         set_last_error("device is not gfx950 (MI355X)");
         return nullptr;
     }
-    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
-        set_last_error("stream creation failed");
-        return nullptr;
-    }
+    for (int c = 0; c < kBatchStreams; ++c)
+        if (hipStreamCreateWithFlags(&s->streams[c], hipStreamNonBlocking) != hipSuccess) {
+            for (int d = 0; d < c; ++d) (void)hipStreamDestroy(s->streams[d]);
+            set_last_error("stream creation failed");
+            return nullptr;
+        }
     if (hipMalloc(&s->arena, s->budget) != hipSuccess) {
-        (void)hipStreamDestroy(s->stream);
+        for (int c = 0; c < kBatchStreams; ++c) (void)hipStreamDestroy(s->streams[c]);
         set_last_error("device arena allocation of " + std::to_string(s->budget) + " bytes failed");
         return nullptr;
     }
@@ -487,15 +615,11 @@ void perm_server_destroy(perm_server *s) {
     }
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
-    (void)hipStreamSynchronize(s->stream);
+    for (int c = 0; c < kBatchStreams; ++c) (void)hipStreamSynchronize(s->streams[c]);
     if (s->arena) (void)hipFree(s->arena);
-    if (s->d_mats) (void)hipFree(s->d_mats);
-    if (s->d_items) (void)hipFree(s->d_items);
-    if (s->d_fin) (void)hipFree(s->d_fin);
-    if (s->d_out) (void)hipFree(s->d_out);
-    if (s->h_stage) (void)hipHostFree(s->h_stage);
-    if (s->h_out) (void)hipHostFree(s->h_out);
-    (void)hipStreamDestroy(s->stream);
+    for (Slot &sl : s->slots)
+        for (ClassBuf &cb : sl.cls) cb.release();
+    for (int c = 0; c < kBatchStreams; ++c) (void)hipStreamDestroy(s->streams[c]);
     delete s;
 }
 

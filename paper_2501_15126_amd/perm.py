@@ -119,7 +119,7 @@ class PermServerStats(ctypes.Structure):
 
 
 _lib.perm_server_create.restype = ctypes.c_void_p
-_lib.perm_server_create.argtypes = [_P(PermOpts), ctypes.c_size_t, ctypes.c_int32]
+_lib.perm_server_create.argtypes = [_P(PermOpts), ctypes.c_size_t, ctypes.c_int32, ctypes.c_double]
 _lib.perm_submit.restype = ctypes.c_int
 _lib.perm_submit.argtypes = [ctypes.c_void_p, _P(PermCsc), _P(ctypes.c_uint64)]
 _lib.perm_poll.restype = ctypes.c_int
@@ -175,7 +175,7 @@ def _stream_handle(stream):
 
 
 def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, force_k=0, force_c=0,
-              max_levels=0, gr_ratio=0.0, stream=None, zero_skip="auto", batch_mode="graph",
+              max_levels=0, gr_ratio=0.0, stream=None, zero_skip="auto", batch_mode="streams",
               batch_kappa_shift=0):
     o = PermOpts()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -183,7 +183,7 @@ def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, 
     o.vgpr_budget, o.force_k, o.force_c, o.max_levels = vgpr_budget, force_k, force_c, max_levels
     o.gr_ratio = gr_ratio
     o.zero_skip = {"auto": 0, True: 1, False: -1}[zero_skip]
-    o.batch_mode = {"graph": 0, "launches": 1, "sequential": 2}[batch_mode]
+    o.batch_mode = {"streams": 0, "graph": 1, "sequential": 2, "one_stream": 3}[batch_mode]
     o.batch_kappa_shift = batch_kappa_shift
     o.hip_stream = _stream_handle(stream)
     return o
@@ -302,9 +302,9 @@ def compile_plan_stats(ccs, **opts):
 class Server:
     """Submit/poll permanent server (perm_server_*)."""
 
-    def __init__(self, device_mem_budget=0, max_inflight=0, **opts):
+    def __init__(self, device_mem_budget=0, max_inflight=0, round_steps=0.0, **opts):
         self._opts = make_opts(**opts)
-        h = _lib.perm_server_create(ctypes.byref(self._opts), device_mem_budget, max_inflight)
+        h = _lib.perm_server_create(ctypes.byref(self._opts), device_mem_budget, max_inflight, float(round_steps))
         if not h:
             raise PermError(PERM_EDEVICE, last_error())
         self._h = ctypes.c_void_p(h)

@@ -55,13 +55,15 @@ def test_batch_vs_oracle_mixed(P, oracle_mod):
 
 
 def test_batch_modes_and_alone_are_bitwise_equal(P):
-    """One graph, plain launches, one matrix per launch, and each matrix alone:
-    identical bits (a matrix's work and reduction order depend only on it)."""
+    """Class streams, one graph, one stream, one matrix per launch, and each
+    matrix alone: identical bits (a matrix's work and reduction order depend
+    only on it)."""
     mats = _mixed(2, 40)
     a = P.perm_batch(mats)
-    b = P.perm_batch(mats, batch_mode="launches")
+    b = P.perm_batch(mats, batch_mode="graph")
     c = P.perm_batch(mats, batch_mode="sequential")
-    assert np.array_equal(a, b) and np.array_equal(a, c)
+    d = P.perm_batch(mats, batch_mode="one_stream")
+    assert np.array_equal(a, b) and np.array_equal(a, c) and np.array_equal(a, d)
     for i in (0, 7, 19, 33):
         alone = P.perm_batch([mats[i]])
         assert alone[0] == a[i]

@@ -92,10 +92,12 @@ def test_server_memory_admission_and_backpressure(P):
 
 def test_server_continuous_batching(P):
     """A small request submitted right after a large one is admitted with it,
-    shares the rounds, and completes while the large one is still running."""
+    shares the rounds, and completes while the large one is still running
+    (rounds of 1e9 Gray steps: the large request, 2^33 steps, needs at least
+    eight more after the small one's)."""
     large = W.single_real(34, 0.3, 2)
     small = W.single_real(14, 0.3, 3)
-    with P.Server() as srv:
+    with P.Server(round_steps=1e9) as srv:
         tl = srv.submit(large)
         ts = srv.submit(small)
         vs = srv.wait(ts)
