@@ -52,7 +52,7 @@ def cpu_baseline(ccs, seconds_target=15.0):
                       % (int(math.log2(steps)), n - 1, dt)}
 
 
-def batch_bench(seed=1, count=2000, reps=3):
+def batch_bench(seed=1, count=2000, reps=3, sequential=True):
     """The batch workload (2000 matrices, n ~ U{16..30}, density ~ U[0.15, 0.40],
     U(-1,1) values): one call of perm_batch (one launch per kernel instance on
     its class stream, host preparation included) against one matrix per
@@ -67,18 +67,27 @@ def batch_bench(seed=1, count=2000, reps=3):
         out, st = P.perm_batch_ex(mats)
         dt = time.perf_counter() - t0
         best = (dt, st, out) if best is None or dt < best[0] else best
-    t0 = time.perf_counter()
-    out_seq, st_seq = P.perm_batch_ex(mats, batch_mode="sequential")
-    dt_seq = time.perf_counter() - t0
     dt, st, out = best
-    return {"workload": "%d sparse real matrices, n ~ U{16..30}, density ~ U[0.15,0.40], U(-1,1), seed %d"
+    res = {"workload": "%d sparse real matrices, n ~ U{16..30}, density ~ U[0.15,0.40], U(-1,1), seed %d"
                         % (count, seed),
             "permanents_per_s": count / dt, "wall_ms": dt * 1e3, "kernel_ms": st["kernel_ms"],
             "prep_ms": st["prep_ms"], "gray_steps": st["steps"], "gray_steps_per_s": st["steps"] / dt,
             "structurally_singular": st["singular"],
-            "sequential_permanents_per_s": count / dt_seq, "sequential_wall_ms": dt_seq * 1e3,
-            "speedup_vs_sequential": dt_seq / dt,
-            "bitwise_equal_to_sequential": bool(np.array_equal(out, out_seq))}
+            # the batch kernels' own FP64 work (counted exactly per chunk from
+            # their code) over the device time of the launches
+            "roofline": {"bound": "alu", "achieved": st["flops"] / (st["kernel_ms"] / 1e3) / 1e12,
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": st["flops"] / (st["kernel_ms"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+                         "fp64_ops": st["fp64_ops"],
+                         "fp64_issue_frac": st["fp64_ops"] / (st["kernel_ms"] / 1e3) / 3.93216e13}}
+    if sequential:
+        t0 = time.perf_counter()
+        out_seq, st_seq = P.perm_batch_ex(mats, batch_mode="sequential")
+        dt_seq = time.perf_counter() - t0
+        res.update({"sequential_permanents_per_s": count / dt_seq, "sequential_wall_ms": dt_seq * 1e3,
+                    "speedup_vs_sequential": dt_seq / dt,
+                    "bitwise_equal_to_sequential": bool(np.array_equal(out, out_seq))})
+    return res
 
 
 def serving_bench(duration_s=20.0, rate_hz=200.0, seed=1, compare_fifo=True, round_steps=0.0):
@@ -184,6 +193,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batch-workload measurement")
     ap.add_argument("--serving-seconds", type=float, default=20.0,
                     help="length of the Poisson serving run (0 skips it)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batch-workload measurement (for profiling the batch kernels)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (torch), to scale HBM byte counters")
     args = ap.parse_args()
@@ -204,6 +215,9 @@ def main():
     import paper_2501_15126_amd.perm as P
     from paper_2501_15126_amd import workloads as W
 
+    if args.batch_only:
+        print(json.dumps({"batch": batch_bench(reps=2, sequential=False)}), flush=True)
+        return
     zs = {"auto": "auto", "on": True, "off": False}[args.zero_skip]
     ccs = W.WORKLOADS[args.workload](args.seed)
     n = ccs[0]
@@ -264,6 +278,19 @@ def main():
         "permanent": values[-1],
         "deterministic": all(x == values[0] for x in values),
     }
+    if zs is not False:
+        # context: the same permanent with every term evaluated (pruning off)
+        P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=False)
+        ks = []
+        for _ in range(3):
+            _, st0 = P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=False)
+            ks.append(st0["kernel_ms"] / 1e3)
+        k0 = sum(ks) / len(ks)
+        tf0 = st0["flops_per_step"] * steps_per_perm / k0 / 1e12
+        out["no_skip"] = {"kernel_ms": k0 * 1e3, "steps_per_s": steps_per_perm / k0, "achieved_tflops": tf0,
+                          "frac": tf0 / FP64_PEAK_TFLOPS,
+                          "fp64_issue_frac": st0["ops_per_step"] * steps_per_perm / k0 / 3.93216e13,
+                          "vgprs": st0["vgprs"], "waves_per_simd": st0["waves_per_simd"]}
     if not args.no_batch:
         out["batch"] = batch_bench()
     if args.serving_seconds > 0:

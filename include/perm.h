@@ -162,6 +162,9 @@ typedef struct {
     int32_t singular;      /* answered 0 by the structural check */
     int32_t launches;      /* kernel launches issued */
     int32_t pad;
+    double fp64_ops;       /* FP64 operations the batch kernels execute (an FMA is one),
+                              counted exactly per chunk without zero-aware skipping */
+    double flops;          /* the same with an FMA counted as 2 */
 } perm_batch_stats;
 
 /* perm_batch with statistics (st may be NULL). */

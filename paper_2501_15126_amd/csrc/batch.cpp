@@ -80,6 +80,37 @@ perm_status prepare_batch_matrix(const perm_csc *m, const BatchOptions &bo, Prep
             if (v != std::floor(v)) pm->zero_skip = false;
     }
     pm->nchunks = (uint64_t)1 << (n - 1 - pm->kappa);
+    // Work of the batch kernel, counted from its code: a step flipping a
+    // column with top group t updates groups t..0 (4 FMAs each), refreshes
+    // the suffix products of groups t..1 (3 multiplies for the group, one
+    // more unless it is the last group) and adds the term (4 multiplies, one
+    // FMA).  Local step l flips column ctz(l); every chunk also runs one
+    // weight-0 step on column 0 and starts with the columns at or above
+    // kappa - 1, the suffix products and the first term.
+    {
+        auto step_ops = [&](int t, double *fmas) {
+            double ops = 9.0;
+            for (int g = 1; g <= t; ++g) ops += (g + 1 < ng) ? 8.0 : 7.0;
+            *fmas = 5.0 + 4.0 * t;
+            return ops;
+        };
+        const int kap = pm->kappa;
+        double ops = 0.0, fmas = 0.0, f = 0.0;
+        for (int j = 0; j < kap; ++j) {  // column j flips 2^(kappa-1-j) times per chunk
+            const double cnt = std::ldexp(1.0, kap - 1 - j);
+            ops += cnt * step_ops(pm->tops[j], &f);
+            fmas += cnt * f;
+        }
+        if (kap >= 1) {
+            ops += step_ops(pm->tops[0], &f);
+            fmas += f;
+        }
+        const double init_fmas = (double)(n - 1 - std::max(kap - 1, 0)) * 4.0 * ng;
+        ops += init_fmas + 4.0 * (ng - 1) + 4.0;
+        fmas += init_fmas;
+        pm->fp64_ops = ops * (double)pm->nchunks;
+        pm->fp64_fmas = fmas * (double)pm->nchunks;
+    }
     return PERM_OK;
 }
 

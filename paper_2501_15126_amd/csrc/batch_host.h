@@ -28,6 +28,8 @@ struct PreparedMatrix {
     std::vector<double> vals;  // [j][ng][4] column groups, then 4*ng base values
     size_t base_index = 0;     // index of the base values in vals
     std::vector<int32_t> tops; // top group per flipped column
+    double fp64_ops = 0.0;     // FP64 operations of all chunks (an FMA is one), no skipping
+    double fp64_fmas = 0.0;    // the FMAs among them
 };
 
 int batch_kappa(int n, int shift);

@@ -166,6 +166,40 @@ struct Gen {
            << ");\n";
     }
 
+    // Branch-free flip of the wave-uniform column `jvar` (one of columns
+    // jlo..jhi, else no column) with direction `svar`: for each row one of
+    // these columns touches, a scalar select picks that column's entry (0
+    // when the row is not in column jvar) and one FMA applies it.  Returns
+    // the highest level the columns touch.
+    int dyn_flip(const char *jvar, const char *svar, int jlo, int jhi, std::map<int, std::string> &cur,
+                 const char *I) {
+        const Ccs &B = p.B;
+        int top_max = 0;
+        std::map<int, std::vector<std::pair<int, double>>> rows;  // row -> (column, value)
+        for (int j = jlo; j <= jhi; ++j) {
+            top_max = std::max(top_max, p.col_top[j]);
+            for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) rows[B.rowidx[q]].push_back({j, B.val[q]});
+        }
+        for (auto &rv : rows) {
+            const int r = rv.first;
+            std::string sel = "0.0";
+            for (auto it = rv.second.rbegin(); it != rv.second.rend(); ++it)
+                sel = "(" + std::string(jvar) + " == " + std::to_string(it->first) + " ? " + lit(it->second) + " : " +
+                      sel + ")";
+            std::string target;
+            if (r < p.k) {
+                target = xname(r);
+            } else {
+                target = fresh();
+                os << I << "double " << target << " = " << cold_addr(r) << ";\n";
+                cur[r] = target;
+            }
+            os << I << target << " = fma(" << svar << ", " << sel << ", " << target << ");\n";
+            if (r >= p.k) os << I << cold_addr(r) << " = " << target << ";\n";
+        }
+        return top_max;
+    }
+
     // Static block of steps i = 1 .. 2^u - 1 inside a 2^(u+1)-aligned pair of
     // blocks; `second` selects the second block (where the step i = 2^(u-1)
     // excludes instead of includes).
@@ -247,8 +281,6 @@ struct Gen {
             for (int j = 0; j < kappa; ++j) chunk_top = std::max(chunk_top, p.col_top[j]);
             const bool skip_chunk = p.zero_skip && chunk_top + 1 <= L - 1;
             if (skip_chunk) os << "  if (!__all(S" << chunk_top + 1 << " == 0.0)) {\n";
-            os << "#pragma clang loop unroll(disable)\n";
-            os << "  for (u32 base = 0; base < " << DELTA << "u; base += " << 2 * U << "u) {\n";
             // local step base + 2^u flips column u; its direction is bit u+1
             // of the local index (uniform), or the chunk parity when u+1 = kappa
             const int term_u = (u == 0) ? -1 : 1;
@@ -259,75 +291,133 @@ struct Gen {
             int block_top = 0;
             for (int j = 0; j <= u; ++j) block_top = std::max(block_top, p.col_top[j]);
             const bool skip_block = p.zero_skip && u >= 1 && block_top + 1 <= L - 1;
-            if (skip_block) {
-                os << "    if (__all(S" << block_top + 1 << " == 0.0)) {\n";
-                std::map<int, std::string> cur;
-                if (u + 1 == kappa) {
-                    update(u, Sign::Lane, cur, "      ");
-                } else {
-                    os << "      const bool neg = (base >> " << (u + 1) << ") & 1u;\n";
-                    update(u, Sign::Uniform, cur, "      ");
+            // Larger intervals (zero-aware, exact): after position pos (a
+            // multiple of 2^v, v >= u + 2) the next 2^v - 1 steps flip only
+            // columns < v, so the rows on levels above those columns' levels
+            // stay constant; when their product is 0 in every lane all those
+            // terms are 0 and the interval reduces to one flip of column v - 1
+            // (the Gray codes at pos and pos + 2^v - 1 differ in that bit only),
+            // direction + when bit v of pos is 0.  Testing, at every position
+            // reached, the largest such interval that starts there (then
+            // smaller ones) visits the dyadic intervals of the chunk depth
+            // first and prunes every all-zero one.  ptop(v) = highest level
+            // columns < v touch grows with v, and S_l == 0 implies S_l' == 0
+            // for l' < l, so the intervals are tried per distinct level.
+            struct Group {
+                int level, lo, hi;
+            };
+            std::vector<Group> groups;  // level descending
+            if (p.zero_skip && u + 2 <= kappa - 1) {
+                int pt = 0;
+                for (int j = 0; j < u + 1; ++j) pt = std::max(pt, p.col_top[j]);
+                std::vector<int> lev(kappa, 0);
+                for (int v = u + 2; v <= kappa - 1; ++v) {
+                    pt = std::max(pt, p.col_top[v - 1]);
+                    lev[v] = pt + 1;
                 }
-                for (int l = block_top; l >= 1; --l) refresh_level(l, cur, "      ");
-                os << "    } else {\n";
-            }
-            os << "    ev += " << (2 * U - 1) << "u;\n";
-            static_block(false, "    ");
-            if (u + 1 == kappa) {
-                step(u, Sign::Lane, term_u, 0, "    ");
-            } else {
-                os << "    {\n      const bool neg = (base >> " << (u + 1) << ") & 1u;\n";
-                step(u, Sign::Uniform, term_u, 0, "      ");
-                os << "    }\n";
-            }
-            static_block(true, "    ");
-            if (skip_block) os << "    }\n";
-            // local step base + 2^(u+1): column jj = ctz >= u + 1, the same in
-            // every lane.  Branch-free: for each row that one of these columns
-            // touches, a scalar select picks that column's entry (0 when row r
-            // is not in column jj), one FMA applies it with the step's
-            // direction, then every level these columns can reach is refreshed.
-            if (u + 1 <= kappa - 1) {
-                const Ccs &B = p.B;
-                int top_max = 0;
-                std::map<int, std::vector<std::pair<int, double>>> rows;  // row -> (column, value)
-                for (int j = u + 1; j <= kappa - 1; ++j) {
-                    top_max = std::max(top_max, p.col_top[j]);
-                    for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) rows[B.rowidx[q]].push_back({j, B.val[q]});
+                for (int v = kappa - 1; v >= u + 2; --v) {
+                    if (lev[v] > L - 1) continue;
+                    if (!groups.empty() && groups.back().level == lev[v])
+                        groups.back().lo = v;
+                    else
+                        groups.push_back(Group{lev[v], v, v});
                 }
-                // The last iteration reaches ell = 2^kappa, which is not a step of
-                // this chunk: no column matches jj = kappa there, and the weight w
-                // = 0 drops its term.  (A branch here instead makes the compiler
-                // restructure the loop at a large cost in registers.)
-                os << "    const u32 ell = base + " << 2 * U << "u;\n";
-                os << "    {\n";
-                os << "      const double w = (ell < " << DELTA << "u) ? 1.0 : 0.0;\n";
-                os << "      const int jj = __builtin_ctz(ell);\n";
-                os << "      const double sgu = ((ell >> (jj + 1)) & 1u) ? -1.0 : 1.0;\n";
-                os << "      const double sg = (jj == " << kappa - 1 << ") ? lsgn : sgu;\n";
-                std::map<int, std::string> cur;
-                for (auto &rv : rows) {
-                    const int r = rv.first;
-                    std::string sel = "0.0";
-                    for (auto it = rv.second.rbegin(); it != rv.second.rend(); ++it)
-                        sel = "(jj == " + std::to_string(it->first) + " ? " + lit(it->second) + " : " + sel + ")";
-                    std::string target;
-                    if (r < p.k) {
-                        target = xname(r);
+            }
+            const bool tree = !groups.empty();
+            auto block_pair = [&](const char *posv, const char *ind) {
+                std::string in2 = std::string(ind) + "  ";
+                if (skip_block) {
+                    os << ind << "if (__all(S" << block_top + 1 << " == 0.0)) {\n";
+                    std::map<int, std::string> cur;
+                    if (u + 1 == kappa) {
+                        update(u, Sign::Lane, cur, in2.c_str());
                     } else {
-                        target = fresh();
-                        os << "      double " << target << " = " << cold_addr(r) << ";\n";
-                        cur[r] = target;
+                        os << in2 << "const bool neg = (" << posv << " >> " << (u + 1) << ") & 1u;\n";
+                        update(u, Sign::Uniform, cur, in2.c_str());
                     }
-                    os << "      " << target << " = fma(sg, " << sel << ", " << target << ");\n";
-                    if (r >= p.k) os << "      " << cold_addr(r) << " = " << target << ";\n";
+                    for (int l = block_top; l >= 1; --l) refresh_level(l, cur, in2.c_str());
+                    os << ind << "} else {\n";
                 }
-                for (int l = top_max; l >= 1; --l) refresh_level(l, cur, "      ");
-                accumulate(1, 1, cur, "      ", "w");
+                const char *bi = skip_block ? in2.c_str() : ind;
+                os << bi << "ev += " << (2 * U - 1) << "u;\n";
+                static_block(false, bi);
+                if (u + 1 == kappa) {
+                    step(u, Sign::Lane, term_u, 0, bi);
+                } else {
+                    os << bi << "{\n" << bi << "  const bool neg = (" << posv << " >> " << (u + 1) << ") & 1u;\n";
+                    step(u, Sign::Uniform, term_u, 0, (std::string(bi) + "  ").c_str());
+                    os << bi << "}\n";
+                }
+                static_block(true, bi);
+                if (skip_block) os << ind << "}\n";
+            };
+            // local step ell (a multiple of 2^(u+1)): column jj = ctz(ell) >= u + 1,
+            // the same in every lane, flipped branch-free by scalar selects, then
+            // every level these columns can reach is refreshed.  At ell =
+            // 2^kappa (not a step of this chunk) no column matches and the
+            // weight w = 0 drops the term.  (A branch there instead makes the
+            // compiler restructure the loop at a large cost in registers.)
+            auto dynamic_step = [&](const char *ellv, const char *ind) {
+                std::string in2 = std::string(ind) + "  ";
+                const char *I2 = in2.c_str();
+                os << ind << "{\n";
+                os << I2 << "const double w = (" << ellv << " < " << DELTA << "u) ? 1.0 : 0.0;\n";
+                os << I2 << "const int jj = __builtin_ctz(" << ellv << ");\n";
+                os << I2 << "const double sgu = ((" << ellv << " >> (jj + 1)) & 1u) ? -1.0 : 1.0;\n";
+                os << I2 << "const double sg = (jj == " << kappa - 1 << ") ? lsgn : sgu;\n";
+                std::map<int, std::string> cur;
+                const int top_max = dyn_flip("jj", "sg", u + 1, kappa - 1, cur, I2);
+                for (int l = top_max; l >= 1; --l) refresh_level(l, cur, I2);
+                accumulate(1, 1, cur, I2, "w");
+                os << ind << "}\n";
+            };
+            if (!tree) {
+                os << "#pragma clang loop unroll(disable)\n";
+                os << "  for (u32 base = 0; base < " << DELTA << "u; base += " << 2 * U << "u) {\n";
+                block_pair("base", "    ");
+                if (u + 1 <= kappa - 1) {
+                    os << "    const u32 ell = base + " << 2 * U << "u;\n";
+                    dynamic_step("ell", "    ");
+                }
+                os << "  }\n";
+                os << "  ev += " << (DELTA / (2 * U) - 1) << "u;  // the dynamic steps\n";
+            } else {
+                // pos: the local index whose term was added last (a multiple of 2^(u+1))
+                os << "  u32 pos = 0u;\n";
+                os << "#pragma clang loop unroll(disable)\n";
+                os << "  do {\n";
+                os << "    u32 vs = 0u;\n";
+                os << "    {\n";
+                os << "      const u32 v = (pos == 0u) ? " << kappa - 1 << "u : (u32)__builtin_ctz(pos);\n";
+                for (size_t gi = 0; gi < groups.size(); ++gi) {
+                    const Group &g = groups[gi];
+                    os << "      " << (gi ? "else " : "") << "if (v >= " << g.lo << "u && __all(S" << g.level
+                       << " == 0.0)) vs = (v < " << g.hi << "u) ? v : " << g.hi << "u;\n";
+                }
                 os << "    }\n";
+                // vs is the same in every lane; saying so keeps pos and what
+                // depends on it in scalar registers
+                os << "    vs = __builtin_amdgcn_readfirstlane(vs);\n";
+                os << "    if (vs == 0u) {\n";
+                block_pair("pos", "      ");
+                os << "    }\n";
+                // net flip of a skipped interval (column vs - 1, none when vs = 0:
+                // no select matches and x is unchanged); straight-line code, so
+                // the two paths do not each keep a copy of x.  The cached
+                // products are refreshed by the dynamic step that follows.
+                os << "    {\n";
+                os << "      const u32 jn = vs - 1u;\n";
+                os << "      const double sn = ((pos >> vs) & 1u) ? -1.0 : 1.0;\n";
+                {
+                    std::map<int, std::string> cur;
+                    dyn_flip("jn", "sn", u + 1, kappa - 2, cur, "      ");
+                }
+                os << "    }\n";
+                os << "    pos += (vs == 0u) ? " << 2 * U << "u : (1u << vs);\n";
+                dynamic_step("pos", "    ");
+                os << "    ev += (pos < " << DELTA << "u) ? 1u : 0u;\n";
+                os << "  } while (pos < " << DELTA << "u);\n";
             }
-            os << "  }\n";
-            os << "  ev += " << (DELTA / (2 * U) - 1) << "u;  // the dynamic steps\n";
             if (skip_chunk) os << "  }\n";
         }
         os << "  return two_sum(acc0, acc1);\n}\n";

@@ -289,15 +289,18 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
     bo.kappa_shift = o.batch_kappa_shift;
     std::vector<PreparedMatrix> prep(count);
     std::string err;
-    double steps = 0.0;
+    double steps = 0.0, ops = 0.0, fmas = 0.0;
     int singular = 0;
     for (int32_t i = 0; i < count; ++i) {
         perm_status s = prepare_batch_matrix(&mats[i], bo, &prep[i], &err);
         if (s != PERM_OK) return fail(s, "matrix " + std::to_string(i) + ": " + err);
-        if (prep[i].singular)
+        if (prep[i].singular) {
             ++singular;
-        else
+        } else {
             steps += std::ldexp(1.0, prep[i].n - 1);
+            ops += prep[i].fp64_ops;
+            fmas += prep[i].fp64_fmas;
+        }
     }
     auto t1 = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> g(g_mu);
@@ -334,6 +337,8 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
         st->count = count;
         st->singular = singular;
         st->launches = launches;
+        st->fp64_ops = ops;
+        st->flops = ops + fmas;
     }
     return PERM_OK;
 }

@@ -56,7 +56,8 @@ class PermOpts(ctypes.Structure):
 class PermBatchStats(ctypes.Structure):
     _fields_ = [("wall_ms", ctypes.c_double), ("prep_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("steps", ctypes.c_double), ("count", ctypes.c_int32), ("singular", ctypes.c_int32),
-                ("launches", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("launches", ctypes.c_int32), ("pad", ctypes.c_int32), ("fp64_ops", ctypes.c_double),
+                ("flops", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}

@@ -17,3 +17,5 @@ static inline double __shfl_xor(double v, int, int) { return v; }
 // one emulated lane is the whole "wave"
 static inline int __all(int p) { return p; }
 using std::fma;
+// a one-lane wave: the first lane's value is the value
+static inline unsigned __builtin_amdgcn_readfirstlane(unsigned v) { return v; }

@@ -210,7 +210,7 @@ def _emulate(P, ccs, **opts):
     f = os.path.join(d, "g.cpp")
     with open(f, "w") as fh:
         fh.write(src + '\nextern "C" void cpu_lane(u64 m, double* xg, u64 xs, u64 lid, double* o)'
-                 ' { u32 ev = 0; dd r = perm_lane(m, xg, xs, lid, ev); o[0] = r.h; o[1] = r.l; }\n')
+                 ' { u32 ev = 0; dd r = perm_lane(m, xg, xs, lid, ev); o[0] = r.h; o[1] = r.l; o[2] = ev; }\n')
     so = os.path.join(d, "g.so")
     subprocess.run(["g++", "-O1", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-include", SHIM,
                     "-o", so, f], check=True)
@@ -218,11 +218,13 @@ def _emulate(P, ccs, **opts):
     lib.cpu_lane.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
     n = ccs[0]
     xg = np.zeros(max(1, n), np.float64)
-    o = np.zeros(2)
+    o = np.zeros(3)
     tot = 0.0
+    info["evaluated"] = 0
     for m in range(info["nchunks"]):
         lib.cpu_lane(m, xg.ctypes.data, 1, 0, o.ctypes.data)
         tot += o[0] + o[1]
+        info["evaluated"] += int(o[2])
     return tot * (2.0 if n % 2 else -2.0), info
 
 
@@ -240,6 +242,36 @@ def test_generated_code_on_cpu_matches_oracle(P, oracle_mod):
             for zs in (True, False):
                 got, info = _emulate(P, ccs, mode=mode, chunk_log2=kappa, unroll_log2=u, zero_skip=zs)
                 assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12, (ccs[0], mode, kappa, u, zs, got, ref)
+
+
+def _nonzero_terms(ccs, fixed):
+    """Number of subsets S of the columns other than `fixed` whose Ryser/NW
+    product prod_i (a_i,fixed - rowsum_i / 2 + sum_{j in S} a_ij) is nonzero
+    (brute force; exact for 0/1 entries)."""
+    n, cp, ri, v = ccs
+    A = np.zeros((n, n))
+    for j in range(n):
+        A[ri[cp[j]:cp[j + 1]], j] = v[cp[j]:cp[j + 1]]
+    others = [j for j in range(n) if j != fixed]
+    x0 = A[:, fixed] - A.sum(axis=1) / 2
+    bits = (np.arange(1 << (n - 1))[:, None] >> np.arange(n - 1)[None, :]) & 1
+    X = x0[None, :] + bits @ A[:, others].T
+    return int((X != 0).all(axis=1).sum())
+
+
+def test_zero_skip_prunes_only_zero_terms(P):
+    """With zero-aware skipping the generated code evaluates every nonzero term
+    (the count of evaluated terms is at least the brute-force count of nonzero
+    ones) and prunes whole intervals (far fewer than 2^(n-1) evaluated)."""
+    for ccs, kappa, u in ((W.single_01(18, 0.12, 5), 9, 3), (W.single_01(20, 0.1, 6), 12, 4),
+                          (W.single_01(16, 0.2, 2), 11, 2)):
+        n = ccs[0]
+        fixed = int(P.perm_plan(ccs)["col_perm"][-1])
+        nz = _nonzero_terms(ccs, fixed)
+        _, on = _emulate(P, ccs, chunk_log2=kappa, unroll_log2=u, zero_skip=True)
+        _, off = _emulate(P, ccs, chunk_log2=kappa, unroll_log2=u, zero_skip=False)
+        assert off["evaluated"] == 1 << (n - 1)
+        assert nz <= on["evaluated"] < (1 << (n - 1)) // 4, (n, nz, on["evaluated"])
 
 
 def test_generated_code_tiny_n_on_cpu(P, oracle_mod):
