@@ -164,6 +164,46 @@ def serving_bench(duration_s=20.0, rate_hz=200.0, seed=1, compare_fifo=True, rou
     return out
 
 
+# The paper's Table 3 (A100, seconds per permanent), for context only: another
+# machine, another code base.  Keys (n, 10 p).
+PAPER_TABLE3_CODEGEN_HYBRID = {
+    (40, 1): 3.18, (40, 2): 3.94, (40, 3): 4.77, (40, 4): 5.96, (40, 5): 6.51,
+    (45, 1): 92.06, (45, 2): 93.69, (45, 3): 155.28, (45, 4): 196.25, (45, 5): 251.07,
+    (48, 1): 741.59, (48, 2): 1059.77, (48, 3): 1361.69, (48, 4): 1906.64, (48, 5): 2023.94}
+
+
+def er_grid_bench(ns, variants, seed=1):
+    """The paper's synthetic grid: one permanent per cell and kernel variant.
+    The code is matrix-specific, so each call includes its hipRTC compile;
+    the kernel time (HIP events) and the compile time are reported apart."""
+    import paper_2501_15126_amd.perm as P
+    from paper_2501_15126_amd import workloads as W
+    rows = []
+    for n, p in W.ER_GRID:
+        if n not in ns:
+            continue
+        ccs = W.er_grid_matrix(n, p, seed)
+        for var in variants:
+            mode, tier = {"auto": ("auto", "global"), "hybrid": ("hybrid", "global"),
+                          "hybrid-lds": ("hybrid", "lds")}[var]
+            t0 = time.perf_counter()
+            v, st = P.perm_sparse_ex(ccs, mode=mode, cold_tier=tier)
+            wall = time.perf_counter() - t0
+            steps = 2.0 ** (n - 1)
+            ks = st["kernel_ms"] / 1e3
+            row = {"n": n, "p": p, "variant": var, "nnz": len(ccs[2]), "permanent": v, "kernel_s": ks,
+                   "wall_s": wall, "compile_s": st["compile_ms"] / 1e3, "steps_per_s": steps / ks,
+                   "fp64_ops_per_step": st["ops_per_step"],
+                   "fp64_issue_frac": st["ops_per_step"] * steps / ks / 3.93216e13,
+                   "tflops": st["flops_per_step"] * steps / ks / 1e12, "vgprs": st["vgprs"],
+                   "waves_per_simd": st["waves_per_simd"], "lds_bytes": st["lds_bytes"], "k": st["k"],
+                   "levels": st["levels"],
+                   "paper_codegen_hybrid_a100_s": PAPER_TABLE3_CODEGEN_HYBRID[(n, int(round(10 * p)))]}
+            print("grid cell n=%d p=%.1f %s: %.3f s kernel" % (n, p, var, ks), file=sys.stderr, flush=True)
+            rows.append(row)
+    return rows
+
+
 def measured_traffic(src):
     """HBM bytes per dispatch of this exact generated kernel, from the committed
     rocprofv3 counter summary (None when the kernel source has changed)."""
@@ -191,8 +231,14 @@ def main():
     ap.add_argument("--zero-skip", default="auto", choices=["auto", "on", "off"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch-workload measurement")
+    ap.add_argument("--no-unpruned", action="store_true",
+                    help="skip the context run of the same permanent with zero-aware skipping off")
     ap.add_argument("--serving-seconds", type=float, default=20.0,
                     help="length of the Poisson serving run (0 skips it)")
+    ap.add_argument("--grid", default="",
+                    help="run only the paper's synthetic grid for these n (comma list, e.g. 40,45,48)")
+    ap.add_argument("--grid-variants", default="auto",
+                    help="kernel variants for --grid: auto, hybrid, hybrid-lds (comma list)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batch-workload measurement (for profiling the batch kernels)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -215,6 +261,12 @@ def main():
     import paper_2501_15126_amd.perm as P
     from paper_2501_15126_amd import workloads as W
 
+    if args.grid:
+        ns = [int(x) for x in args.grid.split(",")]
+        rows = er_grid_bench(ns, args.grid_variants.split(","), seed=args.seed)
+        print(json.dumps({"er_grid": rows, "workload": "Erdos-Renyi n in %s, p in 0.1..0.5, U[0,1], seed %d"
+                          % (ns, args.seed)}), flush=True)
+        return
     if args.batch_only:
         print(json.dumps({"batch": batch_bench(reps=2, sequential=False)}), flush=True)
         return
@@ -278,7 +330,7 @@ def main():
         "permanent": values[-1],
         "deterministic": all(x == values[0] for x in values),
     }
-    if zs is not False:
+    if zs is not False and not args.no_unpruned:
         # context: the same permanent with every term evaluated (pruning off)
         P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=False)
         ks = []

@@ -83,8 +83,9 @@ typedef struct {
     int32_t force_k;       /* > 0: override Alg. 5's k (HYBRID only), with force_c */
     int32_t force_c;       /* > 0: override Alg. 5's c (HYBRID only) */
     int32_t max_levels;    /* > 0: cap on cached product levels (AUTO); 0 = budget-driven */
-    int32_t zero_skip;     /* zero-aware skipping (exact): a wave skips a chunk, or a
-                              block of 2^(u+1) - 1 steps, whose terms all contain a
+    int32_t zero_skip;     /* zero-aware skipping (exact): a wave skips a chunk, a
+                              block of 2^(u+1) - 1 steps or any aligned power-of-two
+                              interval of Gray indices whose terms all contain a
                               factor that is exactly 0 in every lane.  0 = auto (on
                               when every value is an integer, where such zeros are
                               common), 1 = on, -1 = off */
@@ -95,6 +96,10 @@ typedef struct {
                               after each (the sequential baseline); 3 = the launches of
                               0 on one stream */
     int32_t batch_kappa_shift; /* perm_batch: added to the default chunk log2 */
+    int32_t cold_tier;     /* HYBRID: where rows >= k live; 0 = global memory (the paper's
+                              scheme), 1 = LDS, [row][lane] per workgroup (the block is
+                              then chosen so that a workgroup's rows fit 40 KiB, four
+                              workgroups per CU) */
     double gr_ratio;       /* Alg. 5 global/register update cost ratio; 0 = 16 */
     void *hip_stream;      /* hipStream_t to launch on; NULL = the library's stream */
     /* Optional host output: per-workgroup partial sums of the Gray-term sum

@@ -17,15 +17,16 @@
 //    the next chunk's start and is never executed inside a chunk.
 //  * The loop body is a static unrolled block of 2^u steps whose columns and
 //    signs are compile-time constants, followed by one wave-uniform dynamic
-//    step (a scalar switch on ctz).
+//    step whose column ctz(l) selects a row of a constant table of entries.
 //  * Products are cached by level (a generalisation of Sec. V's cached
 //    global product, Listings 4-5): rows are grouped by the first flipped
 //    column that touches them, S_l = product of x over levels >= l is kept,
 //    and a flip of column j recomputes only the levels up to the highest
 //    level column j touches.  With one level this is the plain full product.
 //  * Rows >= k (HYBRID) live in global memory, [row][lane] so that a wave's
-//    accesses are contiguous (Sec. V), and their product is recomputed only
-//    when a column that touches them flips.
+//    accesses are contiguous (Sec. V), or in LDS with the same layout per
+//    workgroup (the shared-memory tier the paper leaves to future work), and
+//    their product is recomputed only when a column that touches them flips.
 #include <cstdio>
 #include <map>
 #include <sstream>
@@ -60,6 +61,7 @@ struct Gen {
     std::string fresh() { return "t" + std::to_string(tmp++); }
     std::string xname(int r) const { return "x" + std::to_string(r); }
     std::string cold_addr(int r) const {
+        if (p.cold_lds) return "xl[" + std::to_string((r - p.k) * p.block) + " + threadIdx.x]";
         return "xg[(u64)" + std::to_string(r - p.k) + " * xs + lid]";
     }
 
@@ -166,26 +168,50 @@ struct Gen {
            << ");\n";
     }
 
-    // Branch-free flip of the wave-uniform column `jvar` (one of columns
-    // jlo..jhi, else no column) with direction `svar`: for each row one of
-    // these columns touches, a scalar select picks that column's entry (0
-    // when the row is not in column jvar) and one FMA applies it.  Returns
-    // the highest level the columns touch.
-    int dyn_flip(const char *jvar, const char *svar, int jlo, int jhi, std::map<int, std::string> &cur,
-                 const char *I) {
+    // Rows that the dynamic columns u+1 .. kappa-1 touch, and the table of
+    // their entries: row (jj - (u+1)) holds column jj's value for each of
+    // those rows (0 where the column has no entry); row kappa - u - 1 (jj =
+    // kappa, "no column") is all zeros.  Emitted as a __constant__ array, so a
+    // wave-uniform jj reads it with scalar loads.
+    std::vector<int> dyn_rows;
+    int dyn_lo = 0, dyn_hi = -1;  // columns in the table
+
+    void build_dyn_table(int lo, int hi) {
         const Ccs &B = p.B;
+        dyn_lo = lo;
+        dyn_hi = hi;
+        std::vector<char> used(p.n, 0);
+        for (int j = lo; j <= hi; ++j)
+            for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) used[B.rowidx[q]] = 1;
+        dyn_rows.clear();
+        for (int r = 0; r < p.n; ++r)
+            if (used[r]) dyn_rows.push_back(r);
+        if (dyn_rows.empty()) return;
+        const size_t R = dyn_rows.size();
+        std::vector<double> tab((size_t)(hi - lo + 2) * R, 0.0);
+        std::vector<int> slot(p.n, -1);
+        for (size_t i = 0; i < R; ++i) slot[dyn_rows[i]] = (int)i;
+        for (int j = lo; j <= hi; ++j)
+            for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q)
+                tab[(size_t)(j - lo) * R + slot[B.rowidx[q]]] = B.val[q];
+        os << "__constant__ double dyn_tab[" << tab.size() << "] = {";
+        for (size_t i = 0; i < tab.size(); ++i) os << (i ? "," : "") << (i % 8 ? " " : "\n  ") << lit(tab[i]);
+        os << "};\n";
+    }
+
+    // Flip of the wave-uniform column `jvar` (one of the table's columns, or
+    // dyn_hi + 1 for none) with direction `svar`: each row the table covers
+    // takes one FMA with its entry (0 leaves x unchanged).  Returns the
+    // highest level the table's columns touch.
+    int dyn_flip(const char *jvar, const char *svar, std::map<int, std::string> &cur, const char *I) {
         int top_max = 0;
-        std::map<int, std::vector<std::pair<int, double>>> rows;  // row -> (column, value)
-        for (int j = jlo; j <= jhi; ++j) {
-            top_max = std::max(top_max, p.col_top[j]);
-            for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) rows[B.rowidx[q]].push_back({j, B.val[q]});
-        }
-        for (auto &rv : rows) {
-            const int r = rv.first;
-            std::string sel = "0.0";
-            for (auto it = rv.second.rbegin(); it != rv.second.rend(); ++it)
-                sel = "(" + std::string(jvar) + " == " + std::to_string(it->first) + " ? " + lit(it->second) + " : " +
-                      sel + ")";
+        for (int j = dyn_lo; j <= dyn_hi; ++j) top_max = std::max(top_max, p.col_top[j]);
+        if (dyn_rows.empty()) return top_max;
+        const size_t R = dyn_rows.size();
+        const std::string tp = fresh();
+        os << I << "const double* " << tp << " = dyn_tab + (u32)(" << jvar << " - " << dyn_lo << ") * " << R << "u;\n";
+        for (size_t i = 0; i < R; ++i) {
+            const int r = dyn_rows[i];
             std::string target;
             if (r < p.k) {
                 target = xname(r);
@@ -194,7 +220,7 @@ struct Gen {
                 os << I << "double " << target << " = " << cold_addr(r) << ";\n";
                 cur[r] = target;
             }
-            os << I << target << " = fma(" << svar << ", " << sel << ", " << target << ");\n";
+            os << I << target << " = fma(" << svar << ", " << tp << "[" << i << "], " << target << ");\n";
             if (r >= p.k) os << I << cold_addr(r) << " = " << target << ";\n";
         }
         return top_max;
@@ -236,6 +262,10 @@ struct Gen {
         // of this lane live at xg[(r - k) * xs + lid].
         // `ev` counts the terms whose product this lane actually evaluates
         // (skipped ones excluded), for the device-work statistics.
+        if (kappa >= 1 && u + 1 <= kappa - 1) build_dyn_table(u + 1, kappa - 1);
+        // LDS tier: the cold rows of a workgroup's lanes, [row][lane], so a
+        // wave's accesses to one row are 64 consecutive doubles
+        if (p.cold_lds) os << "__shared__ double xl[" << (n - k) * p.block << "];\n";
         os << "__device__ __forceinline__ dd perm_lane(const u64 m, double* __restrict__ xg, const u64 xs,\n"
               "                                        const u64 lid, u32 &ev) {\n";
         os << "  ev = 1u;\n";
@@ -352,10 +382,10 @@ struct Gen {
                 if (skip_block) os << ind << "}\n";
             };
             // local step ell (a multiple of 2^(u+1)): column jj = ctz(ell) >= u + 1,
-            // the same in every lane, flipped branch-free by scalar selects, then
-            // every level these columns can reach is refreshed.  At ell =
-            // 2^kappa (not a step of this chunk) no column matches and the
-            // weight w = 0 drops the term.  (A branch there instead makes the
+            // the same in every lane, flipped branch-free with its entries read
+            // from the constant table, then every level these columns can reach
+            // is refreshed.  At ell = 2^kappa (not a step of this chunk) the
+            // table row is zero and the weight w = 0 drops the term.  (A branch there instead makes the
             // compiler restructure the loop at a large cost in registers.)
             auto dynamic_step = [&](const char *ellv, const char *ind) {
                 std::string in2 = std::string(ind) + "  ";
@@ -366,7 +396,7 @@ struct Gen {
                 os << I2 << "const double sgu = ((" << ellv << " >> (jj + 1)) & 1u) ? -1.0 : 1.0;\n";
                 os << I2 << "const double sg = (jj == " << kappa - 1 << ") ? lsgn : sgu;\n";
                 std::map<int, std::string> cur;
-                const int top_max = dyn_flip("jj", "sg", u + 1, kappa - 1, cur, I2);
+                const int top_max = dyn_flip("jj", "sg", cur, I2);
                 for (int l = top_max; l >= 1; --l) refresh_level(l, cur, I2);
                 accumulate(1, 1, cur, I2, "w");
                 os << ind << "}\n";
@@ -401,16 +431,16 @@ struct Gen {
                 os << "    if (vs == 0u) {\n";
                 block_pair("pos", "      ");
                 os << "    }\n";
-                // net flip of a skipped interval (column vs - 1, none when vs = 0:
-                // no select matches and x is unchanged); straight-line code, so
+                // net flip of a skipped interval (column vs - 1; when vs = 0 the
+                // table's zero row, x unchanged); straight-line code, so
                 // the two paths do not each keep a copy of x.  The cached
                 // products are refreshed by the dynamic step that follows.
                 os << "    {\n";
-                os << "      const u32 jn = vs - 1u;\n";
+                os << "      const u32 jn = (vs == 0u) ? " << kappa << "u : vs - 1u;\n";
                 os << "      const double sn = ((pos >> vs) & 1u) ? -1.0 : 1.0;\n";
                 {
                     std::map<int, std::string> cur;
-                    dyn_flip("jn", "sn", u + 1, kappa - 2, cur, "      ");
+                    dyn_flip("jn", "sn", cur, "      ");
                 }
                 os << "    }\n";
                 os << "    pos += (vs == 0u) ? " << 2 * U << "u : (1u << vs);\n";

@@ -67,7 +67,8 @@ struct Plan {
     std::vector<int> lev_begin;         // size nlevels + 1, lev_begin[nlevels] = n
     std::vector<int> row_level;         // level of each ordered row
     std::vector<int> col_top;           // highest level touched by each flipped column
-    bool cold = false;                  // last level lives in global memory (rows >= k)
+    bool cold = false;                  // last level lives outside VGPRs (rows >= k)
+    bool cold_lds = false;              // ... in LDS ([row][lane] per workgroup), else global memory
     int kappa = 0;                      // chunk = 2^kappa Gray steps per lane
     int u = 0;                          // static unrolled block = 2^u steps
     int block = 256;

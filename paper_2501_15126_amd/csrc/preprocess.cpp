@@ -124,10 +124,13 @@ constexpr int kBaseVgprs = 28;
 int auto_kappa(int n) {
     const int total = n - 1;  // log2 of the number of Gray indices
     // about 2^21 lanes (8 resident rounds of the 4096 wave slots at 4 waves
-    // per SIMD), chunks of at least 2^8 steps, at most 2^22
+    // per SIMD), chunks of at least 2^8 steps and at most 2^18 (larger n gets
+    // more lanes instead, so that its launches can be kept short), and no more
+    // than 2^40 chunks
     int kappa = total - 21;
     kappa = std::max(kappa, std::min(total, 8));
-    kappa = std::min(kappa, 22);
+    kappa = std::min(kappa, 18);
+    kappa = std::max(kappa, total - 40);
     return kappa;
 }
 
@@ -202,7 +205,14 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         lev_begin = firsts;
         if (lev_begin.empty() || lev_begin[0] != 0) lev_begin.insert(lev_begin.begin(), 0);
         const int cold_levels = p->cold ? 1 : 0;
-        auto vgprs = [&](int nlev) { return 2 * k + 2 * (nlev + cold_levels - 1) + kBaseVgprs; };
+        // rows that no in-chunk column (index < kappa) touches are constant
+        // inside a chunk: once their level product is formed at the chunk
+        // start their registers are free, so only the other rows count
+        const int kap = o.chunk_log2 > 0 ? std::min(o.chunk_log2, std::max(n - 1, 0)) : auto_kappa(n);
+        int live_rows = 0;
+        for (int r = 0; r < k; ++r)
+            if (first[r] < kap) ++live_rows;
+        auto vgprs = [&](int nlev) { return 2 * live_rows + 2 * (nlev + cold_levels - 1) + kBaseVgprs; };
         int cap = o.max_levels > 0 ? o.max_levels : INT_MAX;
         while ((int)lev_begin.size() > 1 && ((int)lev_begin.size() > cap || vgprs((int)lev_begin.size()) > budget))
             lev_begin.pop_back();  // merge the two highest (least often touched) levels
@@ -263,6 +273,25 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
     }
     p->u = std::max(0, std::min(p->u, p->kappa - 1));
     p->block = o.block > 0 ? o.block : 256;
+    if (o.cold_tier < 0 || o.cold_tier > 1) {
+        *err = "cold_tier must be 0 (global memory) or 1 (LDS)";
+        return PERM_EINVAL;
+    }
+    p->cold_lds = p->cold && o.cold_tier == 1;
+    if (p->cold_lds) {
+        // [row][lane] doubles per workgroup: at most 40 KiB by default (four
+        // workgroups per CU in 160 KiB), at most 64 KiB when the block is given
+        const int64_t lane_bytes = 8 * (int64_t)(n - p->k);
+        if (o.block <= 0) {
+            int b = 256;
+            while (b > 64 && (int64_t)b * lane_bytes > 40960) b -= 64;
+            p->block = b;
+        }
+        if ((int64_t)p->block * lane_bytes > 65536) {
+            *err = "cold rows do not fit LDS at this block size";
+            return PERM_EINVAL;
+        }
+    }
     if (o.zero_skip > 0) {
         p->zero_skip = true;
     } else if (o.zero_skip < 0) {

@@ -36,9 +36,12 @@ perm_status fail(perm_status s, const std::string &msg) {
             return fail(PERM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
     } while (0)
 
-// Lanes per launch; larger jobs are split into several launches over
-// consecutive chunk ranges (each launch writes its own partials range).
+// Workgroups per launch; larger jobs are split into several launches over
+// consecutive chunk ranges (each launch writes its own partials range).  A
+// launch also covers at most 2^42 Gray steps (under 3 s even for dense
+// matrices), so no single dispatch runs for long.
 constexpr int64_t kMaxBlocksPerLaunch = 1 << 16;
+constexpr double kMaxStepsPerLaunch = 4398046511104.0;  // 2^42
 
 struct LoadedKernel {
     hipModule_t mod = nullptr;
@@ -206,13 +209,16 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
     const Plan &pl = p.plan;
     const int64_t nchunks = st.nchunks;
     const int64_t nblocks = st.nblocks;
-    const int64_t launch_blocks = std::min<int64_t>(nblocks, kMaxBlocksPerLaunch);
+    const double steps_per_block = std::ldexp((double)pl.block, pl.kappa);
+    const int64_t launch_blocks = std::max<int64_t>(
+        1, std::min<int64_t>(std::min<int64_t>(nblocks, kMaxBlocksPerLaunch),
+                             (int64_t)(kMaxStepsPerLaunch / steps_per_block)));
     s = ensure_buffer(&g_dev.partials, &g_dev.partials_cap, 2 * (size_t)nblocks);
     if (s != PERM_OK) return s;
     s = ensure_buffer(reinterpret_cast<double **>(&g_dev.counts), &g_dev.counts_cap, (size_t)nblocks);
     if (s != PERM_OK) return s;
     const uint64_t xs = (uint64_t)launch_blocks * pl.block;  // lanes of one launch
-    if (pl.cold) {
+    if (pl.cold && !pl.cold_lds) {
         s = ensure_buffer(&g_dev.xg, &g_dev.xg_cap, (size_t)(pl.n - pl.k) * xs);
         if (s != PERM_OK) return s;
     }

@@ -149,6 +149,16 @@ def erdos_renyi(n: int, p: float, seed: int):
             return _pattern_to_ccs(mask, rng.random(int(mask.sum())))
 
 
+# The paper's synthetic grid (Sec. VI-C, Table 3): n in {40, 45, 48}, p in
+# {0.1, ..., 0.5}, U[0,1] values, structurally nonsingular.
+ER_GRID = [(n, p) for n in (40, 45, 48) for p in (0.1, 0.2, 0.3, 0.4, 0.5)]
+
+
+def er_grid_matrix(n: int, p: float, seed: int = 1):
+    """Cell (n, p) of the grid; the generator is seeded with [seed, n, 10 p]."""
+    return erdos_renyi(n, p, [seed, n, int(round(10 * p))])
+
+
 # The single-matrix workloads at full size, keyed by a descriptive name.
 WORKLOADS = {
     "n24_p0.15_01": lambda seed=1: single_01(24, 0.15, seed),

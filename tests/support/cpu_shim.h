@@ -10,6 +10,7 @@
 #define __launch_bounds__(...)
 #define __restrict__
 #define __shared__ static
+#define __constant__ static const
 struct cpu_dim3 { unsigned x, y, z; };
 static cpu_dim3 threadIdx, blockIdx;
 static inline void __syncthreads() {}

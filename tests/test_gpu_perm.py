@@ -46,16 +46,17 @@ def test_device_and_resources(P, oracle_mod):
     print("vgprs", info["vgprs"], "levels", info["levels"], "occupancy", st["waves_per_simd"])
 
 
-@pytest.mark.parametrize("mode", ["auto", "pure", "hybrid"])
-def test_random_small_vs_oracle(P, oracle_mod, mode):
+@pytest.mark.parametrize("mode,tier", [("auto", "global"), ("pure", "global"), ("hybrid", "global"),
+                                       ("hybrid", "lds")])
+def test_random_small_vs_oracle(P, oracle_mod, mode, tier):
     O = oracle_mod
     rng = np.random.default_rng(123)
     for t in range(12):
         n = int(rng.integers(2, 19))
         kind = ("real", "signed", "01")[t % 3]
         ccs = W.random_sparse(n, float(rng.uniform(0.15, 0.5)), seed=1000 + t, kind=kind)
-        print("case", mode, t, n, kind, flush=True)
-        got, st = P.perm_sparse_ex(ccs, mode=mode)
+        print("case", mode, tier, t, n, kind, flush=True)
+        got, st = P.perm_sparse_ex(ccs, mode=mode, cold_tier=tier)
         if st["singular"]:
             assert got == 0.0
             assert O.structural_rank(ccs) < n
@@ -152,9 +153,9 @@ def test_n24_full_exact(P, oracle_mod):
     for seed in (1, 2, 3):
         rec = g["n24_p0.15_01:%d" % seed]
         ccs = W.single_01(24, 0.15, seed)
-        for mode in ("auto", "pure", "hybrid"):
-            got, st = P.perm_sparse_ex(ccs, mode=mode)
-            assert got == float(int(rec["perm_exact"])), (seed, mode, got)
+        for mode, tier in (("auto", "global"), ("pure", "global"), ("hybrid", "global"), ("hybrid", "lds")):
+            got, st = P.perm_sparse_ex(ccs, mode=mode, cold_tier=tier)
+            assert got == float(int(rec["perm_exact"])), (seed, mode, tier, got)
 
 
 def test_n24_block_partials_vs_oracle(P, oracle_mod):
@@ -173,6 +174,30 @@ def test_n24_block_partials_vs_oracle(P, oracle_mod):
         assert parts[b, 0] + parts[b, 1] == pytest.approx(h + l, rel=1e-12, abs=1e-9), b
 
 
+def test_er_grid_cell_block_partials_vs_oracle(P, oracle_mod):
+    """A full-size cell of the paper's synthetic grid (n=45, p=0.1, U[0,1]
+    values, the launch configuration the grid bench uses): sampled workgroup
+    partials against the oracle on the same Gray-index ranges, and the sum of
+    all partials against the returned permanent."""
+    import math
+    O = oracle_mod
+    n = 45
+    ccs = W.er_grid_matrix(n, 0.1)
+    got, st, parts = P.perm_sparse_ex(ccs, block_partials=True)
+    print("er45 kernel_ms", st["kernel_ms"], "nblocks", st["nblocks"], flush=True)
+    plan = P.perm_plan(ccs)
+    A = O.ccs_to_dense(ccs)
+    B = O.dense_to_ccs(A[np.ix_(plan["row_perm"], plan["col_perm"])])
+    W_ = st["block"] << st["chunk_log2"]
+    for b in (0, st["nblocks"] // 3, st["nblocks"] - 1):
+        (h, l), (ah, al) = O.nw_range(B, b * W_, min((b + 1) * W_, 1 << (n - 1)))
+        ref, abs_sum = h + l, ah + al
+        g = parts[b, 0] + parts[b, 1]
+        assert abs(g - ref) <= max(1e-9 * abs(ref), (2 * n + 2) * 2.0 ** -53 * abs_sum), (b, g, ref)
+    total = math.fsum(parts[:, 0]) + math.fsum(parts[:, 1])
+    assert total * 2.0 == pytest.approx(got, rel=1e-12)
+
+
 def test_n36_full_vs_oracle(P):
     g = _golden()
     key = "n36_p0.30_real:1"
@@ -181,9 +206,9 @@ def test_n36_full_vs_oracle(P):
     rec = g[key]
     ccs = W.single_real(36, 0.30, 1)
     ref = rec["perm_ld_hi"] + rec["perm_ld_lo"]
-    for mode in ("auto", "pure", "hybrid"):
-        got, st = P.perm_sparse_ex(ccs, mode=mode)
-        print("n36", mode, got, ref, abs(got - ref) / abs(ref), st["kernel_ms"])
+    for mode, tier in (("auto", "global"), ("pure", "global"), ("hybrid", "global"), ("hybrid", "lds")):
+        got, st = P.perm_sparse_ex(ccs, mode=mode, cold_tier=tier)
+        print("n36", mode, tier, got, ref, abs(got - ref) / abs(ref), st["kernel_ms"], st["lds_bytes"], flush=True)
         assert abs(got - ref) <= 1e-9 * abs(ref)
 
 

@@ -200,6 +200,12 @@ def test_codegen_resources_no_scratch(P):
             assert info["scratch_bytes"] == 0, (ccs[0], mode)
             assert info["vgprs"] <= 256
         assert P.compile_info(ccs)["vgprs"] <= 128
+        # the LDS tier: cold rows in LDS ([row][lane]), at most 40 KiB per workgroup
+        lds = P.compile_info(ccs, mode="hybrid", cold_tier="lds")
+        plan = P.perm_plan(ccs, mode="hybrid")
+        assert lds["scratch_bytes"] == 0
+        assert lds["lds_bytes"] >= 8 * (ccs[0] - plan["k"]) * lds["block"]
+        assert lds["lds_bytes"] <= 40960 + 1024
 
 
 def _emulate(P, ccs, **opts):
@@ -238,10 +244,10 @@ def test_generated_code_on_cpu_matches_oracle(P, oracle_mod):
     cases += [(W.single_01(18, 0.12, 5), 9, 3), (W.single_01(20, 0.1, 6), 12, 4)]
     for ccs, kappa, u in cases:
         ref, abs_sum = O.perm_nw(ccs)
-        for mode in ("auto", "pure", "hybrid"):
+        for mode, tier in (("auto", "global"), ("pure", "global"), ("hybrid", "global"), ("hybrid", "lds")):
             for zs in (True, False):
-                got, info = _emulate(P, ccs, mode=mode, chunk_log2=kappa, unroll_log2=u, zero_skip=zs)
-                assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12, (ccs[0], mode, kappa, u, zs, got, ref)
+                got, info = _emulate(P, ccs, mode=mode, chunk_log2=kappa, unroll_log2=u, zero_skip=zs, cold_tier=tier)
+                assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12, (ccs[0], mode, tier, kappa, u, zs, got, ref)
 
 
 def _nonzero_terms(ccs, fixed):
