@@ -29,7 +29,7 @@ METRIC = "Gray-code steps/s & % FP64 peak (n=40); batched permanents/s; p50/p99 
 FP64_PEAK_TFLOPS = 78.6  # MI355X published FP64 vector peak (an FMA counts 2)
 
 
-def cpu_baseline(ccs, seconds_target=15.0):
+def cpu_baseline(ccs, seconds_target=25.0):
     """The oracle (Alg. 1 in long double, all host cores) on a bounded prefix of
     the same Gray-index range; returns steps/s."""
     from oracle import oracle as O
@@ -43,13 +43,12 @@ def cpu_baseline(ccs, seconds_target=15.0):
     O.nw_range(ccs, 0, probe, threads)
     dt = max(time.perf_counter() - t0, 1e-3)
     steps = int(min(total, max(probe, probe * seconds_target / dt)))
-    steps = 1 << int(math.log2(steps))
     t0 = time.perf_counter()
     O.nw_range(ccs, 0, steps, threads)
     dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "Gray-code steps/s", "cores": threads, "kind": "oracle",
-            "sample": "Gray indices [0, 2^%d) of the same matrix (of 2^%d), long double Alg. 1, %.1f s"
-                      % (int(math.log2(steps)), n - 1, dt)}
+            "sample": "Gray indices [0, %d) = 2^%.2f of the same matrix (of 2^%d), long double Alg. 1, %.1f s"
+                      % (steps, math.log2(steps), n - 1, dt)}
 
 
 def batch_bench(seed=1, count=2000, reps=3, sequential=True):
@@ -187,7 +186,7 @@ def er_grid_bench(ns, variants, seed=1):
             mode, tier = {"auto": ("auto", "global"), "hybrid": ("hybrid", "global"),
                           "hybrid-lds": ("hybrid", "lds")}[var]
             t0 = time.perf_counter()
-            v, st = P.perm_sparse_ex(ccs, mode=mode, cold_tier=tier)
+            v, st = P.perm_sparse_ex(ccs, mode=mode, cold_tier=tier, progress=n >= 45)
             wall = time.perf_counter() - t0
             steps = 2.0 ** (n - 1)
             ks = st["kernel_ms"] / 1e3

@@ -108,6 +108,9 @@ typedef struct {
      * Filled only if the capacity (in workgroups) is large enough. */
     double *block_partials;
     int64_t block_partials_cap;
+    int32_t progress;      /* > 0: perm_sparse_ex prints one line to stderr as each of
+                              its launches (at most 2^42 Gray steps each) completes */
+    int32_t pad;
 } perm_opts;
 
 /* Statistics of one call (all optional to read). */

@@ -70,6 +70,17 @@ perm_status prepare_batch_matrix(const perm_csc *m, const BatchOptions &bo, Prep
     pm->base_index = (size_t)std::max(1, n - 1) * CS;
     pm->chunk_top = 0;
     for (int j = 0; j < std::min(pm->kappa, n - 1); ++j) pm->chunk_top = std::max(pm->chunk_top, pm->tops[j]);
+    // gv[v], v = 0..kappa, after the tops: 1 + the highest group columns < v
+    // touch (the lowest group constant over an interval of 2^v steps)
+    {
+        const size_t base = pm->tops.size();
+        pm->tops.resize(base + (size_t)pm->kappa + 1, 0);
+        int t = -1;
+        for (int v = 0; v <= pm->kappa; ++v) {
+            pm->tops[base + v] = t + 1;
+            if (v < n - 1) t = std::max(t, pm->tops[v]);
+        }
+    }
     if (bo.zero_skip > 0) {
         pm->zero_skip = true;
     } else if (bo.zero_skip < 0) {
@@ -207,6 +218,7 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
         if (!mats[i]->singular) order.push_back(i);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         if (mats[x]->ng != mats[y]->ng) return mats[x]->ng < mats[y]->ng;
+        if (mats[x]->zero_skip != mats[y]->zero_skip) return mats[y]->zero_skip;
         return mats[x]->n > mats[y]->n;
     });
     for (int i = 0; i < count; ++i)
@@ -237,9 +249,10 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
         nvals += pm.vals.size();
         ntops += pm.tops.size();
         const uint64_t items = (pm.nchunks + 63) / 64;
-        if (plans.empty() || plans.back().ng != pm.ng) {
+        if (plans.empty() || plans.back().ng != pm.ng || plans.back().zero_skip != pm.zero_skip) {
             plans.emplace_back();
             plans.back().ng = pm.ng;
+            plans.back().zero_skip = pm.zero_skip;
         }
         plans.back().add(k, 0, items, nparts);
         fin[k] = FinishDesc{nparts, items, pm.n, 0};
@@ -324,8 +337,8 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
                 if (!used[c]) HIP_OK(hipStreamWaitEvent(st, ev0, 0));
                 used[c] = true;
             }
-            HIP_OK(launch_batch_ranges(w.ng, d_ranges + r0, (int)w.ranges.size(), d_blk + b0, (int64_t)w.nwaves,
-                                       d_mats, d_vals, d_tops, d_partials, st));
+            HIP_OK(launch_batch_ranges(w.ng, w.zero_skip, d_ranges + r0, (int)w.ranges.size(), d_blk + b0,
+                                       (int64_t)w.nwaves, d_mats, d_vals, d_tops, d_partials, st));
             r0 += w.ranges.size();
             b0 += w.blk_first.size();
         }

@@ -19,10 +19,11 @@ namespace permx {
 
 // Launches the batch kernel for waves [0, nwaves) described by ranges[0,
 // nranges) (sorted by wave0, each non-empty, ranges[0].wave0 = 0) whose
-// matrices all have ng groups; blk_first[b] is the range holding wave 4b.
-hipError_t launch_batch_ranges(int ng, const BatchRange *ranges, int nranges, const int32_t *blk_first,
-                               int64_t nwaves, const BatchMat *mats, const double *vals, const int32_t *tops,
-                               double *partials, hipStream_t stream);
+// matrices all have ng groups and the same zero_skip; blk_first[b] is the
+// range holding wave 4b.
+hipError_t launch_batch_ranges(int ng, bool zero_skip, const BatchRange *ranges, int nranges,
+                               const int32_t *blk_first, int64_t nwaves, const BatchMat *mats, const double *vals,
+                               const int32_t *tops, double *partials, hipStream_t stream);
 
 // out[i] = (4 (n mod 2) - 2) * (partials of d[i], double-double, in an order
 // fixed by the partials' count), i = 0..count-1.

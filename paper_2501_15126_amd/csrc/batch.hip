@@ -33,7 +33,7 @@ constexpr int batch_waves_per_eu() {
     return NG == 8 ? 4 : 1;
 }
 
-template <int NG>
+template <int NG, bool ZS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<NG>()))) batch_kernel(const BatchRange *__restrict__ ranges, int nranges,
                                                     const int32_t *__restrict__ blk_first, long long nwaves,
                                                     const BatchMat *__restrict__ mats,
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_
     const u64 m0 = chunk0 + (u64)lane;
     const bool active = m0 < md.nchunks;
     const u64 m = active ? m0 : chunk0;  // inactive lanes replay a valid chunk and add nothing
-    dd cs = batch_lane<NG>(md, vals, tops_all, m);
+    dd cs = batch_lane<NG, ZS>(md, vals, tops_all, m);
     if (!active) {
         cs.h = 0.0;
         cs.l = 0.0;
@@ -114,19 +114,23 @@ __global__ void __launch_bounds__(256) batch_finish(const FinishDesc *__restrict
 }
 
 template <int NG>
-hipError_t launch_t(const BatchRange *ranges, int nranges, const int32_t *blk_first, int64_t nwaves,
+hipError_t launch_t(bool zs, const BatchRange *ranges, int nranges, const int32_t *blk_first, int64_t nwaves,
                     const BatchMat *mats, const double *vals, const int32_t *tops, double *partials,
                     hipStream_t stream) {
     const unsigned blocks = (unsigned)((nwaves + 3) / 4);
-    hipLaunchKernelGGL((batch_kernel<NG>), dim3(blocks), dim3(256), 0, stream, ranges, nranges, blk_first,
-                       (long long)nwaves, mats, vals, tops, partials);
+    if (zs)
+        hipLaunchKernelGGL((batch_kernel<NG, true>), dim3(blocks), dim3(256), 0, stream, ranges, nranges, blk_first,
+                           (long long)nwaves, mats, vals, tops, partials);
+    else
+        hipLaunchKernelGGL((batch_kernel<NG, false>), dim3(blocks), dim3(256), 0, stream, ranges, nranges,
+                           blk_first, (long long)nwaves, mats, vals, tops, partials);
     return hipGetLastError();
 }
 
 template <int NG>
 void attrs_t(int *vgprs, int *scratch) {
     hipFuncAttributes a;
-    if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&batch_kernel<NG>)) == hipSuccess) {
+    if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&batch_kernel<NG, false>)) == hipSuccess) {
         *vgprs = a.numRegs;
         *scratch = (int)a.localSizeBytes;
     }
@@ -136,14 +140,14 @@ void attrs_t(int *vgprs, int *scratch) {
 
 }  // namespace
 
-hipError_t launch_batch_ranges(int ng, const BatchRange *ranges, int nranges, const int32_t *blk_first,
-                               int64_t nwaves, const BatchMat *mats, const double *vals, const int32_t *tops,
-                               double *partials, hipStream_t stream) {
+hipError_t launch_batch_ranges(int ng, bool zero_skip, const BatchRange *ranges, int nranges,
+                               const int32_t *blk_first, int64_t nwaves, const BatchMat *mats, const double *vals,
+                               const int32_t *tops, double *partials, hipStream_t stream) {
     if (nwaves <= 0) return hipSuccess;
     if (nranges <= 0 || (nwaves + 3) / 4 > 0x7fffffff) return hipErrorInvalidValue;
 #define PERM_CASE(NGV) \
     case NGV:          \
-        return launch_t<NGV>(ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
+        return launch_t<NGV>(zero_skip, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
     switch (ng) {
         PERM_NG_TABLE(PERM_CASE)
         default:

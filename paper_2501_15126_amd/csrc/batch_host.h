@@ -39,6 +39,7 @@ perm_status prepare_batch_matrix(const perm_csc *m, const BatchOptions &bo, Prep
 // per-workgroup first-range table the kernel starts its search from.
 struct WavePlan {
     int ng = 0;
+    bool zero_skip = false;
     std::vector<BatchRange> ranges;
     std::vector<int32_t> blk_first;
     uint64_t nwaves = 0;

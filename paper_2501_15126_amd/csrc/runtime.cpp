@@ -62,6 +62,7 @@ struct DeviceState {
     unsigned long long *counts = nullptr;  // evaluated terms per workgroup
     size_t counts_cap = 0;
     double *out = nullptr;    // 2 doubles, then the evaluated-term total (u64)
+    double *host_out = nullptr;  // pinned host copy of out
     std::unordered_map<std::string, LoadedKernel> kernels;  // source -> module
 };
 
@@ -85,6 +86,7 @@ perm_status ensure_device() {
     HIP_TRY(hipStreamCreateWithFlags(&g_dev.stream, hipStreamNonBlocking));
     for (auto &ev : g_dev.ev) HIP_TRY(hipEventCreate(&ev));
     HIP_TRY(hipMalloc(&g_dev.out, 4 * sizeof(double)));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&g_dev.host_out), 4 * sizeof(double), hipHostMallocDefault));
     g_dev.ready = true;
     return PERM_OK;
 }
@@ -172,38 +174,94 @@ void fill_plan_stats(const Prepared &p, perm_stats *st) {
     st->nblocks = (st->nchunks + pl.block - 1) / pl.block;
 }
 
+// Plans and compiled code of recently seen inputs, keyed by the exact input
+// bytes and the options that shape the plan.  Validation, the matching,
+// Alg. 4/5 and the source text cost about 0.15 ms per call; a repeated call
+// with the same matrix skips them (the permanent itself is always computed
+// on the device).
+struct CachedPlan {
+    Prepared p;
+    CodeObject co;
+    LoadedKernel *kern = nullptr;  // set and read under g_mu
+};
+std::mutex g_plan_mu;
+std::unordered_map<std::string, std::shared_ptr<CachedPlan>> g_plan_cache;
+constexpr size_t kPlanCacheMax = 256;
+
+bool plan_key(const perm_csc *m, const perm_opts &o, std::string *key) {
+    if (!m || m->n < 0 || m->n > PERM_MAX_N || !m->colptr) return false;
+    const int32_t n = m->n;
+    const int32_t nnz = m->colptr[n];
+    if (nnz < 0 || (int64_t)nnz > (int64_t)n * n || (nnz > 0 && (!m->rowidx || !m->val))) return false;
+    key->clear();
+    auto put = [&](const void *q, size_t b) { key->append(static_cast<const char *>(q), b); };
+    put(&n, sizeof n);
+    put(m->colptr, sizeof(int32_t) * ((size_t)n + 1));
+    if (nnz > 0) {
+        put(m->rowidx, sizeof(int32_t) * (size_t)nnz);
+        put(m->val, sizeof(double) * (size_t)nnz);
+    }
+    const int32_t f[] = {o.mode,     o.chunk_log2, o.unroll_log2, o.block,     o.vgpr_budget,
+                         o.force_k,  o.force_c,    o.max_levels,  o.zero_skip, o.cold_tier};
+    put(f, sizeof f);
+    put(&o.gr_ratio, sizeof o.gr_ratio);
+    return true;
+}
+
 perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_stats *st_out) {
     auto t0 = std::chrono::steady_clock::now();
     perm_stats st;
     memset(&st, 0, sizeof st);
     const perm_opts o = defaults(opts);
-    Prepared p;
-    perm_status s = prepare(m, o, &p, true);
-    if (s != PERM_OK) return s;
+    std::string key;
+    const bool keyed = plan_key(m, o, &key);
+    std::shared_ptr<CachedPlan> cp;
+    if (keyed) {
+        std::lock_guard<std::mutex> g(g_plan_mu);
+        auto it = g_plan_cache.find(key);
+        if (it != g_plan_cache.end()) cp = it->second;
+    }
+    const bool plan_hit = cp != nullptr;
+    if (!cp) {
+        cp = std::make_shared<CachedPlan>();
+        perm_status s = prepare(m, o, &cp->p, true);
+        if (s != PERM_OK) return s;
+        if (!cp->p.singular) {
+            std::string err;
+            s = compile_source(cp->p.src, &cp->co, &err);
+            if (s != PERM_OK) return fail(s, err);
+        }
+        if (keyed) {
+            std::lock_guard<std::mutex> g(g_plan_mu);
+            if (g_plan_cache.size() >= kPlanCacheMax) g_plan_cache.clear();
+            g_plan_cache.emplace(key, cp);
+        }
+    }
+    const Prepared &p = cp->p;
+    const CodeObject &co = cp->co;
     fill_plan_stats(p, &st);
+    st.host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() -
+                 (plan_hit ? 0.0 : co.compile_ms);
     if (p.singular) {
         *out = 0.0;  // no perfect matching: every permutation product has a zero factor
         st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (st_out) *st_out = st;
         return PERM_OK;
     }
-    CodeObject co;
-    std::string err;
-    s = compile_source(p.src, &co, &err);
-    if (s != PERM_OK) return fail(s, err);
-    st.compile_ms = co.compile_ms;
-    st.cache_hit = co.cache_hit ? 1 : 0;
+    st.compile_ms = plan_hit ? 0.0 : co.compile_ms;
+    st.cache_hit = (plan_hit || co.cache_hit) ? 1 : 0;
     st.vgprs = co.vgprs;
     st.sgprs = co.sgprs;
     st.scratch_bytes = co.scratch_bytes;
     st.lds_bytes = co.lds_bytes;
-
     std::lock_guard<std::mutex> g(g_mu);
-    s = ensure_device();
+    perm_status s = ensure_device();
     if (s != PERM_OK) return s;
-    LoadedKernel *kern = nullptr;
-    s = load_kernel(p.src, co, p.plan.block, &kern);
-    if (s != PERM_OK) return s;
+    if (!cp->kern) {
+        s = load_kernel(p.src, co, p.plan.block, &cp->kern);
+        if (s != PERM_OK) return s;
+    }
+    LoadedKernel *kern = cp->kern;
     st.waves_per_simd = kern->waves_per_simd;
 
     const Plan &pl = p.plan;
@@ -224,6 +282,8 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
     }
     hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : g_dev.stream;
     HIP_TRY(hipEventRecord(g_dev.ev[0], stream));
+    const int64_t nlaunch = (nblocks + launch_blocks - 1) / launch_blocks;
+    std::vector<hipEvent_t> done;  // per launch, only with o.progress
     for (int64_t b0 = 0; b0 < nblocks; b0 += launch_blocks) {
         const int64_t nb = std::min<int64_t>(launch_blocks, nblocks - b0);
         uint64_t chunk_begin = (uint64_t)b0 * pl.block;
@@ -235,13 +295,31 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
         void *args[] = {&chunk_begin, &chunk_end, &part, &cnt, &xg, &xs_arg};
         HIP_TRY(hipModuleLaunchKernel(kern->fn, (unsigned)nb, 1, 1, (unsigned)pl.block, 1, 1, 0, stream, args,
                                       nullptr));
+        if (o.progress > 0 && nlaunch > 1) {
+            hipEvent_t e = nullptr;
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            done.push_back(e);
+            HIP_TRY(hipEventRecord(e, stream));
+        }
+    }
+    // all launches are queued; report each as it completes (the device never
+    // waits for the host here)
+    for (size_t i = 0; i < done.size(); ++i) {
+        const hipError_t e = hipEventSynchronize(done[i]);
+        fprintf(stderr, "perm: n=%d launch %zu of %lld done\n", pl.n, i + 1, (long long)nlaunch);
+        fflush(stderr);
+        (void)hipEventDestroy(done[i]);
+        if (e != hipSuccess) {
+            for (size_t j = i + 1; j < done.size(); ++j) (void)hipEventDestroy(done[j]);
+            return fail(PERM_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+        }
     }
     HIP_TRY(hipEventRecord(g_dev.ev[1], stream));
     unsigned long long *count_out = reinterpret_cast<unsigned long long *>(g_dev.out + 2);
     HIP_TRY(launch_final_reduce(g_dev.partials, g_dev.counts, (long long)nblocks, g_dev.out, count_out, stream));
     HIP_TRY(hipEventRecord(g_dev.ev[2], stream));
-    double hl[3];
-    HIP_TRY(hipMemcpyAsync(hl, g_dev.out, sizeof hl, hipMemcpyDeviceToHost, stream));
+    double *hl = g_dev.host_out;  // pinned: the 24-byte result copy is a plain DMA
+    HIP_TRY(hipMemcpyAsync(hl, g_dev.out, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
     if (o.block_partials && o.block_partials_cap >= nblocks)
         HIP_TRY(hipMemcpyAsync(o.block_partials, g_dev.partials, 2 * sizeof(double) * (size_t)nblocks,
                                hipMemcpyDeviceToHost, stream));

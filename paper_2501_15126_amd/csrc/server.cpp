@@ -278,8 +278,10 @@ bool perm_server::issue(Slot &slot, const std::vector<Request *> &newly, std::st
             if (r->pm.ng % kBatchStreams == c) up.push_back(r);
         if (takes[c].empty() && up.empty()) continue;
         // launches ordered by kernel instance, larger instances first
-        std::stable_sort(takes[c].begin(), takes[c].end(),
-                         [](const Take &x, const Take &y) { return x.r->pm.ng > y.r->pm.ng; });
+        std::stable_sort(takes[c].begin(), takes[c].end(), [](const Take &x, const Take &y) {
+            if (x.r->pm.ng != y.r->pm.ng) return x.r->pm.ng > y.r->pm.ng;
+            return x.r->pm.zero_skip && !y.r->pm.zero_skip;
+        });
         std::vector<BatchMat> mats;
         std::vector<WavePlan> plans;
         std::vector<FinishDesc> fin;
@@ -301,9 +303,10 @@ bool perm_server::issue(Slot &slot, const std::vector<Request *> &newly, std::st
             mats.push_back(d);
             const size_t tops_bytes = (pm.tops.size() * sizeof(int32_t) + kAlign - 1) / kAlign * kAlign;
             const uint64_t part0 = (r->arena_off + r->vals_bytes + tops_bytes) / (2 * sizeof(double));
-            if (plans.empty() || plans.back().ng != pm.ng) {
+            if (plans.empty() || plans.back().ng != pm.ng || plans.back().zero_skip != pm.zero_skip) {
                 plans.emplace_back();
                 plans.back().ng = pm.ng;
+                plans.back().zero_skip = pm.zero_skip;
             }
             plans.back().add(mi, r->next_item, t.items, part0 + r->next_item);
             r->next_item += t.items;
@@ -374,8 +377,8 @@ bool perm_server::issue(Slot &slot, const std::vector<Request *> &newly, std::st
             }
             size_t r0 = 0, b0 = 0;
             for (const WavePlan &w : plans) {
-                SRV_HIP(launch_batch_ranges(w.ng, cb.d_ranges + r0, (int)w.ranges.size(), cb.d_blk + b0,
-                                            (int64_t)w.nwaves, cb.d_mats, vals, tops, parts, st));
+                SRV_HIP(launch_batch_ranges(w.ng, w.zero_skip, cb.d_ranges + r0, (int)w.ranges.size(),
+                                            cb.d_blk + b0, (int64_t)w.nwaves, cb.d_mats, vals, tops, parts, st));
                 r0 += w.ranges.size();
                 b0 += w.blk_first.size();
             }

@@ -9,7 +9,7 @@ using namespace permx::batch_detail;
 
 template <int NG>
 static dd run(const BatchMat &md, const double *vals, const int32_t *tops, u64 m) {
-    return batch_lane<NG>(md, vals, tops, m);
+    return md.zero_skip ? batch_lane<NG, true>(md, vals, tops, m) : batch_lane<NG, false>(md, vals, tops, m);
 }
 
 extern "C" int cpu_batch_lane(const int32_t *desc, const double *vals, size_t nvals, const int32_t *tops, u64 m,

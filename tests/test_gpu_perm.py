@@ -140,11 +140,19 @@ def test_invalid_inputs_raise(P):
 
 
 def test_determinism(P):
+    """Repeated calls give identical bits; repeats reuse the cached plan and
+    code (no compile) but run the kernel again; a changed value is a new plan."""
     ccs = W.random_sparse(22, 0.3, seed=9, kind="signed")
     a, _ = P.perm_sparse_ex(ccs)
-    b, _ = P.perm_sparse_ex(ccs)
-    c, _ = P.perm_sparse_ex(ccs)
+    b, sb = P.perm_sparse_ex(ccs)
+    c, sc = P.perm_sparse_ex(ccs)
     assert a == b == c
+    assert sb["cache_hit"] == 1 and sb["compile_ms"] == 0.0 and sb["kernel_ms"] > 0.0
+    n, cp, ri, v = ccs
+    v2 = v.copy()
+    v2[0] *= 2.0
+    d, sd = P.perm_sparse_ex((n, cp, ri, v2))
+    assert d != a
 
 
 def test_n24_full_exact(P, oracle_mod):
