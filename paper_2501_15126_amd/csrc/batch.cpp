@@ -70,17 +70,6 @@ perm_status prepare_batch_matrix(const perm_csc *m, const BatchOptions &bo, Prep
     pm->base_index = (size_t)std::max(1, n - 1) * CS;
     pm->chunk_top = 0;
     for (int j = 0; j < std::min(pm->kappa, n - 1); ++j) pm->chunk_top = std::max(pm->chunk_top, pm->tops[j]);
-    // gv[v], v = 0..kappa, after the tops: 1 + the highest group columns < v
-    // touch (the lowest group constant over an interval of 2^v steps)
-    {
-        const size_t base = pm->tops.size();
-        pm->tops.resize(base + (size_t)pm->kappa + 1, 0);
-        int t = -1;
-        for (int v = 0; v <= pm->kappa; ++v) {
-            pm->tops[base + v] = t + 1;
-            if (v < n - 1) t = std::max(t, pm->tops[v]);
-        }
-    }
     if (bo.zero_skip > 0) {
         pm->zero_skip = true;
     } else if (bo.zero_skip < 0) {

@@ -106,8 +106,10 @@ __device__ __forceinline__ double suffix_at(const LaneState<NG> &st, int g) {
 // Gray indices [m 2^kappa, (m+1) 2^kappa).  Local step l flips column ctz(l)
 // in every lane (Theorem 1); its direction is bit ctz(l)+1 of l except at
 // l = 2^(kappa-1), where it is the parity of m (Lemma 2's divergent step).
-// ZS: the matrix uses zero-aware skipping (md.zero_skip); a separate kernel
-// instance, so the pruning walk does not cost the other instances registers.
+// ZS: the matrix uses zero-aware skipping (md.zero_skip), a separate kernel
+// instance.  Only whole chunks are skipped: a per-position interval test (as
+// in the generated kernel) cost more than it saved on the serving mix, where
+// the 64 lanes of a wave rarely agree on a zero.
 template <int NG, bool ZS>
 __device__ __forceinline__ dd batch_lane(const BatchMat &md, const double *__restrict__ vals,
                                          const int32_t *__restrict__ tops_all, const u64 m) {
@@ -144,7 +146,7 @@ __device__ __forceinline__ dd batch_lane(const BatchMat &md, const double *__res
         // exact zero-aware skip: rows above every group the chunk's columns
         // touch stay constant; a zero product there in all lanes zeroes every term
         if (ZS && md.chunk_top + 1 < NG) live = !__all(suffix_at(st, md.chunk_top + 1) == 0.0);
-        if constexpr (!ZS) {
+        if (live) {
             for (u32 base = 0; base < DELTA; base += 2) {
                 // step base + 1: column 0, direction bit 1 of the local index
                 const double s0 = (kappa == 1) ? lsgn : (((base >> 1) & 1u) ? -1.0 : 1.0);
@@ -155,35 +157,6 @@ __device__ __forceinline__ dd batch_lane(const BatchMat &md, const double *__res
                 const bool in = ell < DELTA;
                 const int jj = in ? __builtin_ctz(ell) : 0;
                 const double sd = in ? ((jj == kappa - 1) ? lsgn : (((ell >> (jj + 1)) & 1u) ? -1.0 : 1.0)) : 0.0;
-                gray_step(st, cv + (size_t)jj * CS, tops[jj], sd, in ? 1.0 : 0.0, false, st.acc1);
-            }
-        } else {
-            // The same walk with exact pruning: at local position pos (its term
-            // added), v = ctz(pos) >= 2, the next 2^v - 1 steps flip only columns
-            // < v, so groups >= gv[v] (the lowest group none of them touches)
-            // stay constant; when their product is 0 in every lane the interval
-            // is skipped with its net effect, one flip of column v - 1 in the
-            // minus direction (bit v of pos is 1), and no term.  A failed test
-            // continues step by step; the intervals then tested at the next
-            // positions cover all of the failed one but its first four steps.
-            const int32_t *__restrict__ gv = tops + (n > 1 ? n - 1 : 1);
-            u32 pos = live ? 0u : DELTA;
-            while (pos < DELTA) {
-                const int v = pos ? __builtin_ctz(pos) : 0;
-                bool skip = false;
-                if (v >= 2) {
-                    const int g = gv[v];
-                    skip = g < NG && __all(suffix_at(st, g) == 0.0);
-                }
-                // first half: column 0 at pos + 1, or the net flip of (pos, pos + 2^v)
-                const int c = skip ? v - 1 : 0;
-                const double s1 = skip ? -1.0 : ((kappa == 1) ? lsgn : (((pos >> 1) & 1u) ? -1.0 : 1.0));
-                gray_step(st, cv + (size_t)c * CS, tops[c], s1, skip ? 0.0 : 1.0, true, st.acc0);
-                pos += skip ? (1u << v) : 2u;
-                // the step at pos: column ctz(pos); at pos = 2^kappa weight 0, update 0
-                const bool in = pos < DELTA;
-                const int jj = in ? __builtin_ctz(pos) : 0;
-                const double sd = in ? ((jj == kappa - 1) ? lsgn : (((pos >> (jj + 1)) & 1u) ? -1.0 : 1.0)) : 0.0;
                 gray_step(st, cv + (size_t)jj * CS, tops[jj], sd, in ? 1.0 : 0.0, false, st.acc1);
             }
         }
