@@ -121,17 +121,31 @@ namespace {
 // compiled code object).
 constexpr int kBaseVgprs = 28;
 
-int auto_kappa(int n) {
+// Chunk log2 (Gray steps per lane) and static block log2, measured on
+// MI355X.  All-terms kernels: about 2^21 lanes (8 resident rounds of the 4096
+// wave slots at 4 waves per SIMD), chunks of 2^8 .. 2^14 steps, blocks of
+// 2^7 (the paper's grid n = 40, p = 0.1 .. 0.5, and a real n = 36 matrix:
+// 2.5 % less time than 2^18 / 2^6 over all six, 20 % at n = 36).  Pruning
+// kernels (zero-aware skipping): about 2^23 lanes, at most 2^16 steps, blocks
+// of 2^6, since shorter chunks let more whole chunks and intervals be pruned
+// (three n = 40 0/1 matrices: 19 ms in all against 25 ms at 2^18).  At least
+// 2^(n-30) steps, so that the partial sums stay at 2^21 workgroups (32 MiB)
+// or fewer.
+int auto_kappa(int n, bool zero_skip) {
     const int total = n - 1;  // log2 of the number of Gray indices
-    // about 2^21 lanes (8 resident rounds of the 4096 wave slots at 4 waves
-    // per SIMD), chunks of at least 2^8 steps and at most 2^18 (larger n gets
-    // more lanes instead, so that its launches can be kept short), and no more
-    // than 2^40 chunks
-    int kappa = total - 21;
+    int kappa = total - (zero_skip ? 23 : 21);
     kappa = std::max(kappa, std::min(total, 8));
-    kappa = std::min(kappa, 18);
-    kappa = std::max(kappa, total - 40);
-    return kappa;
+    kappa = std::min(kappa, zero_skip ? 16 : 14);
+    kappa = std::max(kappa, total - 29);
+    return std::min(kappa, total);
+}
+
+int auto_unroll(bool zero_skip) { return zero_skip ? 6 : 7; }
+
+bool integer_valued(const Ccs &a) {
+    for (double v : a.val)
+        if (v != std::floor(v)) return false;
+    return true;
 }
 
 }  // namespace
@@ -142,6 +156,10 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
     p->n = n;
     p->nnz = a.nnz();
     p->mode = o.mode;
+    // x_i is an exact zero at many Gray indices only when the values are
+    // integers (then 2 x_i is an integer); real-valued inputs almost never
+    // produce one, and the checks would only cost registers.  0 = auto.
+    const bool zs = o.zero_skip > 0 ? true : o.zero_skip < 0 ? false : integer_valued(a);
     if (o.mode < PERM_MODE_AUTO || o.mode > PERM_MODE_HYBRID) {
         *err = "unknown mode";
         return PERM_EINVAL;
@@ -208,7 +226,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         // rows that no in-chunk column (index < kappa) touches are constant
         // inside a chunk: once their level product is formed at the chunk
         // start their registers are free, so only the other rows count
-        const int kap = o.chunk_log2 > 0 ? std::min(o.chunk_log2, std::max(n - 1, 0)) : auto_kappa(n);
+        const int kap = o.chunk_log2 > 0 ? std::min(o.chunk_log2, std::max(n - 1, 0)) : auto_kappa(n, zs);
         int live_rows = 0;
         for (int r = 0; r < k; ++r)
             if (first[r] < kap) ++live_rows;
@@ -255,7 +273,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
 
     // ---- schedule ----
     const int total_log2 = n - 1;
-    p->kappa = o.chunk_log2 > 0 ? o.chunk_log2 : auto_kappa(n);
+    p->kappa = o.chunk_log2 > 0 ? o.chunk_log2 : auto_kappa(n, zs);
     if (p->kappa > total_log2) p->kappa = total_log2;
     if (p->kappa > 30) {
         *err = "chunk_log2 must be <= 30";
@@ -265,8 +283,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         *err = "too many chunks: raise chunk_log2";
         return PERM_ETOOBIG;
     }
-    const int u_auto = 6;
-    p->u = o.unroll_log2 > 0 ? o.unroll_log2 : u_auto;
+    p->u = o.unroll_log2 > 0 ? o.unroll_log2 : auto_unroll(zs);
     if (p->u > 9) {
         *err = "unroll_log2 must be <= 9";
         return PERM_EINVAL;
@@ -292,18 +309,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
             return PERM_EINVAL;
         }
     }
-    if (o.zero_skip > 0) {
-        p->zero_skip = true;
-    } else if (o.zero_skip < 0) {
-        p->zero_skip = false;
-    } else {
-        // x_i is an exact zero at many Gray indices only when the values are
-        // integers (then 2 x_i is an integer); real-valued inputs almost never
-        // produce one, and the checks would only cost registers.
-        p->zero_skip = true;
-        for (double v : B.val)
-            if (v != std::floor(v)) p->zero_skip = false;
-    }
+    p->zero_skip = zs;
     if (p->block % 64 != 0 || p->block > 1024) {
         *err = "block must be a multiple of 64 and at most 1024";
         return PERM_EINVAL;
