@@ -251,9 +251,14 @@ def test_zero_skip_is_exact(P, oracle_mod):
     A = np.where(np.random.default_rng(1).random((20, 20)) < 0.2, 2.0, 0.0) + np.eye(20) * 3.0
     ccs = O.dense_to_ccs(A)
     ref, abs_sum = O.perm_nw(ccs)
-    on, _ = P.perm_sparse_ex(ccs, zero_skip=True)
-    off, _ = P.perm_sparse_ex(ccs, zero_skip=False)
+    # the same schedule on both sides: bitwise equal (the default schedules
+    # of the two kernel kinds differ, and with them the summation order)
+    on, _ = P.perm_sparse_ex(ccs, zero_skip=True, chunk_log2=8, unroll_log2=6)
+    off, _ = P.perm_sparse_ex(ccs, zero_skip=False, chunk_log2=8, unroll_log2=6)
     assert on == off and abs(on - ref) <= _tol(20, ref, abs_sum)
+    for zs in (True, False):
+        d, _ = P.perm_sparse_ex(ccs, zero_skip=zs)
+        assert abs(d - ref) <= _tol(20, ref, abs_sum)
     ccs = W.single_real(20, 0.3, 4)
     ref, abs_sum = O.perm_nw(ccs)
     on, _ = P.perm_sparse_ex(ccs, zero_skip=True)
