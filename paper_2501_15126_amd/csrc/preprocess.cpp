@@ -322,10 +322,18 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
     double ops = 0.0;
     const double steps = std::ldexp(1.0, n - 1);
     const int L = p->nlevels;
+    // A level that the flipped column does not touch keeps its x values, so
+    // the compiler reuses that level's product from the previous step (the
+    // same values); only touched levels' products and the chain multiplies
+    // S_l = P_l * S_{l+1}, l <= top, are executed.
+    std::vector<char> touched(L, 0);
     for (int j = 0; j < n - 1; ++j) {
         const int t = p->col_top[j];
+        std::fill(touched.begin(), touched.end(), 0);
+        for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) touched[p->row_level[B.rowidx[q]]] = 1;
         double oj = B.colptr[j + 1] - B.colptr[j];  // x updates
-        for (int l = 0; l <= t; ++l) oj += std::max(0, level_size[l] - 1);
+        for (int l = 0; l <= t; ++l)
+            if (touched[l]) oj += std::max(0, level_size[l] - 1);
         for (int l = 1; l <= t; ++l)
             if (l < L - 1) oj += 1;  // chain multiply by S_{l+1}
         if (L > 1) oj += 1;          // accumulate: fma(P_0, S_1, acc)
