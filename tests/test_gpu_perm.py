@@ -206,6 +206,34 @@ def test_er_grid_cell_block_partials_vs_oracle(P, oracle_mod):
     assert total * 2.0 == pytest.approx(got, rel=1e-12)
 
 
+def test_full_size_closed_forms(P, oracle_mod):
+    """n = 40, the benchmark size, on matrices whose permanent is known in
+    closed form (no oracle run): tridiagonal of ones, F(41) = 165580141; a
+    real tridiagonal, its continuant; I + cyclic shift, 2; 2x2 blocks of
+    ones, 2^20.  Rows and columns shuffled; pruned and all-terms kernels."""
+    from fractions import Fraction
+    O = oracle_mod
+    n = 40
+    rng = np.random.default_rng(40)
+    pr, pc = rng.permutation(n), rng.permutation(n)
+    T = np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)
+    R = T * rng.uniform(0.5, 1.5, (n, n))
+    f2, f1 = Fraction(1), Fraction(R[0, 0])
+    for k in range(1, n):
+        f2, f1 = f1, Fraction(R[k, k]) * f1 + Fraction(R[k - 1, k]) * Fraction(R[k, k - 1]) * f2
+    cases = [(T, 165580141.0), (np.eye(n) + np.roll(np.eye(n), 1, axis=1), 2.0),
+             (np.kron(np.eye(n // 2), np.ones((2, 2))), float(2 ** (n // 2))), (R, float(f1))]
+    for A, want in cases:
+        ccs = O.dense_to_ccs(A[np.ix_(pr, pc)])
+        for zs in ("auto", False):
+            got, st = P.perm_sparse_ex(ccs, zero_skip=zs)
+            print("closed form", want, got, zs, st["kernel_ms"], flush=True)
+            if want == round(want) and (A == np.round(A)).all():
+                assert got == want, (want, got, zs)
+            else:
+                assert got == pytest.approx(want, rel=1e-10), (want, got, zs)
+
+
 def test_n36_full_vs_oracle(P):
     g = _golden()
     key = "n36_p0.30_real:1"

@@ -524,3 +524,48 @@ def test_structural_rank(oracle_mod):
     A[:, 1] = 0
     A[0, 1] = 1
     assert O.structural_rank(O.dense_to_ccs(A)) == 3
+
+
+def _tridiagonal(n, rng, real):
+    """Tridiagonal matrix: values U(0.5, 1.5) when real, else all 1."""
+    A = np.zeros((n, n))
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                A[i, j] = rng.uniform(0.5, 1.5) if real else 1.0
+    return A
+
+
+def _continuant(A):
+    """perm of a tridiagonal matrix, exactly: expanding along the last row,
+    perm(T_k) = a_kk perm(T_{k-1}) + a_{k-1,k} a_{k,k-1} perm(T_{k-2})."""
+    from fractions import Fraction
+    n = A.shape[0]
+    f2, f1 = Fraction(1), Fraction(A[0, 0])
+    for k in range(1, n):
+        f2, f1 = f1, Fraction(A[k, k]) * f1 + Fraction(A[k - 1, k]) * Fraction(A[k, k - 1]) * f2
+    return f1
+
+
+def test_nw_tridiagonal_closed_forms(oracle_mod):
+    """Structured sparse matrices with closed-form permanents, rows and columns
+    shuffled: tridiagonal (Fibonacci F(n+1) for all ones, the continuant for
+    real values), I + cyclic shift (2), 2x2 blocks of ones (2^(n/2))."""
+    O = oracle_mod
+    rng = np.random.default_rng(11)
+    fib = [0, 1]
+    while len(fib) < 40:
+        fib.append(fib[-1] + fib[-2])
+    for n in (5, 12, 21):
+        P_r, P_c = rng.permutation(n), rng.permutation(n)
+        A = _tridiagonal(n, rng, real=False)[np.ix_(P_r, P_c)]
+        assert O.perm_int(O.dense_to_ccs(A)) == fib[n + 1]
+        R = _tridiagonal(n, rng, real=True)
+        exact = float(_continuant(R))
+        got, abs_sum = O.perm_nw(O.dense_to_ccs(R[np.ix_(P_r, P_c)]))
+        assert got == pytest.approx(exact, rel=1e-14)
+        C = np.eye(n) + np.roll(np.eye(n), 1, axis=1)
+        assert O.perm_int(O.dense_to_ccs(C[np.ix_(P_r, P_c)])) == 2
+    n = 16
+    B = np.kron(np.eye(n // 2), np.ones((2, 2)))
+    assert O.perm_int(O.dense_to_ccs(B[np.ix_(rng.permutation(n), rng.permutation(n))])) == 2 ** (n // 2)
