@@ -119,7 +119,9 @@ typedef struct {
                                events recorded on the launch stream */
     double reduce_ms;       /* device time of the final reduction kernel */
     double compile_ms;      /* hipRTC compile + module load; 0 on a cache hit */
-    double host_ms;         /* validate + structure check + order + partition + codegen */
+    double host_ms;         /* validate + structure check + order + partition + codegen;
+                               a repeated call with byte-identical input and options
+                               reuses the plan and code (about a microsecond) */
     double total_ms;        /* wall time of the whole call */
     double steps;           /* Gray-code steps evaluated: 2^(n-1) */
     double ops_per_step;    /* FP64 VALU operations per step of the generated
@@ -139,7 +141,7 @@ typedef struct {
     int32_t chunk_log2, unroll_log2, block;
     int32_t vgprs, sgprs, scratch_bytes, lds_bytes;
     int32_t waves_per_simd; /* occupancy reported by the HIP occupancy API */
-    int32_t cache_hit;      /* generated code object reused */
+    int32_t cache_hit;      /* plan or generated code object reused */
     int32_t singular;       /* 1 if answered as 0 by the structural check */
 } perm_stats;
 
@@ -151,12 +153,14 @@ double perm_sparse(int32_t n, const int32_t *colptr, const int32_t *rowidx, cons
  * st may be NULL.  Synchronous: returns after the result is on the host. */
 perm_status perm_sparse_ex(const perm_csc *a, const perm_opts *opts, double *out, perm_stats *st);
 
-/* Permanents of `count` matrices (any mix of sizes n <= 64), out[i] for
- * mats[i].  Synchronous.  Uses kernels compiled into the library (no per-matrix
- * hipRTC): x in registers as 4-row groups, each matrix's columns as data, 64
- * chunks of one matrix per wave, all matrices in one graph of launches.  A
- * matrix's result depends only on that matrix and the options, not on the
- * rest of the batch (bitwise).  Results agree with perm_sparse_ex within the
+/* Permanents (Eq. (1), by Alg. 1) of `count` matrices (any mix of sizes
+ * n <= 64), out[i] for mats[i].  Synchronous.  Uses kernels compiled into the
+ * library (no per-matrix hipRTC): x in registers as 4-row groups, each
+ * matrix's columns as data, 64 chunks of one matrix per wave, one launch per
+ * kernel instance (group count, zero-skip kind), each instance on a stream
+ * of its own (batch_mode selects other launch forms).  A matrix's result
+ * depends only on that matrix and the options, not on the rest of the batch
+ * (bitwise).  Results agree with perm_sparse_ex within the
  * FP64 tolerance, not bitwise (different kernels).  Any invalid matrix fails
  * the whole call (PERM_EINVAL, perm_last_error names its index). */
 perm_status perm_batch(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out);
