@@ -154,7 +154,7 @@ double perm_sparse(int32_t n, const int32_t *colptr, const int32_t *rowidx, cons
 perm_status perm_sparse_ex(const perm_csc *a, const perm_opts *opts, double *out, perm_stats *st);
 
 /* Permanents (Eq. (1), by Alg. 1) of `count` matrices (any mix of sizes
- * n <= 64), out[i] for mats[i].  Synchronous.  Uses kernels compiled into the
+ * n <= 44; larger n gives PERM_ETOOBIG: use perm_sparse_ex), out[i] for mats[i].  Synchronous.  Uses kernels compiled into the
  * library (no per-matrix hipRTC): x in registers as 4-row groups, each
  * matrix's columns as data, 64 chunks of one matrix per wave, one launch per
  * kernel instance (group count, zero-skip kind), each instance on a stream

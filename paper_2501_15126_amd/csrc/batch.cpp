@@ -26,6 +26,8 @@ int batch_kappa(int n, int shift) {
     // which the server interleaves requests); at least 2^5 steps per chunk
     // when n allows it
     int kappa = std::min(std::max(total - 9 + shift, std::min(total, 5)), 13 + shift);
+    // at most 2^22 work items (64-chunk waves) per matrix: 64 MiB of partials
+    kappa = std::max(kappa, total - 28);
     return std::max(0, std::min(kappa, total));
 }
 
@@ -35,6 +37,11 @@ perm_status prepare_batch_matrix(const perm_csc *m, const BatchOptions &bo, Prep
     const Ccs &a = pm->a;
     const int n = a.n;
     pm->n = n;
+    if (n > kBatchMaxN) {
+        *err = "n = " + std::to_string(n) + " is beyond the batch kernels (n <= " + std::to_string(kBatchMaxN) +
+               "); use perm_sparse_ex";
+        return PERM_ETOOBIG;
+    }
     pm->singular = structural_rank(a) < n;
     if (pm->singular) return PERM_OK;
     std::vector<int> rp, cp;

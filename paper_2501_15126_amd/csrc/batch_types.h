@@ -37,7 +37,11 @@ struct FinishDesc {
     int32_t pad;
 };
 
-constexpr int kBatchMaxNG = 16;  // n <= 64
+constexpr int kBatchMaxNG = 16;  // x of up to 64 rows
+// A batch launch covers whole matrices: n <= 44 keeps one at 2^43 Gray steps
+// (about 13 s of the device), with at most 2^22 waves; larger n goes through
+// the single-matrix path, whose launches are sliced.
+constexpr int kBatchMaxN = 44;
 constexpr int kBatchStreams = 4;  // kernel instances ng run on stream ng % kBatchStreams
 
 }  // namespace permx

@@ -130,14 +130,14 @@ constexpr int kBaseVgprs = 28;
 // of 2^6, since shorter chunks let more whole chunks and intervals be pruned
 // (three n = 40 0/1 matrices: 19 ms in all against 25 ms at 2^18).  At least
 // 2^(n-30) steps, so that the partial sums stay at 2^21 workgroups (32 MiB)
-// or fewer.
+// or fewer up to n = 60, and at most 2^30 (the kernel's limit).
 int auto_kappa(int n, bool zero_skip) {
     const int total = n - 1;  // log2 of the number of Gray indices
     int kappa = total - (zero_skip ? 23 : 21);
     kappa = std::max(kappa, std::min(total, 8));
     kappa = std::min(kappa, zero_skip ? 16 : 14);
     kappa = std::max(kappa, total - 29);
-    return std::min(kappa, total);
+    return std::min(kappa, std::min(total, 30));
 }
 
 int auto_unroll(bool zero_skip) { return zero_skip ? 6 : 7; }

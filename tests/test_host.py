@@ -342,3 +342,45 @@ def test_batch_lane_code_on_cpu_matches_oracle(P, oracle_mod):
         exact = O.perm_int(ccs)
         for zs in (True, False):
             assert _batch_emulate(P, lib, ccs, zero_skip=zs) == exact
+
+
+def test_plans_on_random_matrices(P):
+    """Planning invariants over many random sparse matrices (n 1..64, all
+    modes): the orderings are permutations, HYBRID's register-only columns
+    touch register rows only, levels and partition stay in range, and every
+    plan is accepted by the code generator."""
+    rng = np.random.default_rng(2024)
+    for t in range(120):
+        n = int(rng.integers(1, 65))
+        d = float(rng.uniform(0.02, 0.6))
+        ccs = W.random_sparse(n, d, seed=5000 + t, kind=("01", "real", "signed")[t % 3], diag=True)
+        for mode in ("auto", "pure", "hybrid"):
+            pl = P.perm_plan(ccs, mode=mode)
+            assert sorted(pl["row_perm"]) == list(range(n)) and sorted(pl["col_perm"]) == list(range(n))
+            assert pl["structural_rank"] == n  # a forced diagonal
+            k, c = pl["k"], pl["c"]
+            assert 1 <= k <= n and 0 <= c <= n
+            assert pl["levels"] >= 1
+            if mode == "hybrid" and k < n:
+                nn, cp, ri, v = ccs
+                rpos = np.empty(n, int)
+                rpos[np.asarray(pl["row_perm"])] = np.arange(n)
+                for j in range(min(c, n - 1)):
+                    col = pl["col_perm"][j]
+                    assert all(rpos[r] < k for r in ri[cp[col]:cp[col + 1]]), (t, j)
+            if n <= 40 and t % 6 == 0:
+                src = P.perm_codegen(ccs, mode=mode)
+                assert "perm_gray" in src
+
+
+def test_batch_limits(P):
+    """The batch path bounds its work items per matrix (chunks grow with n)
+    and refuses n above 44, where a matrix would need one very long launch."""
+    for n, want_kappa in ((30, 13), (42, 13), (43, 14), (44, 15)):
+        ccs = W.random_sparse(n, 0.2, seed=n, kind="real", diag=True)
+        info, _, _ = P.batch_describe(ccs)
+        assert info["kappa"] == want_kappa, (n, info["kappa"])
+        assert (n - 1 - info["kappa"]) - 6 <= 22
+    with pytest.raises(P.PermError) as e:
+        P.batch_describe(W.random_sparse(45, 0.2, seed=45, kind="real", diag=True))
+    assert e.value.status == P.PERM_ETOOBIG
