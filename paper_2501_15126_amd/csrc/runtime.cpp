@@ -3,6 +3,7 @@
 // introspection entry points.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -11,7 +12,9 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
+#include <vector>
 
 #include "batch_host.h"
 #include "jit.h"
@@ -375,9 +378,23 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
     std::string err;
     double steps = 0.0, ops = 0.0, fmas = 0.0;
     int singular = 0;
+    {
+        // the matrices are independent: prepare them on a few host threads
+        // (each writes only its own slots), then report the first failure
+        std::vector<perm_status> st_of(count, PERM_OK);
+        std::vector<std::string> err_of(count);
+        const int nthreads = std::max(1, std::min<int>({(int)std::thread::hardware_concurrency(), 8, count / 64}));
+        auto work = [&](int t) {
+            for (int32_t i = t; i < count; i += nthreads) st_of[i] = prepare_batch_matrix(&mats[i], bo, &prep[i], &err_of[i]);
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nthreads; ++t) pool.emplace_back(work, t);
+        work(0);
+        for (auto &th : pool) th.join();
+        for (int32_t i = 0; i < count; ++i)
+            if (st_of[i] != PERM_OK) return fail(st_of[i], "matrix " + std::to_string(i) + ": " + err_of[i]);
+    }
     for (int32_t i = 0; i < count; ++i) {
-        perm_status s = prepare_batch_matrix(&mats[i], bo, &prep[i], &err);
-        if (s != PERM_OK) return fail(s, "matrix " + std::to_string(i) + ": " + err);
         if (prep[i].singular) {
             ++singular;
         } else {
