@@ -234,6 +234,10 @@ def main():
                     help="skip the context run of the same permanent with zero-aware skipping off")
     ap.add_argument("--serving-seconds", type=float, default=20.0,
                     help="length of the Poisson serving run (0 skips it)")
+    ap.add_argument("--serving-rate", type=float, default=200.0,
+                    help="Poisson arrival rate of the serving run (requests/s)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving measurement (with --serving-seconds, --serving-rate)")
     ap.add_argument("--grid", default="",
                     help="run only the paper's synthetic grid for these n (comma list, e.g. 40,45,48)")
     ap.add_argument("--grid-variants", default="auto",
@@ -268,6 +272,9 @@ def main():
         return
     if args.batch_only:
         print(json.dumps({"batch": batch_bench(reps=2, sequential=False)}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(args.serving_seconds, rate_hz=args.serving_rate)}), flush=True)
         return
     zs = {"auto": "auto", "on": True, "off": False}[args.zero_skip]
     ccs = W.WORKLOADS[args.workload](args.seed)
@@ -345,7 +352,7 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_bench()
     if args.serving_seconds > 0:
-        out["serving"] = serving_bench(args.serving_seconds)
+        out["serving"] = serving_bench(args.serving_seconds, rate_hz=args.serving_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ccs)
     print(json.dumps(out), flush=True)

@@ -236,6 +236,18 @@ def test_full_size_closed_forms(P, oracle_mod):
                 assert got == pytest.approx(want, rel=1e-10), (want, got, zs)
 
 
+def test_progress_lines(P, capfd):
+    """perm_opts.progress: one stderr line per completed launch, the result
+    unchanged (a real n = 44 matrix: 2^43 steps in launches of at most 2^42)."""
+    ccs = W.er_grid_matrix(44, 0.1)
+    quiet, st = P.perm_sparse_ex(ccs)
+    loud, st2 = P.perm_sparse_ex(ccs, progress=True)
+    err = capfd.readouterr().err
+    lines = [l for l in err.splitlines() if l.startswith("perm: n=44 launch")]
+    assert len(lines) >= 2 and lines[-1].endswith("of %d done" % len(lines)), err[-500:]
+    assert loud == quiet
+
+
 def test_n36_full_vs_oracle(P):
     g = _golden()
     key = "n36_p0.30_real:1"
