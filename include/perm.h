@@ -190,13 +190,13 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
  * that were submitted and not yet collected (0 = 4096).  Requests use the
  * precompiled batch kernels (no per-request hipRTC) with opts' zero_skip and
  * batch_kappa_shift.  Admission is in arrival order, as arena memory frees.
- * Every scheduling round shares `round_steps` Gray steps (0 = 8e9, about
- * 10 ms of device work) among the admitted requests by water-filling (a
- * request that needs less than an equal share leaves the rest to the
- * others); two rounds are in flight, so requests that arrive while others
- * run overlap with them on the GPU.  Each kernel instance (ng) has its own
- * stream.  A request's result is bitwise the same whether it runs alone or
- * in any mix, and equals perm_batch's with the same options.  Returns NULL on
+ * Every scheduling round runs `round_steps` Gray steps (0 = 8e9, about 10 ms
+ * of device work): first all of the remaining work of every small request
+ * (at most a quarter of a round left), then the larger requests in arrival
+ * order, each as much as it can use.  Two rounds are in flight, so requests
+ * that arrive while others run join the next round.  Each kernel instance
+ * (ng) has its own stream.  A request's result is bitwise the same whether
+ * it runs alone or in any mix, and equals perm_batch's with the same options.  Returns NULL on
  * error (perm_last_error).  The server uses the device current at creation. */
 typedef struct perm_server perm_server;
 perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget, int32_t max_inflight,

@@ -4,10 +4,10 @@
 // the submitting thread.  A scheduler thread admits them in arrival order as
 // device memory frees up (one arena of `device_mem_budget` bytes holds each
 // admitted request's matrix data and partial sums) and runs rounds.  A round
-// gives every active request a share of Gray steps (water-filling: a request
-// that needs less than an equal share leaves the rest to the others), as
-// 64-chunk work items, and issues them as one launch per kernel instance on
-// that instance's class stream; the requests whose last items are in the
+// of `round_steps` Gray steps first finishes every small request (at most a
+// quarter of a round left), then gives the rest to the larger requests in
+// arrival order, as 64-chunk work items, and issues them as one launch per
+// kernel instance on that instance's class stream; the requests whose last items are in the
 // round are finished on the same stream.  Two rounds are in flight: while the
 // GPU runs one, the scheduler publishes the previous one's results, admits new
 // requests and issues the next, so a request that arrives while others run
@@ -240,30 +240,42 @@ bool perm_server::dispatchable() const {
 
 bool perm_server::issue(Slot &slot, const std::vector<Request *> &newly, std::string *err) {
     if (!slots[0].busy && !slots[1].busy) busy_since = Clock::now();
-    // ---- shares: water-filling of round_steps over the requests with work left ----
+    // ---- shares of round_steps: small requests first, then oldest first ----
+    // A request whose remaining work is at most a quarter of a round takes
+    // all of it now (oldest first, within the round's budget), so short
+    // requests finish in the next round whatever else is queued.  The rest of
+    // the budget goes to the larger requests in arrival order, each as much
+    // as it can use, so the oldest large request finishes as soon as the
+    // device allows and the next ones fill what it leaves (equal shares among
+    // all active requests slowed the largest ones most at high load).
     struct Take {
         Request *r;
         uint64_t items;
     };
-    std::vector<std::pair<double, Request *>> cand;
+    std::vector<Request *> cand;
     for (Request *r : active)
-        if (r->next_item < r->items_total)
-            cand.emplace_back((double)(r->items_total - r->next_item) * std::ldexp(64.0, r->pm.kappa), r);
-    std::stable_sort(cand.begin(), cand.end(),
-                     [](const std::pair<double, Request *> &x, const std::pair<double, Request *> &y) {
-                         return x.first < y.first;
-                     });
+        if (r->next_item < r->items_total) cand.push_back(r);
+    std::stable_sort(cand.begin(), cand.end(), [](const Request *x, const Request *y) { return x->ticket < y->ticket; });
+    auto item_steps = [](const Request *r) { return std::ldexp(64.0, r->pm.kappa); };
+    auto remaining = [&](const Request *r) { return (double)(r->items_total - r->next_item) * item_steps(r); };
     std::vector<Take> takes[kBatchStreams];
     double left = round_steps;
-    size_t k = cand.size();
-    for (auto &c : cand) {
-        Request *r = c.second;
-        const double item_steps = std::ldexp(64.0, r->pm.kappa);
-        const double give = std::min(c.first, std::max(0.0, left) / (double)k--);
-        const uint64_t rem = r->items_total - r->next_item;
-        const uint64_t t = std::min<uint64_t>(rem, std::max<uint64_t>(1, (uint64_t)(give / item_steps)));
-        left -= (double)t * item_steps;
-        takes[r->pm.ng % kBatchStreams].push_back(Take{r, t});
+    bool any = false;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (Request *r : cand) {
+            const bool small = remaining(r) <= 0.25 * round_steps;
+            if ((pass == 0) != small || left <= 0.0) continue;
+            const uint64_t rem = r->items_total - r->next_item;
+            uint64_t t = small ? rem : std::min<uint64_t>(rem, (uint64_t)(left / item_steps(r)));
+            if (t == 0) continue;
+            left -= (double)t * item_steps(r);
+            takes[r->pm.ng % kBatchStreams].push_back(Take{r, t});
+            any = true;
+        }
+    }
+    if (!any && !cand.empty()) {  // a single item larger than the round: still progress
+        Request *r = cand.front();
+        takes[r->pm.ng % kBatchStreams].push_back(Take{r, 1});
     }
     // ---- per class stream: stage, upload, launch, finish ----
     const double *vals = reinterpret_cast<const double *>(arena);
