@@ -190,8 +190,8 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
  * that were submitted and not yet collected (0 = 4096).  Requests use the
  * precompiled batch kernels (no per-request hipRTC) with opts' zero_skip and
  * batch_kappa_shift.  Admission is in arrival order, as arena memory frees.
- * Every scheduling round runs `round_steps` Gray steps (0 = 8e9, about 10 ms
- * of device work): first all of the remaining work of every small request
+ * Every scheduling round runs `round_steps` Gray steps (0 = 1.6e10, about
+ * 20 ms of device work): first all of the remaining work of every small request
  * (at most a quarter of a round left), then the larger requests in arrival
  * order, each as much as it can use.  Two rounds are in flight, so requests
  * that arrive while others run join the next round.  Each kernel instance
