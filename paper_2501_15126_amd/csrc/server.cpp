@@ -403,7 +403,10 @@ bool perm_server::issue(Slot &slot, const std::vector<Request *> &newly, std::st
         cb.used = true;
     }
     slot.busy = true;
-    ++n_rounds;
+    {
+        std::lock_guard<std::mutex> g(mu);  // read by perm_server_get_stats
+        ++n_rounds;
+    }
     return true;
 }
 
