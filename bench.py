@@ -323,11 +323,13 @@ def main():
                    "gray_steps_per_permanent": steps_per_perm},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(P.perm_codegen(ccs, mode=args.mode, zero_skip=zs))},
+                     "traffic": measured_traffic(P.perm_codegen(ccs, mode=args.mode, zero_skip=zs,
+                                                                 waves_per_simd=st["waves_hint"] or -1))},
         "kernel": {"name": "perm_gray", "avg_ms": avg_kernel_s * 1e3, "steps_per_s": steps_per_perm / avg_kernel_s,
                    "flops_per_step": st["flops_per_step"], "fp64_ops_per_step": st["ops_per_step"],
                    "fp64_issue_frac": ops_rate / 3.93216e13, "vgprs": st["vgprs"], "sgprs": st["sgprs"],
-                   "scratch_bytes": st["scratch_bytes"], "waves_per_simd": st["waves_per_simd"],
+                   "scratch_bytes": st["scratch_bytes"], "waves_per_simd": st["waves_per_simd"], "waves_hint": st["waves_hint"],
+                   "vgpr_spills": st["vgpr_spills"],
                    "chunk_log2": st["chunk_log2"], "unroll_log2": st["unroll_log2"], "levels": st["levels"],
                    "k": st["k"], "c": st["c"], "nblocks": st["nblocks"], "reduce_ms": st["reduce_ms"],
                    "host_ms": st["host_ms"], "compile_ms_cold": first["compile_ms"] if first else None,

@@ -110,7 +110,14 @@ typedef struct {
     int64_t block_partials_cap;
     int32_t progress;      /* > 0: perm_sparse_ex prints one line to stderr as each of
                               its launches (at most 2^42 Gray steps each) completes */
-    int32_t pad;
+    int32_t waves_per_simd; /* occupancy the generated kernel is compiled for.
+                              1..8: that many waves per SIMD (the compiler keeps the
+                              kernel within 512 / waves VGPRs, spilling if it must);
+                              -1: the compiler's own choice; 0 = automatic: the
+                              compiler's choice, except that a kernel it holds to 4
+                              waves (97..128 VGPRs) whose rows are not in LDS is
+                              compiled again for 5 waves, and that build is used if it
+                              spills at most 128 bytes per lane */
 } perm_opts;
 
 /* Statistics of one call (all optional to read). */
@@ -143,6 +150,8 @@ typedef struct {
     int32_t waves_per_simd; /* occupancy reported by the HIP occupancy API */
     int32_t cache_hit;      /* plan or generated code object reused */
     int32_t singular;       /* 1 if answered as 0 by the structural check */
+    int32_t waves_hint;     /* waves per SIMD the kernel was compiled for; 0 = none */
+    int32_t vgpr_spills;    /* VGPRs the compiler spilled to scratch */
 } perm_stats;
 
 /* Permanent of one matrix (Alg. 1 end to end).  Returns NaN on error
@@ -248,7 +257,9 @@ perm_status perm_partition(const perm_csc *ordered, const double *tau, double gr
                            int32_t *c);
 
 /* The HIP source text generated for a matrix.  Writes at most cap bytes
- * (NUL-terminated when it fits) and the full length to *len. */
+ * (NUL-terminated when it fits) and the full length to *len.  Generation only:
+ * with waves_per_simd 0 (automatic) the text carries no occupancy attribute;
+ * passing perm_stats.waves_hint of a run gives the exact text that ran. */
 perm_status perm_codegen(const perm_csc *a, const perm_opts *opts, char *buf, size_t cap, size_t *len);
 
 /* Compile the generated kernel for a matrix with hipRTC (gfx950; no GPU

@@ -84,11 +84,27 @@ __device__ __forceinline__ double suffix1(const LaneState<NG> &st) {
 
 // One Gray step: column (groups 0..top at c, unsigned) flipped with direction
 // s (+-1 per lane), cached products refreshed, term (-1)^l added with weight w.
-template <int NG>
-__device__ __forceinline__ void gray_step(LaneState<NG> &st, const double *__restrict__ c, int top, double s,
-                                          double w, bool negterm, double &acc) {
-    groups_from_top<NG, 1>(st, c, top, s);
-    group_fma<NG, 0>(st, c, s);
+// The column's group 0 values (and, if G1, group 1 values) are passed in v01,
+// already loaded, so that their scalar loads need not wait behind the others.
+template <int NG, bool G1>
+__device__ __forceinline__ void gray_step(LaneState<NG> &st, const double *__restrict__ c, const double *v01,
+                                          int top, double s, double w, bool negterm, double &acc) {
+    if constexpr (G1 && NG >= 2) {
+        if (top >= 1) {
+            groups_from_top<NG, 2>(st, c, top, s);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) st.x[4 + i] = fma(s, v01[4 + i], st.x[4 + i]);
+            const double p = (st.x[4] * st.x[5]) * (st.x[6] * st.x[7]);
+            if constexpr (NG > 2)
+                st.S[1] = p * st.S[2];
+            else
+                st.S[1] = p;
+        }
+    } else {
+        groups_from_top<NG, 1>(st, c, top, s);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) st.x[i] = fma(s, v01[i], st.x[i]);
     const double g0 = group0_product(st) * w;
     acc = fma(negterm ? -g0 : g0, suffix1(st), acc);
 }
@@ -147,17 +163,29 @@ __device__ __forceinline__ dd batch_lane(const BatchMat &md, const double *__res
         // touch stay constant; a zero product there in all lanes zeroes every term
         if (ZS && md.chunk_top + 1 < NG) live = !__all(suffix_at(st, md.chunk_top + 1) == 0.0);
         if (live) {
+            // column 0's groups 0 and 1 stay in scalar registers for the whole chunk
+            constexpr int NV = NG >= 2 ? 8 : 4;
+            double c0[8];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) c0[i] = cv[i];
             for (u32 base = 0; base < DELTA; base += 2) {
-                // step base + 1: column 0, direction bit 1 of the local index
-                const double s0 = (kappa == 1) ? lsgn : (((base >> 1) & 1u) ? -1.0 : 1.0);
-                gray_step(st, cv, t0, s0, 1.0, true, st.acc0);
-                // step base + 2: column ctz >= 1; at base + 2 = 2^kappa (not a
-                // step of this chunk) the weight is 0 and the update is 0
+                // step base + 2 flips column ctz(base + 2) >= 1; at base + 2 =
+                // 2^kappa (not a step of this chunk) the weight is 0 and the
+                // update is 0.  Its top and group 0 are read together, so that
+                // one wait covers both loads.
                 const u32 ell = base + 2;
                 const bool in = ell < DELTA;
                 const int jj = in ? __builtin_ctz(ell) : 0;
+                const double *cj = cv + (size_t)jj * CS;
+                const int tj = tops[jj];
+                double vj[8];  // groups 0 (read) and 1 (not used by this step)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) vj[i] = cj[i];
+                // step base + 1: column 0, direction bit 1 of the local index
+                const double s0 = (kappa == 1) ? lsgn : (((base >> 1) & 1u) ? -1.0 : 1.0);
+                gray_step<NG, true>(st, cv, c0, t0, s0, 1.0, true, st.acc0);
                 const double sd = in ? ((jj == kappa - 1) ? lsgn : (((ell >> (jj + 1)) & 1u) ? -1.0 : 1.0)) : 0.0;
-                gray_step(st, cv + (size_t)jj * CS, tops[jj], sd, in ? 1.0 : 0.0, false, st.acc1);
+                gray_step<NG, false>(st, cj, vj, tj, sd, in ? 1.0 : 0.0, false, st.acc1);
             }
         }
     }

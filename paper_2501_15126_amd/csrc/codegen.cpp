@@ -456,7 +456,9 @@ struct Gen {
         // ---- the kernel: one chunk per lane, then a deterministic reduction
         //      lane -> wave (butterfly) -> workgroup ----
         const int nw = p.block / 64;
-        os << "extern \"C\" __global__ void __launch_bounds__(" << p.block << ") " << kGrayKernelName
+        os << "extern \"C\" __global__ void __launch_bounds__(" << p.block << ") ";
+        if (p.waves_per_simd > 0) os << "__attribute__((amdgpu_waves_per_eu(" << p.waves_per_simd << "))) ";
+        os << kGrayKernelName
            << "(const u64 chunk_begin, const u64 chunk_end, double* __restrict__ partials,\n"
               "    u64* __restrict__ counts, double* __restrict__ xg, const u64 xs) {\n";
         os << "  const u64 lid = (u64)blockIdx.x * " << p.block << "u + threadIdx.x;\n"

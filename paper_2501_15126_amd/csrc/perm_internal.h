@@ -72,6 +72,7 @@ struct Plan {
     int kappa = 0;                      // chunk = 2^kappa Gray steps per lane
     int u = 0;                          // static unrolled block = 2^u steps
     int block = 256;
+    int waves_per_simd = 0;             // > 0: occupancy hint for the compiler
     bool zero_skip = true;              // skip chunks / blocks whose terms are exactly 0
     double base_x_hi[PERM_MAX_N];       // x_r at Gray index 0 (Alg. 1 lines 1-5)
     double ops_per_step = 0, flops_per_step = 0;

@@ -310,6 +310,11 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         }
     }
     p->zero_skip = zs;
+    if (o.waves_per_simd < -1 || o.waves_per_simd > 8) {
+        *err = "waves_per_simd must be -1 (compiler's choice), 0 (automatic) or 1..8";
+        return PERM_EINVAL;
+    }
+    p->waves_per_simd = std::max(0, o.waves_per_simd);
     if (p->block % 64 != 0 || p->block > 1024) {
         *err = "block must be a multiple of 64 and at most 1024";
         return PERM_EINVAL;

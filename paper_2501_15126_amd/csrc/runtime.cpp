@@ -156,6 +156,36 @@ perm_status prepare(const perm_csc *m, const perm_opts &o, Prepared *p, bool wan
     return PERM_OK;
 }
 
+// Largest per-lane scratch accepted from the second, 5-wave build of the
+// automatic occupancy choice (16 doubles).
+constexpr int kAutoWavesMaxScratch = 128;
+
+// Compiles p->src.  With the occupancy left automatic, a kernel that the
+// compiler holds to 4 waves per SIMD (97..128 VGPRs; 512 VGPRs per SIMD lane,
+// allocated in steps of 8) is generated and compiled again for 5 waves, and
+// that build replaces the first if it spills little: a fifth wave hides more
+// of the FP64 dependency and branch latency than the few spilled values cost.
+// Kernels with LDS-resident rows are left alone (their LDS use already bounds
+// the occupancy).
+perm_status compile_prepared(Prepared *p, const perm_opts &o, CodeObject *co, std::string *err) {
+    perm_status s = compile_source(p->src, co, err);
+    if (s != PERM_OK || o.waves_per_simd != 0 || p->plan.cold_lds) return s;
+    if (co->vgprs <= 96 || co->vgprs > 128) return PERM_OK;
+    Plan q = p->plan;
+    q.waves_per_simd = 5;
+    std::string src5 = generate_source(q);
+    CodeObject c5;
+    std::string err5;
+    if (compile_source(src5, &c5, &err5) != PERM_OK) return PERM_OK;  // keep the first build
+    if (c5.scratch_bytes < 0 || c5.scratch_bytes > kAutoWavesMaxScratch) return PERM_OK;
+    c5.compile_ms += co->compile_ms;
+    c5.cache_hit = c5.cache_hit && co->cache_hit;
+    p->plan.waves_per_simd = 5;
+    p->src = std::move(src5);
+    *co = std::move(c5);
+    return PERM_OK;
+}
+
 void fill_plan_stats(const Prepared &p, perm_stats *st) {
     st->n = p.a.n;
     st->nnz = p.a.nnz();
@@ -205,7 +235,8 @@ bool plan_key(const perm_csc *m, const perm_opts &o, std::string *key) {
         put(m->val, sizeof(double) * (size_t)nnz);
     }
     const int32_t f[] = {o.mode,     o.chunk_log2, o.unroll_log2, o.block,     o.vgpr_budget,
-                         o.force_k,  o.force_c,    o.max_levels,  o.zero_skip, o.cold_tier};
+                         o.force_k,  o.force_c,    o.max_levels,  o.zero_skip, o.cold_tier,
+                         o.waves_per_simd};
     put(f, sizeof f);
     put(&o.gr_ratio, sizeof o.gr_ratio);
     return true;
@@ -231,7 +262,7 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
         if (s != PERM_OK) return s;
         if (!cp->p.singular) {
             std::string err;
-            s = compile_source(cp->p.src, &cp->co, &err);
+            s = compile_prepared(&cp->p, o, &cp->co, &err);
             if (s != PERM_OK) return fail(s, err);
         }
         if (keyed) {
@@ -257,6 +288,8 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
     st.sgprs = co.sgprs;
     st.scratch_bytes = co.scratch_bytes;
     st.lds_bytes = co.lds_bytes;
+    st.waves_hint = p.plan.waves_per_simd;
+    st.vgpr_spills = co.vgpr_spills;
     std::lock_guard<std::mutex> g(g_mu);
     perm_status s = ensure_device();
     if (s != PERM_OK) return s;
@@ -509,8 +542,10 @@ perm_status perm_compile_info(const perm_csc *a, const perm_opts *opts, perm_sta
     if (p.singular) return PERM_OK;
     CodeObject co;
     std::string err;
-    s = compile_source(p.src, &co, &err);
+    s = compile_prepared(&p, o, &co, &err);
     if (s != PERM_OK) return fail(s, err);
+    st->waves_hint = p.plan.waves_per_simd;
+    st->vgpr_spills = co.vgpr_spills;
     st->compile_ms = co.compile_ms;
     st->cache_hit = co.cache_hit;
     st->vgprs = co.vgprs;

@@ -50,7 +50,7 @@ class PermOpts(ctypes.Structure):
                 ("batch_mode", ctypes.c_int32), ("batch_kappa_shift", ctypes.c_int32),
                 ("cold_tier", ctypes.c_int32), ("gr_ratio", ctypes.c_double),
                 ("hip_stream", ctypes.c_void_p), ("block_partials", ctypes.POINTER(ctypes.c_double)),
-                ("block_partials_cap", ctypes.c_int64), ("progress", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("block_partials_cap", ctypes.c_int64), ("progress", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
 
 
 class PermBatchStats(ctypes.Structure):
@@ -74,7 +74,7 @@ class PermStats(ctypes.Structure):
                 ("chunk_log2", ctypes.c_int32), ("unroll_log2", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("vgprs", ctypes.c_int32), ("sgprs", ctypes.c_int32), ("scratch_bytes", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("cache_hit", ctypes.c_int32),
-                ("singular", ctypes.c_int32)]
+                ("singular", ctypes.c_int32), ("waves_hint", ctypes.c_int32), ("vgpr_spills", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -177,7 +177,7 @@ def _stream_handle(stream):
 
 def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, force_k=0, force_c=0,
               max_levels=0, gr_ratio=0.0, stream=None, zero_skip="auto", batch_mode="streams",
-              batch_kappa_shift=0, cold_tier="global", progress=False):
+              batch_kappa_shift=0, cold_tier="global", progress=False, waves_per_simd=0):
     o = PermOpts()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.chunk_log2, o.unroll_log2, o.block = chunk_log2, unroll_log2, block
@@ -188,6 +188,7 @@ def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, 
     o.batch_kappa_shift = batch_kappa_shift
     o.cold_tier = {"global": 0, "lds": 1}[cold_tier]
     o.progress = 1 if progress else 0
+    o.waves_per_simd = waves_per_simd
     o.hip_stream = _stream_handle(stream)
     return o
 
