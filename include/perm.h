@@ -192,6 +192,44 @@ typedef struct {
 perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out,
                           perm_batch_stats *st);
 
+/* ---- Autotuning ---------------------------------------------------------- */
+
+typedef struct {
+    double default_ms;      /* device time of the starting options on the sample */
+    double best_ms;         /* device time of the returned options on the sample */
+    double sample_fraction; /* fraction of the work each candidate ran (batch: 1) */
+    double tune_ms;         /* wall time of the whole search, compiles included */
+    int32_t candidates;     /* option sets timed, the starting one included */
+    int32_t pad;
+} perm_tune_stats;
+
+/* Picks launch options for one matrix by timing its generated kernel: starting
+ * from opts (NULL = defaults), it tries in turn the register/global split
+ * (AUTO; HYBRID with Alg. 5's partition and the cold rows in global memory or
+ * in LDS), the chunk size (log2 of the Gray steps per lane, +-1 and +-2 around
+ * the current), the static block (+-1), the threads per workgroup (64, 128,
+ * 256) and the compiled occupancy (-1, 4, 5, 6), keeping a candidate only if
+ * it is at least 2 % faster.  Every candidate runs on the same sample of the
+ * Gray-index space: 16 evenly spaced slices, each of 2^16 chunks of the
+ * largest candidate chunk (so every candidate fills the GPU), or the whole
+ * space when that is no larger; best of 3 passes (one pass above 100 ms).
+ * Candidates that the planner rejects are skipped.  *best receives the winning options (pass them to
+ * perm_sparse_ex); candidates' plans and code stay in the plan cache.  The
+ * result of the permanent does not depend on these options beyond FP64
+ * rounding (bitwise for the occupancy).  The paper takes the thread count
+ * from the occupancy API (Alg. 3) and Alg. 5's GRratio from preliminary
+ * benchmarks; here the launch shape and the split are chosen by timing. */
+perm_status perm_autotune(const perm_csc *a, const perm_opts *opts, perm_opts *best, perm_tune_stats *st);
+
+/* Picks perm_batch options for a batch by running it whole: the launch form
+ * (batch_mode 0, instances on their own streams, or 1, one captured graph)
+ * and then batch_kappa_shift (+-1, +-2), each kept if at least 2 % faster
+ * in device time (best of 3 runs).  Results are bitwise independent of
+ * batch_mode; batch_kappa_shift changes the chunking, so results may differ
+ * in the last bits. */
+perm_status perm_batch_autotune(int32_t count, const perm_csc *mats, const perm_opts *opts, perm_opts *best,
+                                perm_tune_stats *st);
+
 /* ---- Serving: submit / poll with continuous batching ------------------- */
 
 /* A server owns a scheduler thread, a device-memory arena of

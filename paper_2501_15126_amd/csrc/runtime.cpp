@@ -242,11 +242,9 @@ bool plan_key(const perm_csc *m, const perm_opts &o, std::string *key) {
     return true;
 }
 
-perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_stats *st_out) {
-    auto t0 = std::chrono::steady_clock::now();
-    perm_stats st;
-    memset(&st, 0, sizeof st);
-    const perm_opts o = defaults(opts);
+// The plan and code object for (m, o): from the plan cache, else prepared,
+// compiled and cached.
+perm_status acquire_plan(const perm_csc *m, const perm_opts &o, std::shared_ptr<CachedPlan> *out, bool *hit) {
     std::string key;
     const bool keyed = plan_key(m, o, &key);
     std::shared_ptr<CachedPlan> cp;
@@ -255,7 +253,7 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
         auto it = g_plan_cache.find(key);
         if (it != g_plan_cache.end()) cp = it->second;
     }
-    const bool plan_hit = cp != nullptr;
+    *hit = cp != nullptr;
     if (!cp) {
         cp = std::make_shared<CachedPlan>();
         perm_status s = prepare(m, o, &cp->p, true);
@@ -270,6 +268,21 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
             if (g_plan_cache.size() >= kPlanCacheMax) g_plan_cache.clear();
             g_plan_cache.emplace(key, cp);
         }
+    }
+    *out = std::move(cp);
+    return PERM_OK;
+}
+
+perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_stats *st_out) {
+    auto t0 = std::chrono::steady_clock::now();
+    perm_stats st;
+    memset(&st, 0, sizeof st);
+    const perm_opts o = defaults(opts);
+    std::shared_ptr<CachedPlan> cp;
+    bool plan_hit = false;
+    {
+        perm_status s = acquire_plan(m, o, &cp, &plan_hit);
+        if (s != PERM_OK) return s;
     }
     const Prepared &p = cp->p;
     const CodeObject &co = cp->co;
@@ -380,6 +393,320 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
     return PERM_OK;
 }
 
+// ---- autotuner -------------------------------------------------------------
+
+// The part of the Gray-index space every tuning candidate is timed on:
+// `slices` slices of 2^slice_log2 indices starting at s * 2^(n-1) / slices.
+// A slice holds at least 2^16 chunks of the largest candidate chunk (256
+// workgroups of 256 lanes, so the 16 slices give every CU 16 workgroups, as
+// a full run does); when 16 such slices would cover the whole space, the
+// whole space is the sample.
+struct TuneSample {
+    int slices = 1;
+    int slice_log2 = 0;
+};
+
+constexpr int kTuneSlicesLog2 = 4;
+constexpr int kTuneSliceChunksLog2 = 16;
+
+TuneSample tune_sample(int n, int max_kappa) {
+    TuneSample t;
+    const int total = n - 1;
+    const int q = max_kappa + kTuneSliceChunksLog2;
+    if (q + kTuneSlicesLog2 >= total) {
+        t.slices = 1;
+        t.slice_log2 = total;
+    } else {
+        t.slices = 1 << kTuneSlicesLog2;
+        t.slice_log2 = q;
+    }
+    return t;
+}
+
+// One pass of the plan's kernel over the sample: device time between events
+// around the launches, and the sample's Gray-term sum (hi, lo).  g_mu held.
+perm_status time_sample(CachedPlan &cp, const TuneSample &ts, hipStream_t stream, float *ms, double sum[2]) {
+    const Plan &pl = cp.p.plan;
+    if (!cp.kern) {
+        perm_status s = load_kernel(cp.p.src, cp.co, pl.block, &cp.kern);
+        if (s != PERM_OK) return s;
+    }
+    const int total = pl.n - 1;
+    if (pl.kappa > ts.slice_log2) return fail(PERM_EINVAL, "chunk larger than the tuning sample's slices");
+    const uint64_t chunks_per_slice = 1ull << (ts.slice_log2 - pl.kappa);
+    const uint64_t B = (uint64_t)pl.block;
+    const int64_t blocks_per_slice = (int64_t)((chunks_per_slice + B - 1) / B);
+    const int64_t launch_blocks = std::min<int64_t>(blocks_per_slice, kMaxBlocksPerLaunch);
+    const int64_t nblocks = blocks_per_slice * ts.slices;
+    perm_status s = ensure_buffer(&g_dev.partials, &g_dev.partials_cap, 2 * (size_t)nblocks);
+    if (s != PERM_OK) return s;
+    s = ensure_buffer(reinterpret_cast<double **>(&g_dev.counts), &g_dev.counts_cap, (size_t)nblocks);
+    if (s != PERM_OK) return s;
+    const uint64_t xs = (uint64_t)launch_blocks * B;
+    if (pl.cold && !pl.cold_lds) {
+        s = ensure_buffer(&g_dev.xg, &g_dev.xg_cap, (size_t)(pl.n - pl.k) * xs);
+        if (s != PERM_OK) return s;
+    }
+    HIP_TRY(hipEventRecord(g_dev.ev[0], stream));
+    int64_t off = 0;
+    for (int sl = 0; sl < ts.slices; ++sl) {
+        // first chunk of slice sl: (sl * 2^(total - log2 slices)) >> kappa
+        const uint64_t g0 = ts.slices == 1 ? 0 : (uint64_t)sl << (total - kTuneSlicesLog2);
+        const uint64_t c0 = g0 >> pl.kappa;
+        uint64_t chunk_end = c0 + chunks_per_slice;
+        for (int64_t b = 0; b < blocks_per_slice; b += launch_blocks) {
+            const int64_t nb = std::min<int64_t>(launch_blocks, blocks_per_slice - b);
+            uint64_t chunk_begin = c0 + (uint64_t)b * B;
+            double *part = g_dev.partials + 2 * off;
+            unsigned long long *cnt = g_dev.counts + off;
+            double *xg = g_dev.xg;
+            uint64_t xs_arg = xs;
+            void *args[] = {&chunk_begin, &chunk_end, &part, &cnt, &xg, &xs_arg};
+            HIP_TRY(hipModuleLaunchKernel(cp.kern->fn, (unsigned)nb, 1, 1, (unsigned)B, 1, 1, 0, stream, args,
+                                          nullptr));
+            off += nb;
+        }
+    }
+    HIP_TRY(hipEventRecord(g_dev.ev[1], stream));
+    unsigned long long *count_out = reinterpret_cast<unsigned long long *>(g_dev.out + 2);
+    HIP_TRY(launch_final_reduce(g_dev.partials, g_dev.counts, (long long)nblocks, g_dev.out, count_out, stream));
+    HIP_TRY(hipMemcpyAsync(g_dev.host_out, g_dev.out, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipEventElapsedTime(ms, g_dev.ev[0], g_dev.ev[1]));
+    sum[0] = g_dev.host_out[0];
+    sum[1] = g_dev.host_out[1];
+    return PERM_OK;
+}
+
+// Relative gain a candidate must show over the current best to be adopted
+// (the spread of repeated sample timings is below 1 %).
+constexpr double kTuneMinGain = 0.02;
+constexpr int kTuneRepeats = 3;
+constexpr double kTuneLongPassMs = 100.0;
+
+perm_status autotune_one(const perm_csc *a, const perm_opts *opts, perm_opts *best, perm_tune_stats *ts_out) {
+    const auto t0 = std::chrono::steady_clock::now();
+    perm_tune_stats ts;
+    memset(&ts, 0, sizeof ts);
+    perm_opts cur = defaults(opts);
+    cur.block_partials = nullptr;
+    cur.block_partials_cap = 0;
+    cur.progress = 0;
+    TuneSample smp;  // set from the starting plan's chunk size
+    // sampled device time of one option set; the resolved plan in *pl
+    auto eval = [&](const perm_opts &c, double *ms, Plan *pl, bool *singular) -> perm_status {
+        std::shared_ptr<CachedPlan> cp;
+        bool hit = false;
+        perm_status s = acquire_plan(a, c, &cp, &hit);
+        if (s != PERM_OK) return s;
+        *singular = cp->p.singular;
+        if (cp->p.singular) return PERM_OK;
+        if (pl) *pl = cp->p.plan;
+        std::lock_guard<std::mutex> g(g_mu);
+        s = ensure_device();
+        if (s != PERM_OK) return s;
+        hipStream_t stream = c.hip_stream ? (hipStream_t)c.hip_stream : g_dev.stream;
+        if (smp.slice_log2 == 0) smp = tune_sample(cp->p.plan.n, cp->p.plan.kappa + 2);
+        double bestms = std::numeric_limits<double>::infinity();
+        for (int r = 0; r < kTuneRepeats; ++r) {
+            float t = 0;
+            double sum[2];
+            s = time_sample(*cp, smp, stream, &t, sum);
+            if (s != PERM_OK) return s;
+            bestms = std::min(bestms, (double)t);
+            if (t > kTuneLongPassMs) break;  // one pass of a long sample is enough
+        }
+        *ms = bestms;
+        ts.candidates++;
+        return PERM_OK;
+    };
+    Plan plan;
+    bool singular = false;
+    double best_ms = 0;
+    perm_status s = eval(cur, &best_ms, &plan, &singular);
+    if (s != PERM_OK) return s;
+    if (singular) {
+        *best = cur;
+        ts.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (ts_out) *ts_out = ts;
+        return PERM_OK;
+    }
+    ts.default_ms = best_ms;
+    ts.sample_fraction = std::ldexp((double)smp.slices, smp.slice_log2 - (plan.n - 1));
+    // try each candidate of one dimension against the current best; keep the
+    // fastest if it gains at least kTuneMinGain
+    auto try_dim = [&](const std::vector<perm_opts> &cands) -> perm_status {
+        const perm_opts *win = nullptr;
+        double win_ms = best_ms * (1.0 - kTuneMinGain);
+        Plan win_plan;
+        for (const perm_opts &c : cands) {
+            double ms = 0;
+            Plan pl;
+            bool sg = false;
+            perm_status r = eval(c, &ms, &pl, &sg);
+            if (r == PERM_EINVAL || r == PERM_ECOMPILE) continue;  // not a valid shape here
+            if (r != PERM_OK) return r;
+            if (ms < win_ms) {
+                win = &c;
+                win_ms = ms;
+                win_plan = pl;
+            }
+        }
+        if (win) {
+            cur = *win;
+            best_ms = win_ms;
+            plan = win_plan;
+        }
+        return PERM_OK;
+    };
+    std::vector<perm_opts> cands;
+    // 1. register / global split: AUTO (all rows in VGPRs), HYBRID with the
+    //    cold rows in global memory or in LDS
+    if (cur.mode == PERM_MODE_AUTO || cur.mode == PERM_MODE_HYBRID) {
+        cands.clear();
+        perm_opts c = cur;
+        c.chunk_log2 = c.unroll_log2 = c.block = 0;
+        if (cur.mode == PERM_MODE_AUTO) {
+            c.mode = PERM_MODE_HYBRID;
+            c.cold_tier = 0;
+            cands.push_back(c);
+            c.cold_tier = 1;
+            cands.push_back(c);
+        } else {
+            c.mode = PERM_MODE_AUTO;
+            c.cold_tier = 0;
+            cands.push_back(c);
+            c.mode = PERM_MODE_HYBRID;
+            c.cold_tier = cur.cold_tier == 1 ? 0 : 1;
+            cands.push_back(c);
+        }
+        s = try_dim(cands);
+        if (s != PERM_OK) return s;
+    }
+    // 2. chunk size (log2 of Gray steps per lane)
+    cands.clear();
+    for (int d : {-2, -1, 1, 2}) {
+        const int k = plan.kappa + d;
+        if (k < 1 || k > smp.slice_log2) continue;
+        perm_opts c = cur;
+        c.chunk_log2 = k;
+        cands.push_back(c);
+    }
+    s = try_dim(cands);
+    if (s != PERM_OK) return s;
+    // 3. static block (log2 of unrolled steps)
+    cands.clear();
+    for (int d : {-1, 1}) {
+        const int u = plan.u + d;
+        if (u < 1 || u > plan.kappa - 1) continue;
+        perm_opts c = cur;
+        c.chunk_log2 = plan.kappa;
+        c.unroll_log2 = u;
+        cands.push_back(c);
+    }
+    s = try_dim(cands);
+    if (s != PERM_OK) return s;
+    // 4. threads per workgroup
+    cands.clear();
+    for (int b : {64, 128, 256}) {
+        if (b == plan.block) continue;
+        perm_opts c = cur;
+        c.chunk_log2 = plan.kappa;
+        c.unroll_log2 = plan.u;
+        c.block = b;
+        cands.push_back(c);
+    }
+    s = try_dim(cands);
+    if (s != PERM_OK) return s;
+    // 5. occupancy the kernel is compiled for
+    cands.clear();
+    for (int w : {-1, 4, 5, 6}) {
+        if (w == plan.waves_per_simd || (w == -1 && plan.waves_per_simd == 0)) continue;
+        perm_opts c = cur;
+        c.chunk_log2 = plan.kappa;
+        c.unroll_log2 = plan.u;
+        c.block = plan.block;
+        c.waves_per_simd = w;
+        cands.push_back(c);
+    }
+    s = try_dim(cands);
+    if (s != PERM_OK) return s;
+    *best = cur;
+    ts.best_ms = best_ms;
+    ts.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (ts_out) *ts_out = ts;
+    return PERM_OK;
+}
+
+perm_status autotune_batch(int32_t count, const perm_csc *mats, const perm_opts *opts, perm_opts *best,
+                           perm_tune_stats *ts_out) {
+    const auto t0 = std::chrono::steady_clock::now();
+    perm_tune_stats ts;
+    memset(&ts, 0, sizeof ts);
+    perm_opts cur = defaults(opts);
+    if (cur.batch_mode == 2) cur.batch_mode = 0;  // the sequential baseline is not a candidate
+    std::vector<double> out((size_t)std::max(count, 1));
+    // device time of the whole batch (the better of kTuneRepeats runs)
+    auto eval = [&](const perm_opts &c, double *ms) -> perm_status {
+        double b = std::numeric_limits<double>::infinity();
+        for (int r = 0; r < kTuneRepeats; ++r) {
+            perm_batch_stats bs;
+            perm_status s = perm_batch_ex(count, mats, &c, out.data(), &bs);
+            if (s != PERM_OK) return s;
+            b = std::min(b, bs.kernel_ms);
+        }
+        *ms = b;
+        ts.candidates++;
+        return PERM_OK;
+    };
+    double best_ms = 0;
+    perm_status s = eval(cur, &best_ms);
+    if (s != PERM_OK) return s;
+    ts.default_ms = best_ms;
+    ts.sample_fraction = 1.0;
+    auto try_all = [&](const std::vector<perm_opts> &cands) -> perm_status {
+        int win = -1;
+        double win_ms = best_ms * (1.0 - kTuneMinGain);
+        for (size_t i = 0; i < cands.size(); ++i) {
+            double ms = 0;
+            perm_status r = eval(cands[i], &ms);
+            if (r != PERM_OK) return r;
+            if (ms < win_ms) {
+                win = (int)i;
+                win_ms = ms;
+            }
+        }
+        if (win >= 0) {
+            cur = cands[(size_t)win];
+            best_ms = win_ms;
+        }
+        return PERM_OK;
+    };
+    // launch form: instances on their own streams, or captured as one graph
+    std::vector<perm_opts> cands;
+    {
+        perm_opts c = cur;
+        c.batch_mode = cur.batch_mode == 1 ? 0 : 1;
+        cands.push_back(c);
+    }
+    s = try_all(cands);
+    if (s != PERM_OK) return s;
+    // chunk size: shift of the per-matrix chunk log2
+    cands.clear();
+    for (int d : {-2, -1, 1, 2}) {
+        perm_opts c = cur;
+        c.batch_kappa_shift = cur.batch_kappa_shift + d;
+        cands.push_back(c);
+    }
+    s = try_all(cands);
+    if (s != PERM_OK) return s;
+    *best = cur;
+    ts.best_ms = best_ms;
+    ts.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (ts_out) *ts_out = ts;
+    return PERM_OK;
+}
+
 }  // namespace
 
 void permx::set_last_error(const std::string &msg) { t_err = msg; }
@@ -396,6 +723,18 @@ double perm_sparse(int32_t n, const int32_t *colptr, const int32_t *rowidx, cons
 perm_status perm_sparse_ex(const perm_csc *a, const perm_opts *opts, double *out, perm_stats *st) {
     if (!out) return fail(PERM_EINVAL, "null output pointer");
     return run_one(a, opts, out, st);
+}
+
+perm_status perm_autotune(const perm_csc *a, const perm_opts *opts, perm_opts *best, perm_tune_stats *st) {
+    if (!best) return fail(PERM_EINVAL, "null output options");
+    return autotune_one(a, opts, best, st);
+}
+
+perm_status perm_batch_autotune(int32_t count, const perm_csc *mats, const perm_opts *opts, perm_opts *best,
+                                perm_tune_stats *st) {
+    if (!best) return fail(PERM_EINVAL, "null output options");
+    if (count < 1 || !mats) return fail(PERM_EINVAL, "bad batch arguments");
+    return autotune_batch(count, mats, opts, best, st);
 }
 
 perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out,

@@ -105,6 +105,18 @@ _lib.perm_batch_describe.restype = ctypes.c_int
 _lib.perm_batch_describe.argtypes = [_P(PermCsc), _P(PermOpts), _P(ctypes.c_int32), _P(ctypes.c_double),
                                      ctypes.c_size_t, _P(ctypes.c_size_t), _P(ctypes.c_int32), ctypes.c_size_t,
                                      _P(ctypes.c_size_t)]
+class PermTuneStats(ctypes.Structure):
+    _fields_ = [("default_ms", ctypes.c_double), ("best_ms", ctypes.c_double), ("sample_fraction", ctypes.c_double),
+                ("tune_ms", ctypes.c_double), ("candidates", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+
+
+_lib.perm_autotune.restype = ctypes.c_int
+_lib.perm_autotune.argtypes = [_P(PermCsc), _P(PermOpts), _P(PermOpts), _P(PermTuneStats)]
+_lib.perm_batch_autotune.restype = ctypes.c_int
+_lib.perm_batch_autotune.argtypes = [ctypes.c_int32, _P(PermCsc), _P(PermOpts), _P(PermOpts), _P(PermTuneStats)]
 _lib.perm_last_error.restype = ctypes.c_char_p
 _lib.perm_last_error.argtypes = []
 _lib.perm_version.restype = ctypes.c_char_p
@@ -136,7 +148,7 @@ _lib.perm_server_destroy.argtypes = [ctypes.c_void_p]
 EXPORTED = ["perm_sparse", "perm_sparse_ex", "perm_batch", "perm_batch_ex", "perm_server_create", "perm_submit",
             "perm_poll", "perm_wait", "perm_server_get_stats", "perm_server_destroy", "perm_batch_describe",
             "perm_plan", "perm_partition", "perm_codegen",
-            "perm_compile_info", "perm_last_error", "perm_version"]
+            "perm_compile_info", "perm_autotune", "perm_batch_autotune", "perm_last_error", "perm_version"]
 
 
 def library():
@@ -237,6 +249,41 @@ def perm_batch_ex(mats, **opts):
     _check(_lib.perm_batch_ex(len(held), arr, ctypes.byref(o), out.ctypes.data_as(_P(ctypes.c_double)),
                               ctypes.byref(st)))
     return out[:len(held)], st.as_dict()
+
+
+def _opts_kwargs(o):
+    """make_opts keyword arguments that rebuild the tuning fields of o."""
+    inv = {v: k for k, v in MODES.items()}
+    return {"mode": inv.get(o.mode, o.mode), "chunk_log2": o.chunk_log2, "unroll_log2": o.unroll_log2,
+            "block": o.block, "vgpr_budget": o.vgpr_budget, "force_k": o.force_k, "force_c": o.force_c,
+            "max_levels": o.max_levels, "gr_ratio": o.gr_ratio,
+            "zero_skip": {0: "auto", 1: True, -1: False}[o.zero_skip],
+            "batch_mode": {0: "streams", 1: "graph", 2: "sequential", 3: "one_stream"}[o.batch_mode],
+            "batch_kappa_shift": o.batch_kappa_shift, "cold_tier": {0: "global", 1: "lds"}[o.cold_tier],
+            "waves_per_simd": o.waves_per_simd}
+
+
+def perm_autotune(ccs, **opts):
+    """Times candidate launch options for one matrix (perm_autotune); returns
+    (keyword options for perm_sparse_ex, tuning stats dict)."""
+    m = _Csc(ccs)
+    o = make_opts(**opts)
+    best = PermOpts()
+    st = PermTuneStats()
+    _check(_lib.perm_autotune(ctypes.byref(m.c), ctypes.byref(o), ctypes.byref(best), ctypes.byref(st)))
+    return _opts_kwargs(best), st.as_dict()
+
+
+def perm_batch_autotune(mats, **opts):
+    """Times candidate perm_batch options on the batch (perm_batch_autotune);
+    returns (keyword options for perm_batch_ex, tuning stats dict)."""
+    held = [_Csc(c) for c in mats]
+    arr = (PermCsc * max(1, len(held)))(*[h.c for h in held])
+    o = make_opts(**opts)
+    best = PermOpts()
+    st = PermTuneStats()
+    _check(_lib.perm_batch_autotune(len(held), arr, ctypes.byref(o), ctypes.byref(best), ctypes.byref(st)))
+    return _opts_kwargs(best), st.as_dict()
 
 
 def perm_plan(ccs, **opts):

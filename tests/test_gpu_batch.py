@@ -117,3 +117,22 @@ def test_batch_edge_cases(P, oracle_mod):
     with pytest.raises(P.PermError) as e:
         P.perm_batch([ones[0], (2, np.array([0, 1, 1]), np.array([5]), np.array([1.0]))])
     assert e.value.status == P.PERM_EINVAL and "matrix 1" in str(e.value)
+
+
+def test_batch_autotune(P, oracle_mod):
+    """perm_batch_autotune runs the batch per candidate (launch form, chunk
+    shift) and returns options whose results agree with the oracle."""
+    O = oracle_mod
+    mats = _mixed(5, 48)
+    opts, st = P.perm_batch_autotune(mats)
+    print("batch autotune", opts, st, flush=True)
+    assert st["candidates"] == 6 and st["sample_fraction"] == 1.0
+    assert 0.0 < st["best_ms"] <= st["default_ms"]
+    assert opts["batch_mode"] in ("streams", "graph") and -2 <= opts["batch_kappa_shift"] <= 2
+    got = P.perm_batch(mats, **opts)
+    for i, ccs in enumerate(mats):
+        if O.structural_rank(ccs) < ccs[0]:
+            assert got[i] == 0.0
+            continue
+        ref, abs_sum = O.perm_nw(ccs)
+        assert abs(got[i] - ref) <= _tol(ccs[0], ref, abs_sum), (i, got[i], ref)

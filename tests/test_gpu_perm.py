@@ -38,9 +38,11 @@ def _golden():
 
 def test_device_and_resources(P, oracle_mod):
     ccs = W.single_01(40, 0.10, 1)
-    info = P.compile_info(ccs)
+    info = P.compile_info(ccs, waves_per_simd=-1)
     assert info["scratch_bytes"] == 0, "generated kernel spills to scratch"
     assert info["vgprs"] <= 128
+    auto = P.compile_info(ccs)  # the automatic occupancy: 5 waves with a small spill, or as above
+    assert auto["scratch_bytes"] <= 128 and auto["vgprs"] <= 128
     got, st = P.perm_sparse_ex(W.single_01(12, 0.3, 0))
     assert st["waves_per_simd"] >= 1
     print("vgprs", info["vgprs"], "levels", info["levels"], "occupancy", st["waves_per_simd"])
@@ -305,3 +307,42 @@ def test_zero_skip_is_exact(P, oracle_mod):
     ref, abs_sum = O.perm_nw(ccs)
     on, _ = P.perm_sparse_ex(ccs, zero_skip=True)
     assert abs(on - ref) <= _tol(20, ref, abs_sum)
+
+
+def test_occupancy_choice_is_bitwise_neutral(P):
+    """The occupancy the kernel is compiled for changes registers and spills,
+    not the arithmetic: every choice gives the same bits."""
+    for ccs in (W.single_01(40, 0.10, 1), W.single_real(30, 0.30, 2)):
+        vals = {}
+        for w in (0, -1, 4, 5, 6):
+            got, st = P.perm_sparse_ex(ccs, waves_per_simd=w)
+            print("occupancy", ccs[0], w, got, st["vgprs"], st["scratch_bytes"], st["waves_per_simd"],
+                  st["waves_hint"], st["kernel_ms"], flush=True)
+            vals[w] = got
+        assert len(set(vals.values())) == 1, vals
+
+
+def test_autotune_single(P, oracle_mod):
+    """perm_autotune times candidates on a sample of the Gray-index space and
+    returns options that run and give the same permanent (exact for 0/1; the
+    oracle's tolerance for a real matrix)."""
+    O = oracle_mod
+    ccs = W.single_01(40, 0.10, 1)
+    opts, st = P.perm_autotune(ccs)
+    print("autotune n40", opts, st, flush=True)
+    assert st["candidates"] >= 8 and 0.0 < st["best_ms"] <= st["default_ms"]
+    assert st["sample_fraction"] == 0.5  # chunks up to 2^(16 + 2): 16 slices of 2^(18 + 16) of 2^39
+    got, _ = P.perm_sparse_ex(ccs, **opts)
+    assert got == 4022060880.0
+    # a sampled search: n = 44, 16 slices of 2^(kappa + 2 + 16) of 2^43 Gray indices
+    big = W.single_01(44, 0.10, 2)
+    opts, st = P.perm_autotune(big, zero_skip=False)
+    print("autotune n44", opts, st, flush=True)
+    assert 0.0 < st["sample_fraction"] < 1.0 and st["best_ms"] <= st["default_ms"]
+    small = W.random_sparse(20, 0.3, seed=77, kind="real")
+    ref, abs_sum = O.perm_nw(small)
+    opts, st = P.perm_autotune(small)
+    print("autotune n20", opts, st, flush=True)
+    assert st["sample_fraction"] == 1.0
+    got, _ = P.perm_sparse_ex(small, **opts)
+    assert abs(got - ref) <= _tol(20, ref, abs_sum)
