@@ -395,3 +395,31 @@ def test_batch_limits(P):
     with pytest.raises(P.PermError) as e:
         P.batch_describe(W.random_sparse(45, 0.2, seed=45, kind="real", diag=True))
     assert e.value.status == P.PERM_ETOOBIG
+
+
+def test_tuned_options_round_trip(P):
+    """The autotuners return a perm_opts; the binding turns it into keyword
+    options that rebuild every tuning field exactly."""
+    o = P.make_opts(mode="hybrid", chunk_log2=15, unroll_log2=5, block=128, vgpr_budget=112, force_k=30,
+                    force_c=20, max_levels=9, gr_ratio=12.5, zero_skip=False, batch_mode="graph",
+                    batch_kappa_shift=-2, cold_tier="lds", waves_per_simd=5)
+    back = P.make_opts(**P._opts_kwargs(o))
+    for name, _ in P.PermOpts._fields_:
+        if name in ("hip_stream", "block_partials", "block_partials_cap", "progress"):
+            continue
+        assert getattr(back, name) == getattr(o, name), name
+
+
+def test_autotune_argument_errors(P):
+    """Argument checks of the tuning entry points run before any device use."""
+    import ctypes
+    lib = P.library()
+    ccs = W.single_01(12, 0.3, 0)
+    m = P._Csc(ccs)
+    st = P.PermTuneStats()
+    assert lib.perm_autotune(ctypes.byref(m.c), None, None, ctypes.byref(st)) == P.PERM_EINVAL
+    assert "null output" in P.last_error()
+    best = P.PermOpts()
+    assert lib.perm_batch_autotune(0, None, None, ctypes.byref(best), ctypes.byref(st)) == P.PERM_EINVAL
+    with pytest.raises(P.PermError):
+        P.compile_info(ccs, waves_per_simd=9)
