@@ -171,22 +171,32 @@ PAPER_TABLE3_CODEGEN_HYBRID = {
     (48, 1): 741.59, (48, 2): 1059.77, (48, 3): 1361.69, (48, 4): 1906.64, (48, 5): 2023.94}
 
 
-def er_grid_bench(ns, variants, seed=1):
+def er_grid_bench(ns, variants, seed=1, ps=None):
     """The paper's synthetic grid: one permanent per cell and kernel variant.
     The code is matrix-specific, so each call includes its hipRTC compile;
-    the kernel time (HIP events) and the compile time are reported apart."""
+    the kernel time (HIP events) and the compile time are reported apart.
+    Variant "tuned" runs perm_autotune first (its search time is reported as
+    tune_s) and then the permanent with the options it returns."""
     import paper_2501_15126_amd.perm as P
     from paper_2501_15126_amd import workloads as W
     rows = []
     for n, p in W.ER_GRID:
-        if n not in ns:
+        if n not in ns or (ps and int(round(10 * p)) not in ps):
             continue
         ccs = W.er_grid_matrix(n, p, seed)
         for var in variants:
-            mode, tier = {"auto": ("auto", "global"), "hybrid": ("hybrid", "global"),
-                          "hybrid-lds": ("hybrid", "lds")}[var]
+            tune = None
+            if var == "tuned":
+                opts, tune = P.perm_autotune(ccs)
+                print("grid cell n=%d p=%.1f tuned in %.1f s: %s" % (n, p, tune["tune_ms"] / 1e3, {
+                    k: opts[k] for k in ("mode", "cold_tier", "chunk_log2", "unroll_log2", "block",
+                                         "waves_per_simd")}), file=sys.stderr, flush=True)
+            else:
+                mode, tier = {"auto": ("auto", "global"), "hybrid": ("hybrid", "global"),
+                              "hybrid-lds": ("hybrid", "lds")}[var]
+                opts = {"mode": mode, "cold_tier": tier}
             t0 = time.perf_counter()
-            v, st = P.perm_sparse_ex(ccs, mode=mode, cold_tier=tier, progress=n >= 45)
+            v, st = P.perm_sparse_ex(ccs, progress=n >= 45, **opts)
             wall = time.perf_counter() - t0
             steps = 2.0 ** (n - 1)
             ks = st["kernel_ms"] / 1e3
@@ -196,7 +206,9 @@ def er_grid_bench(ns, variants, seed=1):
                    "fp64_issue_frac": st["ops_per_step"] * steps / ks / 3.93216e13,
                    "tflops": st["flops_per_step"] * steps / ks / 1e12, "vgprs": st["vgprs"],
                    "waves_per_simd": st["waves_per_simd"], "lds_bytes": st["lds_bytes"], "k": st["k"],
-                   "levels": st["levels"],
+                   "levels": st["levels"], "chunk_log2": st["chunk_log2"], "unroll_log2": st["unroll_log2"],
+                   "block": st["block"], "waves_hint": st["waves_hint"],
+                   "tune_s": tune["tune_ms"] / 1e3 if tune else None,
                    "paper_codegen_hybrid_a100_s": PAPER_TABLE3_CODEGEN_HYBRID[(n, int(round(10 * p)))]}
             print("grid cell n=%d p=%.1f %s: %.3f s kernel" % (n, p, var, ks), file=sys.stderr, flush=True)
             rows.append(row)
@@ -241,7 +253,9 @@ def main():
     ap.add_argument("--grid", default="",
                     help="run only the paper's synthetic grid for these n (comma list, e.g. 40,45,48)")
     ap.add_argument("--grid-variants", default="auto",
-                    help="kernel variants for --grid: auto, hybrid, hybrid-lds (comma list)")
+                    help="kernel variants for --grid: auto, hybrid, hybrid-lds, tuned (comma list)")
+    ap.add_argument("--grid-p", default="",
+                    help="restrict --grid to these densities, in tenths (comma list, e.g. 4,5)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batch-workload measurement (for profiling the batch kernels)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -266,7 +280,8 @@ def main():
 
     if args.grid:
         ns = [int(x) for x in args.grid.split(",")]
-        rows = er_grid_bench(ns, args.grid_variants.split(","), seed=args.seed)
+        ps = [int(x) for x in args.grid_p.split(",")] if args.grid_p else None
+        rows = er_grid_bench(ns, args.grid_variants.split(","), seed=args.seed, ps=ps)
         print(json.dumps({"er_grid": rows, "workload": "Erdos-Renyi n in %s, p in 0.1..0.5, U[0,1], seed %d"
                           % (ns, args.seed)}), flush=True)
         return

@@ -116,7 +116,8 @@ typedef struct {
                               -1: the compiler's own choice; 0 = automatic: the
                               compiler's choice, except that a kernel it holds to 4
                               waves (97..128 VGPRs) whose rows are not in LDS is
-                              compiled again for 5 waves, and that build is used if it
+                              compiled again for 5 waves, one held to 3 waves
+                              (129..168) again for 4, and that build is used if it
                               spills at most 128 bytes per lane */
 } perm_opts;
 

@@ -136,7 +136,7 @@ int auto_kappa(int n, bool zero_skip) {
     int kappa = total - (zero_skip ? 23 : 21);
     kappa = std::max(kappa, std::min(total, 8));
     kappa = std::min(kappa, zero_skip ? 16 : 14);
-    kappa = std::max(kappa, total - 29);
+    kappa = std::max(kappa, total - 31);  // at most 2^31 chunks (2^23 workgroups of partials)
     return std::min(kappa, std::min(total, 30));
 }
 

@@ -156,23 +156,24 @@ perm_status prepare(const perm_csc *m, const perm_opts &o, Prepared *p, bool wan
     return PERM_OK;
 }
 
-// Largest per-lane scratch accepted from the second, 5-wave build of the
-// automatic occupancy choice (16 doubles).
+// Largest per-lane scratch accepted from the second, higher-occupancy build
+// of the automatic occupancy choice (16 doubles).
 constexpr int kAutoWavesMaxScratch = 128;
 
 // Compiles p->src.  With the occupancy left automatic, a kernel that the
 // compiler holds to 4 waves per SIMD (97..128 VGPRs; 512 VGPRs per SIMD lane,
 // allocated in steps of 8) is generated and compiled again for 5 waves, and
-// that build replaces the first if it spills little: a fifth wave hides more
-// of the FP64 dependency and branch latency than the few spilled values cost.
-// Kernels with LDS-resident rows are left alone (their LDS use already bounds
-// the occupancy).
+// one held to 3 waves (129..168 VGPRs) again for 4; the second build replaces
+// the first if it spills little: one more wave hides more of the FP64
+// dependency and branch latency than the few spilled values cost.  Kernels
+// with LDS-resident rows are left alone (their LDS use already bounds the
+// occupancy).
 perm_status compile_prepared(Prepared *p, const perm_opts &o, CodeObject *co, std::string *err) {
     perm_status s = compile_source(p->src, co, err);
     if (s != PERM_OK || o.waves_per_simd != 0 || p->plan.cold_lds) return s;
-    if (co->vgprs <= 96 || co->vgprs > 128) return PERM_OK;
+    if (co->vgprs <= 96 || co->vgprs > 168) return PERM_OK;
     Plan q = p->plan;
-    q.waves_per_simd = 5;
+    q.waves_per_simd = co->vgprs <= 128 ? 5 : 4;
     std::string src5 = generate_source(q);
     CodeObject c5;
     std::string err5;
@@ -180,7 +181,7 @@ perm_status compile_prepared(Prepared *p, const perm_opts &o, CodeObject *co, st
     if (c5.scratch_bytes < 0 || c5.scratch_bytes > kAutoWavesMaxScratch) return PERM_OK;
     c5.compile_ms += co->compile_ms;
     c5.cache_hit = c5.cache_hit && co->cache_hit;
-    p->plan.waves_per_simd = 5;
+    p->plan.waves_per_simd = q.waves_per_simd;
     p->src = std::move(src5);
     *co = std::move(c5);
     return PERM_OK;

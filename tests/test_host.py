@@ -195,21 +195,22 @@ def test_codegen_hex_literals_exact(P):
 def test_codegen_resources(P):
     """hipRTC (gfx950) compiles without a GPU.  At the compiler's own occupancy
     x stays in VGPRs (no scratch); the automatic occupancy choice recompiles a
-    4-wave kernel (97..128 VGPRs) for 5 waves and keeps that build only if it
-    spills at most 128 bytes per lane."""
+    4-wave kernel (97..128 VGPRs) for 5 waves and a 3-wave one (129..168) for
+    4, and keeps that build only if it spills at most 128 bytes per lane."""
     for ccs in (W.single_01(40, 0.10, 1), W.single_real(36, 0.30, 1), W.single_01(24, 0.15, 1)):
         for mode in ("auto", "pure", "hybrid"):
             plain = P.compile_info(ccs, mode=mode, waves_per_simd=-1)
             assert plain["scratch_bytes"] == 0 and plain["waves_hint"] == 0, (ccs[0], mode)
             assert plain["vgprs"] <= 256
             auto = P.compile_info(ccs, mode=mode)
+            want = 5 if 96 < plain["vgprs"] <= 128 else 4 if 128 < plain["vgprs"] <= 168 else 0
             if auto["waves_hint"] == 0:
                 assert auto["vgprs"] == plain["vgprs"] and auto["scratch_bytes"] == 0
-                if 96 < plain["vgprs"] <= 128:  # the 5-wave build was rejected
-                    assert P.compile_info(ccs, mode=mode, waves_per_simd=5)["scratch_bytes"] > 128
+                if want:  # the higher-occupancy build was rejected
+                    assert P.compile_info(ccs, mode=mode, waves_per_simd=want)["scratch_bytes"] > 128
             else:
-                assert auto["waves_hint"] == 5 and 96 < plain["vgprs"] <= 128, (ccs[0], mode)
-                assert auto["vgprs"] <= 102 and auto["scratch_bytes"] <= 128
+                assert auto["waves_hint"] == want, (ccs[0], mode, plain["vgprs"])
+                assert auto["vgprs"] <= 512 // want and auto["scratch_bytes"] <= 128
         assert P.compile_info(ccs, waves_per_simd=-1)["vgprs"] <= 128
         # the LDS tier: cold rows in LDS ([row][lane]), at most 40 KiB per workgroup
         lds = P.compile_info(ccs, mode="hybrid", cold_tier="lds")
