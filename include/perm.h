@@ -119,6 +119,15 @@ typedef struct {
                               compiled again for 5 waves, one held to 3 waves
                               (129..168) again for 4, and that build is used if it
                               spills at most 128 bytes per lane */
+    int32_t block_queue;   /* zero-aware kernels: a block of 2^(u+1) - 1 steps that only some
+                              lanes of a wave need is queued (its start state, in LDS) and
+                              evaluated after the walks, one block per thread of the
+                              workgroup, instead of by the whole wave in place; a full queue
+                              falls back to in place.  Slots per wave: 8, 16, 32 or 64;
+                              0 = the most of those whose queue fits 32 KiB of LDS per
+                              workgroup; -1 = off.  Used where it applies (the block's rows
+                              in VGPRs, the queue within 32 KiB) */
+    int32_t pad;
 } perm_opts;
 
 /* Statistics of one call (all optional to read). */
@@ -209,8 +218,9 @@ typedef struct {
  * (AUTO; HYBRID with Alg. 5's partition and the cold rows in global memory or
  * in LDS), the chunk size (log2 of the Gray steps per lane, +-1 and +-2 around
  * the current), the static block (+-1), the threads per workgroup (64, 128,
- * 256) and the compiled occupancy (-1, 4, 5, 6), keeping a candidate only if
- * it is at least 2 % faster.  Every candidate runs on the same sample of the
+ * 256), the block queue of zero-aware kernels (off, 16, 32, 64 slots) and the
+ * compiled occupancy (-1, 4, 5, 6), keeping a candidate only if it is at
+ * least 2 % faster.  Every candidate runs on the same sample of the
  * Gray-index space: 16 evenly spaced slices, each of 2^16 chunks of the
  * largest candidate chunk (so every candidate fills the GPU), or the whole
  * space when that is no larger; best of 3 passes (one pass above 100 ms).

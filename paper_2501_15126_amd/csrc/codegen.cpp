@@ -23,6 +23,12 @@
 //    column that touches them, S_l = product of x over levels >= l is kept,
 //    and a flip of column j recomputes only the levels up to the highest
 //    level column j touches.  With one level this is the plain full product.
+//  * Zero-aware pruning (exact): intervals of Gray indices whose terms all
+//    have an exactly-zero factor in every lane are skipped.  A block of steps
+//    that only some lanes of a wave need is not evaluated in place: each
+//    needing lane queues the block's start state in LDS and takes the skip
+//    path; after the walks, the workgroup evaluates all queued blocks, one per
+//    thread, in a fixed order (so the sum stays deterministic).
 //  * Rows >= k (HYBRID) live in global memory, [row][lane] so that a wave's
 //    accesses are contiguous (Sec. V), or in LDS with the same layout per
 //    workgroup (the shared-memory tier the paper leaves to future work), and
@@ -57,6 +63,15 @@ struct Gen {
         level_rows.assign(p.nlevels, {});
         for (int r = 0; r < p.n; ++r) level_rows[p.row_level[r]].push_back(r);
     }
+
+    // Block queue: per wave kQueueSlots slots of the start state of a block
+    // pair (rows of levels <= qtop, then S_{qtop+1}, then the direction of
+    // the middle step), stored [field][slot].
+    bool use_queue = false;
+    int qslots = 0;
+    int qtop = 0;
+    std::vector<int> qrows;
+    int qfields() const { return (int)qrows.size() + 2; }
 
     std::string fresh() { return "t" + std::to_string(tmp++); }
     std::string xname(int r) const { return "x" + std::to_string(r); }
@@ -266,8 +281,67 @@ struct Gen {
         // LDS tier: the cold rows of a workgroup's lanes, [row][lane], so a
         // wave's accesses to one row are 64 consecutive doubles
         if (p.cold_lds) os << "__shared__ double xl[" << (n - k) * p.block << "];\n";
+        // Block queue: used where block pairs are pruned (zero-aware, u >= 1)
+        // and their rows all live in VGPRs, within 32 KiB of LDS per workgroup;
+        // at most 64 slots per wave, so the workgroup drains in one pass.
+        {
+            int bt = 0;
+            for (int j = 0; j <= u && j < n - 1; ++j) bt = std::max(bt, p.col_top[j]);
+            qtop = bt;
+            qrows.clear();
+            for (int r = 0; r < n; ++r)
+                if (p.row_level[r] <= bt) qrows.push_back(r);
+            // slots per wave: as given, or the most of 64, 32, 16, 8 that fit
+            auto fits = [&](int slots) { return (long)(p.block / 64) * qfields() * slots * 8 <= 32768; };
+            qslots = 0;
+            if (p.queue_slots > 0) {
+                if (fits(p.queue_slots)) qslots = p.queue_slots;
+            } else if (p.queue_slots == 0) {
+                for (int slots : {64, 32, 16, 8})
+                    if (fits(slots)) {
+                        qslots = slots;
+                        break;
+                    }
+            }
+            use_queue = qslots > 0 && kappa >= 1 && u >= 1 && u + 1 <= kappa && p.zero_skip && !p.cold &&
+                        bt + 1 <= L - 1;
+        }
+        const int QS = qslots;
+        if (use_queue) {
+            os << "__shared__ double bq[" << (p.block / 64) * qfields() * QS << "];\n";
+            os << "__shared__ u32 bqn[" << p.block / 64 << "];\n";
+        }
+        os << "constexpr u32 kBlockQueueWords = " << (use_queue ? qfields() * QS : 1) << "u;\n";
+        // block_eval: the 2^(u+1) - 1 steps of a queued block pair from its
+        // start state it[field * QS] (rows of levels <= qtop, S_{qtop+1}, the
+        // direction of the middle step), the same arithmetic as in place.
+        os << "__device__ __forceinline__ dd block_eval(const double* __restrict__ it, u32 &ev) {\n";
+        if (use_queue) {
+            for (size_t i = 0; i < qrows.size(); ++i)
+                os << "  double " << xname(qrows[i]) << " = it[" << i * QS << "];\n";
+            os << "  double S" << qtop + 1 << " = it[" << qrows.size() * QS << "];\n";
+            os << "  const double lsgn = it[" << (qrows.size() + 1) * QS << "];\n";
+            for (int l = qtop; l >= 1; --l) os << "  double S" << l << ";\n";
+            {
+                std::map<int, std::string> cur;
+                for (int l = qtop; l >= 1; --l) refresh_level(l, cur, "  ");
+            }
+            os << "  double acc0 = 0.0, acc1 = 0.0;\n";
+            os << "  ev += " << (2 * U - 1) << "u;\n";
+            static_block(false, "  ");
+            step(u, Sign::Lane, 1, 0, "  ");
+            static_block(true, "  ");
+            os << "  return two_sum(acc0, acc1);\n";
+        } else {
+            os << "  (void)it; (void)ev;\n  dd r; r.h = 0.0; r.l = 0.0; return r;\n";
+        }
+        os << "}\n";
+        // perm_lane: `act` is false for a lane past the last chunk (it queues
+        // nothing); qw is this wave's queue region and qc its fill (uniform).
         os << "__device__ __forceinline__ dd perm_lane(const u64 m, double* __restrict__ xg, const u64 xs,\n"
-              "                                        const u64 lid, u32 &ev) {\n";
+              "                                        const u64 lid, const bool act, double* __restrict__ qw,\n"
+              "                                        u32 &qc, u32 &ev) {\n";
+        if (!use_queue) os << "  (void)act; (void)qw; (void)qc;\n";
         os << "  ev = 1u;\n";
         os << "  const u64 g0 = m << "
            << kappa
@@ -357,7 +431,30 @@ struct Gen {
             auto block_pair = [&](const char *posv, const char *ind) {
                 std::string in2 = std::string(ind) + "  ";
                 if (skip_block) {
-                    os << ind << "if (__all(S" << block_top + 1 << " == 0.0)) {\n";
+                    if (use_queue) {
+                        // lanes that need this block queue its start state and
+                        // skip it like the rest; a full queue evaluates in place
+                        const std::string in3 = in2 + "  ";
+                        os << ind << "const bool need = act && (S" << block_top + 1 << " != 0.0);\n";
+                        os << ind << "const u64 bal = __ballot(need);\n";
+                        os << ind << "const u32 nk = (u32)__popcll(bal);\n";
+                        os << ind << "if (nk == 0u || qc + nk <= " << QS << "u) {\n";
+                        os << in2 << "if (need) {\n";
+                        os << in3 << "const u32 sl = qc + __builtin_amdgcn_mbcnt_hi((u32)(bal >> 32), "
+                                     "__builtin_amdgcn_mbcnt_lo((u32)bal, 0u));\n";
+                        for (size_t i = 0; i < qrows.size(); ++i)
+                            os << in3 << "qw[" << i * QS << "u + sl] = " << xname(qrows[i]) << ";\n";
+                        os << in3 << "qw[" << qrows.size() * QS << "u + sl] = S" << block_top + 1 << ";\n";
+                        os << in3 << "qw[" << (qrows.size() + 1) * QS << "u + sl] = ";
+                        if (u + 1 == kappa)
+                            os << "lsgn;\n";
+                        else
+                            os << "((" << posv << " >> " << (u + 1) << ") & 1u) ? -1.0 : 1.0;\n";
+                        os << in2 << "}\n";
+                        os << in2 << "qc += nk;\n";
+                    } else {
+                        os << ind << "if (__all(S" << block_top + 1 << " == 0.0)) {\n";
+                    }
                     std::map<int, std::string> cur;
                     if (u + 1 == kappa) {
                         update(u, Sign::Lane, cur, in2.c_str());
@@ -465,22 +562,44 @@ struct Gen {
               "  const bool active = chunk_begin + lid < chunk_end;\n"
               "  // an inactive lane (past the last chunk) replays a valid chunk and contributes 0\n"
               "  const u64 m = active ? chunk_begin + lid : chunk_begin;\n"
-              "  u32 ev = 0u;\n"
-              "  dd cs = perm_lane(m, xg, xs, lid, ev);\n"
-              "  if (!active) { cs.h = 0.0; cs.l = 0.0; }\n"
+              "  const u32 wid = threadIdx.x >> 6;\n"
+              "  u32 ev = 0u, qc = 0u;\n";
+        if (use_queue)
+            os << "  double* qw = bq + wid * " << qfields() * QS << "u;\n";
+        else
+            os << "  double* qw = nullptr;\n";
+        os << "  dd cs = perm_lane(m, xg, xs, lid, active, qw, qc, ev);\n"
+              "  if (!active) { cs.h = 0.0; cs.l = 0.0; }\n";
+        if (use_queue) {
+            // the workgroup's queued blocks, item g (waves in order, then
+            // slots) evaluated by thread g: at most 64 per wave, so one pass
+            os << "  if ((threadIdx.x & 63u) == 0u) bqn[wid] = qc;\n"
+                  "  __syncthreads();\n"
+                  "  {\n"
+                  "    u32 total = 0u;\n"
+                  "    for (int w = 0; w < " << nw << "; ++w) total += bqn[w];\n"
+                  "    const u32 g = threadIdx.x;\n"
+                  "    if (g < total) {\n"
+                  "      u32 ww = 0u, b0 = 0u;\n"
+                  "      while (g >= b0 + bqn[ww]) { b0 += bqn[ww]; ++ww; }\n"
+                  "      cs = dd_add(cs, block_eval(bq + ww * " << qfields() * QS << "u + (g - b0), ev));\n"
+                  "    }\n"
+                  "  }\n";
+        }
+        os << "  u64 e64 = ev;  // terms this lane evaluated\n"
               "  for (int off = 32; off > 0; off >>= 1) {\n"
               "    dd o; o.h = __shfl_xor(cs.h, off, 64); o.l = __shfl_xor(cs.l, off, 64);\n"
               "    cs = dd_add(cs, o);\n"
+              "    e64 += __shfl_xor(e64, off, 64);\n"
               "  }\n";
         os << "  __shared__ double wsum[" << 2 * nw << "];\n"
-              "  __shared__ u32 wev[" << nw << "];\n"
-              "  if ((threadIdx.x & 63u) == 0) { wsum[2 * (threadIdx.x >> 6)] = cs.h; wsum[2 * (threadIdx.x >> 6) + 1] = cs.l;\n"
-              "                                 wev[threadIdx.x >> 6] = ev; }\n"
+              "  __shared__ u64 wev[" << nw << "];\n"
+              "  if ((threadIdx.x & 63u) == 0) { wsum[2 * wid] = cs.h; wsum[2 * wid + 1] = cs.l; wev[wid] = e64; }\n"
               "  __syncthreads();\n"
               "  if (threadIdx.x == 0) {\n"
               "    dd t; t.h = wsum[0]; t.l = wsum[1];\n";
         os << "    for (int w = 1; w < " << nw << "; ++w) { dd o; o.h = wsum[2 * w]; o.l = wsum[2 * w + 1]; t = dd_add(t, o); }\n";
-        os << "    u64 te = 0;\n    for (int w = 0; w < " << nw << "; ++w) te += 64ull * wev[w];  // lanes x terms\n";
+        os << "    u64 te = 0;\n    for (int w = 0; w < " << nw << "; ++w) te += wev[w];  // lane-terms\n";
         os << "    counts[blockIdx.x] = te;\n";
         os << "    partials[2 * (u64)blockIdx.x] = t.h;\n"
               "    partials[2 * (u64)blockIdx.x + 1] = t.l;\n"

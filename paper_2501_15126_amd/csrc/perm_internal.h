@@ -73,6 +73,8 @@ struct Plan {
     int u = 0;                          // static unrolled block = 2^u steps
     int block = 256;
     int waves_per_simd = 0;             // > 0: occupancy hint for the compiler
+    int queue_slots = 0;                // per-wave queue of partly needed blocks: slots,
+                                        // 0 = the most that fit, -1 = none
     bool zero_skip = true;              // skip chunks / blocks whose terms are exactly 0
     double base_x_hi[PERM_MAX_N];       // x_r at Gray index 0 (Alg. 1 lines 1-5)
     double ops_per_step = 0, flops_per_step = 0;

@@ -315,6 +315,12 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         return PERM_EINVAL;
     }
     p->waves_per_simd = std::max(0, o.waves_per_simd);
+    if (!(o.block_queue == -1 || o.block_queue == 0 || o.block_queue == 8 || o.block_queue == 16 ||
+          o.block_queue == 32 || o.block_queue == 64)) {
+        *err = "block_queue must be -1 (off), 0 (automatic) or 8, 16, 32, 64 slots per wave";
+        return PERM_EINVAL;
+    }
+    p->queue_slots = o.block_queue;
     if (p->block % 64 != 0 || p->block > 1024) {
         *err = "block must be a multiple of 64 and at most 1024";
         return PERM_EINVAL;

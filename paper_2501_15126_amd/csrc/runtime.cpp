@@ -237,7 +237,7 @@ bool plan_key(const perm_csc *m, const perm_opts &o, std::string *key) {
     }
     const int32_t f[] = {o.mode,     o.chunk_log2, o.unroll_log2, o.block,     o.vgpr_budget,
                          o.force_k,  o.force_c,    o.max_levels,  o.zero_skip, o.cold_tier,
-                         o.waves_per_simd};
+                         o.waves_per_simd, o.block_queue};
     put(f, sizeof f);
     put(&o.gr_ratio, sizeof o.gr_ratio);
     return true;
@@ -619,7 +619,22 @@ perm_status autotune_one(const perm_csc *a, const perm_opts *opts, perm_opts *be
     }
     s = try_dim(cands);
     if (s != PERM_OK) return s;
-    // 5. occupancy the kernel is compiled for
+    // 5. queue of partly needed blocks (zero-aware kernels): off or its size
+    if (plan.zero_skip) {
+        cands.clear();
+        for (int q : {-1, 16, 32, 64}) {
+            if (q == cur.block_queue) continue;
+            perm_opts c = cur;
+            c.chunk_log2 = plan.kappa;
+            c.unroll_log2 = plan.u;
+            c.block = plan.block;
+            c.block_queue = q;
+            cands.push_back(c);
+        }
+        s = try_dim(cands);
+        if (s != PERM_OK) return s;
+    }
+    // 6. occupancy the kernel is compiled for
     cands.clear();
     for (int w : {-1, 4, 5, 6}) {
         if (w == plan.waves_per_simd || (w == -1 && plan.waves_per_simd == 0)) continue;

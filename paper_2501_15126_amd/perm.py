@@ -50,7 +50,8 @@ class PermOpts(ctypes.Structure):
                 ("batch_mode", ctypes.c_int32), ("batch_kappa_shift", ctypes.c_int32),
                 ("cold_tier", ctypes.c_int32), ("gr_ratio", ctypes.c_double),
                 ("hip_stream", ctypes.c_void_p), ("block_partials", ctypes.POINTER(ctypes.c_double)),
-                ("block_partials_cap", ctypes.c_int64), ("progress", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
+                ("block_partials_cap", ctypes.c_int64), ("progress", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+                ("block_queue", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class PermBatchStats(ctypes.Structure):
@@ -189,7 +190,8 @@ def _stream_handle(stream):
 
 def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, force_k=0, force_c=0,
               max_levels=0, gr_ratio=0.0, stream=None, zero_skip="auto", batch_mode="streams",
-              batch_kappa_shift=0, cold_tier="global", progress=False, waves_per_simd=0):
+              batch_kappa_shift=0, cold_tier="global", progress=False, waves_per_simd=0,
+              block_queue=True):
     o = PermOpts()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.chunk_log2, o.unroll_log2, o.block = chunk_log2, unroll_log2, block
@@ -201,6 +203,7 @@ def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, 
     o.cold_tier = {"global": 0, "lds": 1}[cold_tier]
     o.progress = 1 if progress else 0
     o.waves_per_simd = waves_per_simd
+    o.block_queue = (0 if block_queue is True else -1 if block_queue is False else int(block_queue))
     o.hip_stream = _stream_handle(stream)
     return o
 
@@ -260,7 +263,8 @@ def _opts_kwargs(o):
             "zero_skip": {0: "auto", 1: True, -1: False}[o.zero_skip],
             "batch_mode": {0: "streams", 1: "graph", 2: "sequential", 3: "one_stream"}[o.batch_mode],
             "batch_kappa_shift": o.batch_kappa_shift, "cold_tier": {0: "global", 1: "lds"}[o.cold_tier],
-            "waves_per_simd": o.waves_per_simd}
+            "waves_per_simd": o.waves_per_simd,
+            "block_queue": {0: True, -1: False}.get(o.block_queue, o.block_queue)}
 
 
 def perm_autotune(ccs, **opts):

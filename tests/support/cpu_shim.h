@@ -15,6 +15,12 @@ struct cpu_dim3 { unsigned x, y, z; };
 static cpu_dim3 threadIdx, blockIdx;
 static inline void __syncthreads() {}
 static inline double __shfl_xor(double v, int, int) { return v; }
+static inline unsigned long long __shfl_xor(unsigned long long v, int, int) { return v; }
+// one-lane wave: the ballot is the lane's own bit, and no lane is below it
+static inline unsigned long long __ballot(int p) { return p ? 1ull : 0ull; }
+static inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
+static inline unsigned __builtin_amdgcn_mbcnt_lo(unsigned, unsigned acc) { return acc; }
+static inline unsigned __builtin_amdgcn_mbcnt_hi(unsigned, unsigned acc) { return acc; }
 // one emulated lane is the whole "wave"
 static inline int __all(int p) { return p; }
 using std::fma;

@@ -291,15 +291,23 @@ def test_zero_skip_is_exact(P, oracle_mod):
                 on, st_on = P.perm_sparse_ex(ccs, zero_skip=True, chunk_log2=kappa, unroll_log2=u)
                 off, _ = P.perm_sparse_ex(ccs, zero_skip=False, chunk_log2=kappa, unroll_log2=u)
                 assert on == off == exact, (seed, n, kappa, u, on, off, exact)
+                # the block queue (default: as many slots as fit), off, and small
+                # enough to overflow into the in-place path
+                for bq in (False, 8):
+                    q, st_q = P.perm_sparse_ex(ccs, zero_skip=True, chunk_log2=kappa, unroll_log2=u, block_queue=bq)
+                    assert q == exact, (seed, n, kappa, u, bq, q, exact)
     # integer values other than 0/1, and a real matrix forced through the skipping code
     A = np.where(np.random.default_rng(1).random((20, 20)) < 0.2, 2.0, 0.0) + np.eye(20) * 3.0
     ccs = O.dense_to_ccs(A)
     ref, abs_sum = O.perm_nw(ccs)
-    # the same schedule on both sides: bitwise equal (the default schedules
-    # of the two kernel kinds differ, and with them the summation order)
-    on, _ = P.perm_sparse_ex(ccs, zero_skip=True, chunk_log2=8, unroll_log2=6)
+    # the same schedule on both sides and no block queue: bitwise equal (the
+    # default schedules of the two kernel kinds differ, and queued blocks are
+    # added by other lanes, so either changes the summation order)
+    on, _ = P.perm_sparse_ex(ccs, zero_skip=True, chunk_log2=8, unroll_log2=6, block_queue=False)
     off, _ = P.perm_sparse_ex(ccs, zero_skip=False, chunk_log2=8, unroll_log2=6)
     assert on == off and abs(on - ref) <= _tol(20, ref, abs_sum)
+    queued, _ = P.perm_sparse_ex(ccs, zero_skip=True, chunk_log2=8, unroll_log2=6)
+    assert abs(queued - ref) <= _tol(20, ref, abs_sum)
     for zs in (True, False):
         d, _ = P.perm_sparse_ex(ccs, zero_skip=zs)
         assert abs(d - ref) <= _tol(20, ref, abs_sum)

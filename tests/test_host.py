@@ -227,8 +227,12 @@ def _emulate(P, ccs, **opts):
     d = tempfile.mkdtemp(prefix="permemu")
     f = os.path.join(d, "g.cpp")
     with open(f, "w") as fh:
-        fh.write(src + '\nextern "C" void cpu_lane(u64 m, double* xg, u64 xs, u64 lid, double* o)'
-                 ' { u32 ev = 0; dd r = perm_lane(m, xg, xs, lid, ev); o[0] = r.h; o[1] = r.l; o[2] = ev; }\n')
+        # one lane: its own queued blocks (if any) are evaluated after its walk
+        fh.write(src + '\nextern "C" void cpu_lane(u64 m, double* xg, u64 xs, u64 lid, double* o) {'
+                 ' static double q[kBlockQueueWords]; u32 ev = 0, qc = 0;'
+                 ' dd r = perm_lane(m, xg, xs, lid, true, q, qc, ev);'
+                 ' for (u32 s = 0; s < qc; ++s) r = dd_add(r, block_eval(q + s, ev));'
+                 ' o[0] = r.h; o[1] = r.l; o[2] = ev; o[3] = qc; }\n')
     so = os.path.join(d, "g.so")
     subprocess.run(["g++", "-O1", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-include", SHIM,
                     "-o", so, f], check=True)
@@ -236,13 +240,15 @@ def _emulate(P, ccs, **opts):
     lib.cpu_lane.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
     n = ccs[0]
     xg = np.zeros(max(1, n), np.float64)
-    o = np.zeros(3)
+    o = np.zeros(4)
     tot = 0.0
     info["evaluated"] = 0
+    info["queued"] = 0
     for m in range(info["nchunks"]):
         lib.cpu_lane(m, xg.ctypes.data, 1, 0, o.ctypes.data)
         tot += o[0] + o[1]
         info["evaluated"] += int(o[2])
+        info["queued"] += int(o[3])
     return tot * (2.0 if n % 2 else -2.0), info
 
 
@@ -424,3 +430,29 @@ def test_autotune_argument_errors(P):
     assert lib.perm_batch_autotune(0, None, None, ctypes.byref(best), ctypes.byref(st)) == P.PERM_EINVAL
     with pytest.raises(P.PermError):
         P.compile_info(ccs, waves_per_simd=9)
+
+
+def test_block_queue_on_cpu(P, oracle_mod):
+    """Queued blocks (start state saved, evaluated after the walk) give the
+    exact result and evaluate exactly the terms the in-place path evaluates;
+    a one-lane wave fills an 8-slot queue often, exercising the in-place
+    fallback of a full queue as well."""
+    O = oracle_mod
+    queued_any = False
+    for ccs, kappa, u in ((W.single_01(18, 0.12, 5), 9, 3), (W.single_01(20, 0.1, 6), 12, 4),
+                          (W.single_01(16, 0.2, 2), 11, 2), (W.single_01(22, 0.1, 7), 14, 2)):
+        exact = float(O.perm_int(ccs))
+        base, ib = _emulate(P, ccs, chunk_log2=kappa, unroll_log2=u, zero_skip=True, block_queue=False)
+        assert ib["queued"] == 0 and base == exact
+        for slots in (8, 32):
+            got, iq = _emulate(P, ccs, chunk_log2=kappa, unroll_log2=u, zero_skip=True, block_queue=slots)
+            assert got == exact, (ccs[0], slots, got, exact)
+            assert iq["evaluated"] == ib["evaluated"]
+            queued_any |= iq["queued"] > 0
+    assert queued_any
+    # integer values other than 0/1 through the queue
+    A = np.where(np.random.default_rng(3).random((16, 16)) < 0.25, 2.0, 0.0) + np.eye(16) * 3.0
+    ccs = O.dense_to_ccs(A)
+    ref, abs_sum = O.perm_nw(ccs)
+    got, iq = _emulate(P, ccs, chunk_log2=10, unroll_log2=3, zero_skip=True, block_queue=16)
+    assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12
