@@ -242,6 +242,11 @@ def main():
     ap.add_argument("--zero-skip", default="auto", choices=["auto", "on", "off"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch-workload measurement")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the library's default options instead of the options perm_autotune picks")
+    ap.add_argument("--opts", default="",
+                    help="time these options (JSON of perm_sparse_ex keywords) instead of searching, e.g. for "
+                         "profiling the kernel an earlier run chose")
     ap.add_argument("--no-unpruned", action="store_true",
                     help="skip the context run of the same permanent with zero-aware skipping off")
     ap.add_argument("--serving-seconds", type=float, default=20.0,
@@ -296,16 +301,29 @@ def main():
     n = ccs[0]
     print("bench: workload %s seed %d n=%d nnz=%d mode %s" % (args.workload, args.seed, n, len(ccs[2]), args.mode),
           file=sys.stderr, flush=True)
+    # launch options: the autotuner's pick for this matrix (searched once,
+    # before and outside the timed region), given ones, or the defaults
+    opts = {"mode": args.mode, "zero_skip": zs}
+    tune = None
+    if args.opts:
+        opts.update(json.loads(args.opts))
+    elif not args.no_tune:
+        t = time.perf_counter()
+        opts, tune = P.perm_autotune(ccs, **opts)
+        tune["wall_s"] = time.perf_counter() - t
+        print("bench: autotuned in %.1f s" % tune["wall_s"], file=sys.stderr, flush=True)
+    chosen = {k: opts.get(k) for k in ("mode", "chunk_log2", "unroll_log2", "block", "waves_per_simd",
+                                          "block_queue", "cold_tier") if k in opts}
     first = None
     for _ in range(args.warmup):
-        v, st = P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=zs)
+        v, st = P.perm_sparse_ex(ccs, **opts)
         first = st if first is None else first
     kernel_ms = []
     evaluated = []
     values = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        v, st = P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=zs)  # synchronous: result on the host
+        v, st = P.perm_sparse_ex(ccs, **opts)  # synchronous: result on the host
         kernel_ms.append(st["kernel_ms"])
         evaluated.append(st["evaluated_steps"])
         values.append(v)
@@ -335,11 +353,12 @@ def main():
         "config": {"workload": "single sparse 0/1 matrix n=%d, permutation pattern OR Bernoulli(0.10), seed %d"
                                % (n, args.seed), "n": n, "nnz": len(ccs[2]), "mode": args.mode,
                    "zero_skip": args.zero_skip,
-                   "gray_steps_per_permanent": steps_per_perm},
+                   "options": "given" if args.opts else ("library defaults" if args.no_tune else
+                                                         "perm_autotune, searched before the timed region"),
+                   "chosen": chosen, "gray_steps_per_permanent": steps_per_perm},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(P.perm_codegen(ccs, mode=args.mode, zero_skip=zs,
-                                                                 waves_per_simd=st["waves_hint"] or -1))},
+                     "traffic": measured_traffic(P.perm_codegen(ccs, **dict(opts, waves_per_simd=st["waves_hint"] or -1)))},
         "kernel": {"name": "perm_gray", "avg_ms": avg_kernel_s * 1e3, "steps_per_s": steps_per_perm / avg_kernel_s,
                    "flops_per_step": st["flops_per_step"], "fp64_ops_per_step": st["ops_per_step"],
                    "fp64_issue_frac": ops_rate / 3.93216e13, "vgprs": st["vgprs"], "sgprs": st["sgprs"],
@@ -353,6 +372,14 @@ def main():
         "permanent": values[-1],
         "deterministic": all(x == values[0] for x in values),
     }
+    if tune is not None:
+        # context: the search, and the same permanent with the library's defaults
+        ks = []
+        for _ in range(3):
+            _, std = P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=zs)
+            ks.append(std["kernel_ms"])
+        kd = sum(ks) / len(ks)
+        out["autotune"] = dict(tune, default_options_kernel_ms=kd, default_options_steps_per_s=steps_per_perm / kd * 1e3)
     if zs is not False and not args.no_unpruned:
         # context: the same permanent with every term evaluated (pruning off)
         P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=False)

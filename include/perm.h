@@ -221,8 +221,8 @@ typedef struct {
  * 256), the block queue of zero-aware kernels (off, 16, 32, 64 slots) and the
  * compiled occupancy (-1, 4, 5, 6), keeping a candidate only if it is at
  * least 2 % faster.  Every candidate runs on the same sample of the
- * Gray-index space: 16 evenly spaced slices, each of 2^16 chunks of the
- * largest candidate chunk (so every candidate fills the GPU), or the whole
+ * Gray-index space: 8 evenly spaced slices, each of 2^19 chunks of the
+ * largest candidate chunk (so every launch fills the GPU), or the whole
  * space when that is no larger; best of 3 passes (one pass above 100 ms).
  * Candidates that the planner rejects are skipped.  *best receives the winning options (pass them to
  * perm_sparse_ex); candidates' plans and code stay in the plan cache.  The

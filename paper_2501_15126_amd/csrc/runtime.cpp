@@ -398,17 +398,17 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
 
 // The part of the Gray-index space every tuning candidate is timed on:
 // `slices` slices of 2^slice_log2 indices starting at s * 2^(n-1) / slices.
-// A slice holds at least 2^16 chunks of the largest candidate chunk (256
-// workgroups of 256 lanes, so the 16 slices give every CU 16 workgroups, as
-// a full run does); when 16 such slices would cover the whole space, the
-// whole space is the sample.
+// Each slice is its own launch (or launches), and holds at least 2^19 chunks
+// of the largest candidate chunk: 2048 workgroups of 256 lanes, 8 per CU, so
+// that every launch fills the GPU as a full run does; when 8 such slices
+// would cover the whole space, the whole space is the sample.
 struct TuneSample {
     int slices = 1;
     int slice_log2 = 0;
 };
 
-constexpr int kTuneSlicesLog2 = 4;
-constexpr int kTuneSliceChunksLog2 = 16;
+constexpr int kTuneSlicesLog2 = 3;
+constexpr int kTuneSliceChunksLog2 = 19;
 
 TuneSample tune_sample(int n, int max_kappa) {
     TuneSample t;

@@ -339,10 +339,10 @@ def test_autotune_single(P, oracle_mod):
     opts, st = P.perm_autotune(ccs)
     print("autotune n40", opts, st, flush=True)
     assert st["candidates"] >= 8 and 0.0 < st["best_ms"] <= st["default_ms"]
-    assert st["sample_fraction"] == 0.5  # chunks up to 2^(16 + 2): 16 slices of 2^(18 + 16) of 2^39
+    assert st["sample_fraction"] == 1.0  # chunks up to 2^(16 + 2): 8 slices of 2^(18 + 19) exceed 2^39
     got, _ = P.perm_sparse_ex(ccs, **opts)
     assert got == 4022060880.0
-    # a sampled search: n = 44, 16 slices of 2^(kappa + 2 + 16) of 2^43 Gray indices
+    # a sampled search: n = 44, 8 slices of 2^(kappa + 2 + 19) of 2^43 Gray indices
     big = W.single_01(44, 0.10, 2)
     opts, st = P.perm_autotune(big, zero_skip=False)
     print("autotune n44", opts, st, flush=True)
