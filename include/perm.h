@@ -147,8 +147,10 @@ typedef struct {
                                and an add the method needs as 2 */
     double sum_hi, sum_lo;  /* the Gray-term sum before the final factor */
     double evaluated_steps; /* lane-steps whose product the kernel evaluated, over
-                               all launched lanes (inactive padding lanes included);
-                               below steps when zero-aware skipping removed work */
+                               all launched lanes (inactive padding lanes included;
+                               a queued block counts once, for the thread that
+                               evaluates it); below steps when zero-aware
+                               skipping removed work */
     int64_t nblocks;        /* workgroups launched */
     int64_t nchunks;        /* lane chunks (2^(n-1-chunk_log2)) */
     int32_t n, nnz;         /* after dropping explicit zeros */
