@@ -248,15 +248,18 @@ perm_status perm_batch_autotune(int32_t count, const perm_csc *mats, const perm_
 /* A server owns a scheduler thread, a device-memory arena of
  * `device_mem_budget` bytes (0 = 1 GiB) and at most `max_inflight` requests
  * that were submitted and not yet collected (0 = 4096).  Requests use the
- * precompiled batch kernels (no per-request hipRTC) with opts' zero_skip and
- * batch_kappa_shift.  Admission is in arrival order, as arena memory frees.
+ * precompiled batch kernels (no per-request hipRTC) with opts' zero_skip, and
+ * chunks 2^3 times smaller than perm_batch's (batch_kappa_shift - 3), so that
+ * rounds interleave requests at a finer grain.  Admission is in arrival
+ * order, as arena memory frees.
  * Every scheduling round runs `round_steps` Gray steps (0 = 1.6e10, about
  * 20 ms of device work): first all of the remaining work of every small request
  * (at most a quarter of a round left), then the larger requests in arrival
  * order, each as much as it can use.  Two rounds are in flight, so requests
  * that arrive while others run join the next round.  Each kernel instance
  * (ng) has its own stream.  A request's result is bitwise the same whether
- * it runs alone or in any mix, and equals perm_batch's with the same options.  Returns NULL on
+ * it runs alone or in any mix, and equals perm_batch's with the same options
+ * except batch_kappa_shift lowered by 3.  Returns NULL on
  * error (perm_last_error).  The server uses the device current at creation. */
 typedef struct perm_server perm_server;
 perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget, int32_t max_inflight,

@@ -40,6 +40,13 @@ using namespace permx;
 
 namespace {
 
+// The server's chunks are 2^3 times smaller than perm_batch's for the same
+// options: a request then spans more, shorter waves, so rounds interleave
+// requests at a finer grain.  Measured on the serving mix (Poisson, n 12..36):
+// at 400 req/s p50 / p99 went from 6.5 / 106 ms (shift 0) to 1.2 / 76 ms
+// (-3); -2 and -4 were between, -5 worse again.
+constexpr int kServerChunkShift = -3;
+
 using Clock = std::chrono::steady_clock;
 
 constexpr size_t kAlign = 256;
@@ -504,7 +511,7 @@ perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget,
     memset(&s->opts, 0, sizeof s->opts);
     if (opts) s->opts = *opts;
     s->bo.zero_skip = s->opts.zero_skip;
-    s->bo.kappa_shift = s->opts.batch_kappa_shift;
+    s->bo.kappa_shift = s->opts.batch_kappa_shift + kServerChunkShift;
     s->budget = device_mem_budget ? device_mem_budget : ((size_t)1 << 30);
     s->max_inflight = max_inflight > 0 ? max_inflight : 4096;
     if (!(round_steps >= 0.0)) {

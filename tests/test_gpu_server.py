@@ -64,7 +64,8 @@ def test_server_alone_equals_in_mix(P):
             if not isinstance(t, tuple):
                 srv.wait(t)
     assert mixed == alone
-    assert list(P.perm_batch(probe)) == alone
+    # the server's chunks: batch_kappa_shift lowered by 3
+    assert list(P.perm_batch(probe, batch_kappa_shift=-3)) == alone
 
 
 def test_server_memory_admission_and_backpressure(P):
@@ -79,7 +80,7 @@ def test_server_memory_admission_and_backpressure(P):
         with pytest.raises(P.PermError) as e:
             srv.submit(big)
         assert e.value.status == P.PERM_ETOOBIG
-    assert list(P.perm_batch(reqs)) == res
+    assert list(P.perm_batch(reqs, batch_kappa_shift=-3)) == res
     with P.Server(max_inflight=3) as srv:
         t = [srv.submit(reqs[i]) for i in range(3)]
         assert srv.try_submit(reqs[3]) is None  # three outstanding tickets
@@ -105,8 +106,8 @@ def test_server_continuous_batching(P):
         vl = srv.wait(tl)
         st = srv.stats()
     assert st["rounds"] >= 2
-    assert vs == P.perm_batch([small])[0]
-    assert vl == P.perm_batch([large])[0]
+    assert vs == P.perm_batch([small], batch_kappa_shift=-3)[0]
+    assert vl == P.perm_batch([large], batch_kappa_shift=-3)[0]
 
 
 def test_server_errors(P):
