@@ -123,10 +123,10 @@ typedef struct {
                               lanes of a wave need is queued (its start state, in LDS) and
                               evaluated after the walks, one block per thread of the
                               workgroup, instead of by the whole wave in place; a full queue
-                              falls back to in place.  Slots per wave: 8, 16, 32 or 64;
-                              0 = the most of those whose queue fits 32 KiB of LDS per
-                              workgroup; -1 = off.  Used where it applies (the block's rows
-                              in VGPRs, the queue within 32 KiB) */
+                              falls back to in place.  Slots per wave: 8, 16, 32 or 64
+                              (used if the queue fits 40 KiB of LDS per workgroup); 0 =
+                              the most of those whose queue fits 32 KiB; -1 = off.  Only
+                              where the block's rows live in VGPRs */
     int32_t pad;
 } perm_opts;
 
