@@ -125,8 +125,8 @@ typedef struct {
                               workgroup, instead of by the whole wave in place; a full queue
                               falls back to in place.  Slots per wave: 8, 16, 32 or 64
                               (used if the queue fits 40 KiB of LDS per workgroup); 0 =
-                              the most of those whose queue fits 32 KiB; -1 = off.  Only
-                              where the block's rows live in VGPRs */
+                              the most of those that fit; -1 = off.  Only where the
+                              block's rows live in VGPRs */
     int32_t pad;
 } perm_opts;
 

@@ -282,8 +282,8 @@ struct Gen {
         // wave's accesses to one row are 64 consecutive doubles
         if (p.cold_lds) os << "__shared__ double xl[" << (n - k) * p.block << "];\n";
         // Block queue: used where block pairs are pruned (zero-aware, u >= 1)
-        // and their rows all live in VGPRs, within 32 or 40 KiB of LDS per
-        // workgroup; at most 64 slots per wave, so the workgroup drains in one pass.
+        // and their rows all live in VGPRs, within 40 KiB of LDS per workgroup;
+        // at most 64 slots per wave, so the workgroup drains in one pass.
         {
             int bt = 0;
             for (int j = 0; j <= u && j < n - 1; ++j) bt = std::max(bt, p.col_top[j]);
@@ -291,15 +291,18 @@ struct Gen {
             qrows.clear();
             for (int r = 0; r < n; ++r)
                 if (p.row_level[r] <= bt) qrows.push_back(r);
-            // slots per wave: the most of 64, 32, 16, 8 whose queue fits 32 KiB
-            // (five 256-lane workgroups per CU), or as given within 40 KiB (four)
-            auto fits = [&](int slots, long cap) { return (long)(p.block / 64) * qfields() * slots * 8 <= cap; };
+            // slots per wave: as given, or the most of 64, 32, 16, 8; the queue
+            // may take 40 KiB of LDS per workgroup (four 256-lane workgroups
+            // per CU): more slots beat the fifth wave that a 32 KiB cap keeps
+            // (n = 36 0/1: 3.25 ms with 64 slots in 35 KiB against 3.51 ms with
+            // 32 in 17 KiB; n = 40: 7.9 against 9.2 ms)
+            auto fits = [&](int slots) { return (long)(p.block / 64) * qfields() * slots * 8 <= 40960; };
             qslots = 0;
             if (p.queue_slots > 0) {
-                if (fits(p.queue_slots, 40960)) qslots = p.queue_slots;
+                if (fits(p.queue_slots)) qslots = p.queue_slots;
             } else if (p.queue_slots == 0) {
                 for (int slots : {64, 32, 16, 8})
-                    if (fits(slots, 32768)) {
+                    if (fits(slots)) {
                         qslots = slots;
                         break;
                     }
