@@ -450,6 +450,16 @@ def test_block_queue_on_cpu(P, oracle_mod):
             assert iq["evaluated"] == ib["evaluated"]
             queued_any |= iq["queued"] > 0
     assert queued_any
+    # random 0/1 matrices, chunk and unroll sizes, queue sizes
+    rng = np.random.default_rng(77)
+    for t in range(8):
+        n = int(rng.integers(12, 21))
+        ccs = W.single_01(n, float(rng.uniform(0.08, 0.25)), 700 + t)
+        kappa = int(rng.integers(4, n - 2))
+        u = int(rng.integers(1, min(kappa, 9)))
+        slots = (8, 16, 32, 64)[t % 4]
+        got, _ = _emulate(P, ccs, chunk_log2=kappa, unroll_log2=u, zero_skip=True, block_queue=slots)
+        assert got == float(O.perm_int(ccs)), (n, kappa, u, slots)
     # integer values other than 0/1 through the queue
     A = np.where(np.random.default_rng(3).random((16, 16)) < 0.25, 2.0, 0.0) + np.eye(16) * 3.0
     ccs = O.dense_to_ccs(A)
