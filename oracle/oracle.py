@@ -13,7 +13,7 @@ Functions (each follows the passage named in ``perm_oracle.c``):
 * ``perm_nw(ccs)``           Alg. 1 full range times the final factor.
 * ``perm_int(ccs)``          exact integer permanent of a 0/1 pattern via the
                              integer form of Alg. 1 (terms mod 2^128).
-* ``gray(g)``, ``changed_bit(g)``  Alg. 1 lines 9-10 from the XOR definition.
+* ``gray(g)``, ``changed_bit(g)``  Alg. 1's Gray-code step, from the XOR definition.
 * ``permanent_ordering(ccs)``  Alg. 4.
 * ``partitioning(ccs, tau, grratio)``  Alg. 5.
 * ``structural_rank(ccs)``   maximum bipartite matching size.
@@ -95,7 +95,7 @@ def default_threads() -> int:
 
 
 # --------------------------------------------------------------------------
-# Gray code (Alg. 1 lines 9-10)
+# Gray code (Alg. 1's Gray-code step)
 # --------------------------------------------------------------------------
 
 def gray(g: int) -> int:

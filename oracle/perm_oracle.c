@@ -60,7 +60,7 @@
 typedef long double ld;
 
 /* ------------------------------------------------------------------------ */
-/* Gray code, Alg. 1 lines 9-10                                             */
+/* Gray code, the Gray-code step of Alg. 1                                 */
 /* ------------------------------------------------------------------------ */
 
 /* Binary reflected Gray code of index g. */
@@ -158,7 +158,7 @@ typedef struct {
     ld sum, abs_sum;
 } nw_job;
 
-/* x(Gray_g) for the Nijenhuis-Wilf variant: lines 1-5 of Alg. 1 (under the
+/* x(Gray_g) for the Nijenhuis-Wilf variant: the initialisation of x in Alg. 1 (under the
  * a_{i,n-1} reading), then the columns whose bit is set in Gray_g. */
 static void nw_x_at(const nw_job *J, uint64_t g, ld *x) {
     int n = J->n;
@@ -189,12 +189,12 @@ static void *nw_worker(void *arg) {
         abs_sum += fabsl(prod);
         for (uint64_t g = J->b + 1; g < J->e; ++g) {
             int j, s;
-            oracle_changed_bit(g, &j, &s);                  /* lines 9-10 */
-            for (int p = J->colptr[j]; p < J->colptr[j + 1]; ++p) /* lines 12-15 */
+            oracle_changed_bit(g, &j, &s);                  /* which column changes */
+            for (int p = J->colptr[j]; p < J->colptr[j + 1]; ++p) /* x update */
                 x[J->rowidx[p]] += (ld)s * (ld)J->val[p];
-            prod = 1;                                        /* lines 17-19 */
+            prod = 1;                                        /* product */
             for (int i = 0; i < n; ++i) prod *= x[i];
-            sum += (g % 2 == 1) ? -prod : prod;              /* line 21 */
+            sum += (g % 2 == 1) ? -prod : prod;              /* signed sum */
             abs_sum += fabsl(prod);
         }
     }
@@ -240,7 +240,7 @@ int oracle_nw_range(int n, const int *colptr, const int *rowidx, const double *v
 }
 
 /* Permanent by Alg. 1 over the full range: the sum of all 2^(n-1) terms
- * times 4 (n mod 2) - 2 (the return line of Alg. 1). */
+ * times 4 (n mod 2) - 2 (the final scaling of Alg. 1). */
 int oracle_perm_nw(int n, const int *colptr, const int *rowidx, const double *val, int nthreads,
                    double out[4]) {
     if (n < 1 || n > ORACLE_MAX_N) return -1;

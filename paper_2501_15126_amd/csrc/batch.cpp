@@ -63,7 +63,7 @@ perm_status prepare_batch_matrix(const perm_csc *m, const BatchOptions &bo, Prep
         }
         pm->tops[j] = top;
     }
-    // x at Gray index 0 (Alg. 1 lines 1-5, a_{i,n-1} = 0 when absent); padding rows 1
+    // x at Gray index 0 (Alg. 1's initialisation, a_{i,n-1} = 0 when absent); padding rows 1
     double *base = &pm->vals[(size_t)std::max(1, n - 1) * CS];
     {
         std::vector<long double> rowsum(n, 0.0L), last(n, 0.0L);

@@ -136,7 +136,7 @@ __device__ __forceinline__ dd batch_lane(const BatchMat &md, const double *__res
     constexpr int CS = NG * 4;  // doubles per column
 
     LaneState<NG> st;
-    // x(Gray_{m 2^kappa}): Alg. 1 lines 1-5 plus the columns set in the code
+    // x(Gray_{m 2^kappa}): Alg. 1's initialisation plus the columns set in the code
 #pragma unroll
     for (int r = 0; r < 4 * NG; ++r) st.x[r] = vals[md.base_off + r];
     const u64 g0 = m << kappa;

@@ -76,7 +76,7 @@ struct Plan {
     int queue_slots = 0;                // per-wave queue of partly needed blocks: slots,
                                         // 0 = the most that fit, -1 = none
     bool zero_skip = true;              // skip chunks / blocks whose terms are exactly 0
-    double base_x_hi[PERM_MAX_N];       // x_r at Gray index 0 (Alg. 1 lines 1-5)
+    double base_x_hi[PERM_MAX_N];       // x_r at Gray index 0 (Alg. 1's initialisation)
     double ops_per_step = 0, flops_per_step = 0;
     std::vector<double> ops_of_col;     // FP64 VALU ops of one step flipping column j
 };

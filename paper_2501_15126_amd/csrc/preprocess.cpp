@@ -260,7 +260,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         p->col_top[j] = t;
     }
 
-    // ---- x at Gray index 0 (Alg. 1 lines 1-5, with a_{i,n-1} = 0 when absent) ----
+    // ---- x at Gray index 0 (Alg. 1's initialisation, with a_{i,n-1} = 0 when absent) ----
     {
         std::vector<long double> rowsum(n, 0.0L), last(n, 0.0L);
         for (int j = 0; j < n; ++j)
