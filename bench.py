@@ -277,7 +277,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the permanent's chunk ranges would shard across GPUs with a "
-              "16-byte gather per GPU, but this build runs and reports a single GPU only", file=sys.stderr)
+              "16-byte gather per GPU, but this benchmark runs and reports a single GPU only", file=sys.stderr)
         sys.exit(2)
 
     import paper_2501_15126_amd.perm as P
