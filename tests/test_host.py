@@ -466,3 +466,16 @@ def test_block_queue_on_cpu(P, oracle_mod):
     ref, abs_sum = O.perm_nw(ccs)
     got, iq = _emulate(P, ccs, chunk_log2=10, unroll_log2=3, zero_skip=True, block_queue=16)
     assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12
+
+
+def test_autotune_singular_needs_no_device(P):
+    """A structurally singular matrix has nothing to tune: perm_autotune
+    answers with the options it was given and times no candidate (no device
+    is touched, so this runs on the CPU)."""
+    ccs = W.random_sparse(9, 0.3, seed=3, kind="real")
+    n, cp, ri, v = ccs
+    keep = ri != 0  # row 0 left empty: structurally singular
+    cp2 = np.concatenate([[0], np.cumsum([keep[cp[j]:cp[j + 1]].sum() for j in range(n)])]).astype(np.int32)
+    sing = (n, cp2, ri[keep].astype(np.int32), v[keep])
+    opts, st = P.perm_autotune(sing, unroll_log2=3)
+    assert st["candidates"] == 0 and opts["unroll_log2"] == 3 and opts["mode"] == "auto"
