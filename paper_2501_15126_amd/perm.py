@@ -39,8 +39,10 @@ class PermError(RuntimeError):
 
 
 class PermCsc(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("colptr", ctypes.POINTER(ctypes.c_int32)),
-                ("rowidx", ctypes.POINTER(ctypes.c_int32)), ("val", ctypes.POINTER(ctypes.c_double))]
+    # the three arrays as plain addresses (int32, int32, float64): setting an
+    # address is cheaper than building a typed ctypes pointer on every call
+    _fields_ = [("n", ctypes.c_int32), ("colptr", ctypes.c_void_p), ("rowidx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
 
 
 class PermOpts(ctypes.Structure):
@@ -83,7 +85,7 @@ class PermStats(ctypes.Structure):
 
 _P = ctypes.POINTER
 _lib.perm_sparse.restype = ctypes.c_double
-_lib.perm_sparse.argtypes = [ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_double)]
+_lib.perm_sparse.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
 _lib.perm_sparse_ex.restype = ctypes.c_int
 _lib.perm_sparse_ex.argtypes = [_P(PermCsc), _P(PermOpts), _P(ctypes.c_double), _P(PermStats)]
 _lib.perm_batch.restype = ctypes.c_int
@@ -175,9 +177,7 @@ class _Csc:
         if self.rowidx.size == 0:  # keep valid pointers for empty matrices
             self.rowidx = np.zeros(1, np.int32)
             self.val = np.zeros(1, np.float64)
-        self.c = PermCsc(int(n), self.colptr.ctypes.data_as(_P(ctypes.c_int32)),
-                         self.rowidx.ctypes.data_as(_P(ctypes.c_int32)),
-                         self.val.ctypes.data_as(_P(ctypes.c_double)))
+        self.c = PermCsc(int(n), self.colptr.ctypes.data, self.rowidx.ctypes.data, self.val.ctypes.data)
 
 
 def _stream_handle(stream):
