@@ -25,4 +25,4 @@ static inline unsigned __builtin_amdgcn_mbcnt_hi(unsigned, unsigned acc) { retur
 static inline int __all(int p) { return p; }
 using std::fma;
 // a one-lane wave: the first lane's value is the value
-static inline unsigned __builtin_amdgcn_readfirstlane(unsigned v) { return v; }
+static inline int __builtin_amdgcn_readfirstlane(int v) { return v; }  // int, as the device builtin

@@ -220,8 +220,9 @@ def test_codegen_resources(P):
         assert lds["lds_bytes"] <= 40960 + 1024
 
 
-def _emulate(P, ccs, **opts):
-    """Run the generated perm_lane() of every chunk on the CPU (g++)."""
+def _emulate(P, ccs, chunks=None, **opts):
+    """Run the generated perm_lane() of every chunk (or of the chunks listed)
+    on the CPU (g++); the listed chunks' sums are returned in info["sums"]."""
     src = P.perm_codegen(ccs, **opts)
     info = P.compile_info(ccs, **opts)
     d = tempfile.mkdtemp(prefix="permemu")
@@ -244,9 +245,12 @@ def _emulate(P, ccs, **opts):
     tot = 0.0
     info["evaluated"] = 0
     info["queued"] = 0
-    for m in range(info["nchunks"]):
+    info["sums"] = []
+    for m in range(info["nchunks"]) if chunks is None else chunks:
         lib.cpu_lane(m, xg.ctypes.data, 1, 0, o.ctypes.data)
         tot += o[0] + o[1]
+        if chunks is not None:
+            info["sums"].append(o[0] + o[1])
         info["evaluated"] += int(o[2])
         info["queued"] += int(o[3])
     return tot * (2.0 if n % 2 else -2.0), info
@@ -296,6 +300,39 @@ def test_zero_skip_prunes_only_zero_terms(P):
         _, off = _emulate(P, ccs, chunk_log2=kappa, unroll_log2=u, zero_skip=False)
         assert off["evaluated"] == 1 << (n - 1)
         assert nz <= on["evaluated"] < (1 << (n - 1)) // 4, (n, nz, on["evaluated"])
+
+
+def test_generated_chunk_start_at_high_indices(P, oracle_mod):
+    """Single chunks of the n=40 workload far into the Gray-index space (the
+    chunk start reads bits up to 38 of the Gray code, those from chunk_log2 + 6
+    on once per wave), emulated on the CPU, against the oracle over the same
+    index range of the plan's ordered matrix.  Most chunks of this matrix sum
+    to zero, so the chunks tested are drawn (seeded) among those whose Gray
+    start has bit 31 set and whose terms the oracle finds nonzero."""
+    O = oracle_mod
+    ccs = W.single_01(40, 0.10, 1)
+    plan = P.perm_plan(ccs)
+    A = O.ccs_to_dense(ccs)
+    B = O.dense_to_ccs(A[np.ix_(plan["row_perm"], plan["col_perm"])])
+    rng = np.random.default_rng(11)
+    for zs in (True, False):  # chunk 2^16 pruned, 2^14 not
+        kappa = P.compile_info(ccs, zero_skip=zs)["chunk_log2"]
+        top = 1 << (39 - kappa)
+        ms, refs = [top - 1], [O.nw_range(B, (top - 1) << kappa, top << kappa)]
+        for _ in range(20000):
+            m = int(rng.integers(0, top))
+            g = (m << kappa) ^ (m << kappa >> 1)
+            if g >> 31 & 1:
+                r = O.nw_range(B, m << kappa, (m + 1) << kappa)
+                if r[1][0] + r[1][1] > 0:
+                    ms.append(m)
+                    refs.append(r)
+                    if len(ms) == 5:
+                        break
+        assert len(ms) == 5
+        _, info = _emulate(P, ccs, chunks=ms, zero_skip=zs)
+        for m, got, ((h, l), (ah, al)) in zip(ms, info["sums"], refs):
+            assert abs(got - (h + l)) <= 1e-12 * (ah + al), (zs, m, got, h + l)
 
 
 def test_generated_code_tiny_n_on_cpu(P, oracle_mod):
