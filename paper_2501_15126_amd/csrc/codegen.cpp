@@ -355,13 +355,30 @@ struct Gen {
         for (int r = 0; r < n; ++r)
             os << "  double " << (r < k ? xname(r) : "cx" + std::to_string(r)) << " = " << lit(p.base_x_hi[r]) << ";\n";
         const int jlo = kappa >= 1 ? kappa - 1 : 0;  // lower Gray bits of an aligned start are zero
+        // Bit j of the Gray code is bit j - kappa of m xor bit j - kappa + 1.
+        // A wave's 64 chunks are consecutive and 64-aligned (every launch
+        // starts at a multiple of the workgroup size), so from j = kappa + 6
+        // on the bit is the same in all its lanes: read it once from the
+        // first lane and add the column only when it is set (a lane past the
+        // last chunk may then start from another chunk's x; it adds nothing).
+        const int juni = kappa + 6;
+        if (juni < n - 1)
+            // (the builtin returns int: each half goes through u32, not sign-extended)
+            os << "  const u64 Gw = ((u64)(u32)__builtin_amdgcn_readfirstlane((int)(u32)(G >> 32)) << 32) |\n"
+                  "                 (u64)(u32)__builtin_amdgcn_readfirstlane((int)(u32)G);\n";
         for (int j = jlo; j < n - 1; ++j) {
             if (B.colptr[j + 1] == B.colptr[j]) continue;
-            os << "  { const double b = (double)((G >> " << j << ") & 1ull);\n";
+            if (j >= juni)
+                os << "  if ((Gw >> " << j << ") & 1ull) {\n";
+            else
+                os << "  { const double b = (double)((G >> " << j << ") & 1ull);\n";
             for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) {
                 const int r = B.rowidx[q];
                 const std::string v = r < k ? xname(r) : "cx" + std::to_string(r);
-                os << "    " << v << " = fma(b, " << lit(B.val[q]) << ", " << v << ");\n";
+                if (j >= juni)
+                    os << "    " << v << " += " << lit(B.val[q]) << ";\n";
+                else
+                    os << "    " << v << " = fma(b, " << lit(B.val[q]) << ", " << v << ");\n";
             }
             os << "  }\n";
         }
