@@ -48,7 +48,27 @@ __global__ void __launch_bounds__(kThreads) final_reduce(const double *__restric
     acc.h = 0.0;
     acc.l = 0.0;
     unsigned long long c = 0;
-    for (long long b = t; b < count; b += kThreads) {
+    // the same order of additions as a plain strided loop, with the loads of
+    // eight partials issued before the first of their additions waits
+    constexpr int kBatch = 8;
+    long long b = t;
+    for (; b + (kBatch - 1) * (long long)kThreads < count; b += kBatch * (long long)kThreads) {
+        dd v[kBatch];
+        unsigned long long cc[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const long long q = b + (long long)i * kThreads;
+            v[i].h = partials[2 * q];
+            v[i].l = partials[2 * q + 1];
+            cc[i] = counts[q];
+        }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            acc = dd_add(acc, v[i]);
+            c += cc[i];
+        }
+    }
+    for (; b < count; b += kThreads) {
         dd v;
         v.h = partials[2 * b];
         v.l = partials[2 * b + 1];
