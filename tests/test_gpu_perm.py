@@ -279,6 +279,53 @@ def test_n40_full_exact(P):
         assert abs(got - exact) < 0.5 and round(got) == exact
 
 
+def test_n40_bench_configuration_block_partials(P, oracle_mod):
+    """The n=40 workload in the two launch configurations the benchmark's
+    tuner chooses between (unroll 2^7; automatic and compiler-chosen
+    occupancy): the exact count, and sampled workgroup partials (the first,
+    the last, and seeded ones, about half of which start with Gray bit 31
+    set) against the oracle on the same Gray-index ranges of the plan's
+    ordered matrix."""
+    O = oracle_mod
+    g = _golden()
+    key = "n40_p0.10_01:1"
+    if key not in g:
+        pytest.skip("stored n=40 oracle value not generated")
+    exact = int(g[key]["perm_exact"])
+    ccs = W.single_01(40, 0.10, 1)
+    plan = P.perm_plan(ccs)
+    A = O.ccs_to_dense(ccs)
+    B = O.dense_to_ccs(A[np.ix_(plan["row_perm"], plan["col_perm"])])
+    info = P.compile_info(ccs, unroll_log2=7)
+    W_ = info["block"] << info["chunk_log2"]
+    nb = info["nblocks"]
+    # most workgroups of this matrix sum to zero: sample among those the
+    # oracle finds nonzero, two of them with Gray bit 31 of their start set
+    rng = np.random.default_rng(5)
+    refs = {b: O.nw_range(B, b * W_, (b + 1) * W_) for b in (0, nb - 1)}
+    want = {0: 2, 1: 2}
+    for _ in range(400):
+        b = int(rng.integers(1, nb - 1))
+        bit = ((b * W_) ^ (b * W_ >> 1)) >> 31 & 1
+        if want[bit] == 0 or b in refs:
+            continue
+        r = O.nw_range(B, b * W_, (b + 1) * W_)
+        if r[1][0] + r[1][1] > 0:
+            refs[b] = r
+            want[bit] -= 1
+            if not any(want.values()):
+                break
+    assert not any(want.values())
+    for w in (0, -1):
+        got, st, parts = P.perm_sparse_ex(ccs, unroll_log2=7, waves_per_simd=w, block_partials=True)
+        print("n40 bench config", w, got, st["kernel_ms"], st["vgprs"], st["waves_per_simd"], flush=True)
+        assert abs(got - exact) < 0.5 and round(got) == exact
+        assert (st["block"] << st["chunk_log2"]) == W_ and st["nblocks"] == nb
+        for b, ((h, l), (ah, al)) in refs.items():
+            part = parts[b, 0] + parts[b, 1]
+            assert abs(part - (h + l)) <= 1e-12 * (ah + al) + 1e-9, (w, b, part, h + l)
+
+
 def test_zero_skip_is_exact(P, oracle_mod):
     """Skipping chunks/blocks whose terms are exactly 0 leaves every result
     unchanged (0/1 and integer matrices, several chunk and unroll sizes)."""
