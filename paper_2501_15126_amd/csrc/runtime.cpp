@@ -484,6 +484,8 @@ perm_status time_sample(CachedPlan &cp, const TuneSample &ts, hipStream_t stream
 constexpr double kTuneMinGain = 0.02;
 constexpr int kTuneRepeats = 3;
 constexpr double kTuneLongPassMs = 100.0;
+// Further steps of the static block past a winning first step, at most.
+constexpr int kTuneMaxExtraSteps = 3;
 
 perm_status autotune_one(const perm_csc *a, const perm_opts *opts, perm_opts *best, perm_tune_stats *ts_out) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -595,18 +597,35 @@ perm_status autotune_one(const perm_csc *a, const perm_opts *opts, perm_opts *be
     }
     s = try_dim(cands);
     if (s != PERM_OK) return s;
-    // 3. static block (log2 of unrolled steps)
-    cands.clear();
-    for (int d : {-1, 1}) {
-        const int u = plan.u + d;
-        if (u < 1 || u > plan.kappa - 1) continue;
-        perm_opts c = cur;
-        c.chunk_log2 = plan.kappa;
-        c.unroll_log2 = u;
-        cands.push_back(c);
+    // 3. static block (log2 of unrolled steps); a side that wins is followed
+    //    one step further at a time while it keeps winning
+    {
+        const int u0 = plan.u;
+        cands.clear();
+        for (int d : {-1, 1}) {
+            const int u = plan.u + d;
+            if (u < 1 || u > plan.kappa - 1) continue;
+            perm_opts c = cur;
+            c.chunk_log2 = plan.kappa;
+            c.unroll_log2 = u;
+            cands.push_back(c);
+        }
+        s = try_dim(cands);
+        if (s != PERM_OK) return s;
+        const int dir = plan.u > u0 ? 1 : plan.u < u0 ? -1 : 0;
+        for (int more = 0; dir != 0 && more < kTuneMaxExtraSteps; ++more) {
+            const int before = plan.u;
+            const int u = before + dir;
+            if (u < 1 || u > plan.kappa - 1) break;
+            perm_opts c = cur;
+            c.chunk_log2 = plan.kappa;
+            c.unroll_log2 = u;
+            cands.assign(1, c);
+            s = try_dim(cands);
+            if (s != PERM_OK) return s;
+            if (plan.u == before) break;
+        }
     }
-    s = try_dim(cands);
-    if (s != PERM_OK) return s;
     // 4. threads per workgroup
     cands.clear();
     for (int b : {64, 128, 256}) {
