@@ -484,7 +484,8 @@ perm_status time_sample(CachedPlan &cp, const TuneSample &ts, hipStream_t stream
 constexpr double kTuneMinGain = 0.02;
 constexpr int kTuneRepeats = 3;
 constexpr double kTuneLongPassMs = 100.0;
-// Further steps of the static block past a winning first step, at most.
+// Further steps past a winning edge candidate (chunk) or first step (static
+// block), at most.
 constexpr int kTuneMaxExtraSteps = 3;
 
 perm_status autotune_one(const perm_csc *a, const perm_opts *opts, perm_opts *best, perm_tune_stats *ts_out) {
@@ -586,17 +587,34 @@ perm_status autotune_one(const perm_csc *a, const perm_opts *opts, perm_opts *be
         s = try_dim(cands);
         if (s != PERM_OK) return s;
     }
-    // 2. chunk size (log2 of Gray steps per lane)
-    cands.clear();
-    for (int d : {-2, -1, 1, 2}) {
-        const int k = plan.kappa + d;
-        if (k < 1 || k > smp.slice_log2) continue;
-        perm_opts c = cur;
-        c.chunk_log2 = k;
-        cands.push_back(c);
+    // 2. chunk size (log2 of Gray steps per lane); when a candidate at the
+    //    edge of the range wins, the search goes on past it one step at a time
+    //    while it keeps winning
+    {
+        const int k0 = plan.kappa;
+        cands.clear();
+        for (int d : {-2, -1, 1, 2}) {
+            const int k = plan.kappa + d;
+            if (k < 1 || k > smp.slice_log2) continue;
+            perm_opts c = cur;
+            c.chunk_log2 = k;
+            cands.push_back(c);
+        }
+        s = try_dim(cands);
+        if (s != PERM_OK) return s;
+        const int dir = plan.kappa == k0 + 2 ? 1 : plan.kappa == k0 - 2 ? -1 : 0;
+        for (int more = 0; dir != 0 && more < kTuneMaxExtraSteps; ++more) {
+            const int before = plan.kappa;
+            const int k = before + dir;
+            if (k < 1 || k > smp.slice_log2) break;
+            perm_opts c = cur;
+            c.chunk_log2 = k;
+            cands.assign(1, c);
+            s = try_dim(cands);
+            if (s != PERM_OK) return s;
+            if (plan.kappa == before) break;
+        }
     }
-    s = try_dim(cands);
-    if (s != PERM_OK) return s;
     // 3. static block (log2 of unrolled steps); a side that wins is followed
     //    one step further at a time while it keeps winning
     {
