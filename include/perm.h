@@ -219,13 +219,15 @@ typedef struct {
  * from opts (NULL = defaults), it tries in turn the register/global split
  * (AUTO; HYBRID with Alg. 5's partition and the cold rows in global memory or
  * in LDS), the chunk size (log2 of the Gray steps per lane, +-1 and +-2 around
- * the current), the static block (+-1), the threads per workgroup (64, 128,
- * 256), the block queue of zero-aware kernels (off, 16, 32, 64 slots) and the
- * compiled occupancy (-1, 4, 5, 6), keeping a candidate only if it is at
- * least 2 % faster.  Every candidate runs on the same sample of the
- * Gray-index space: 8 evenly spaced slices, each of 2^19 chunks of the
- * largest candidate chunk (so every launch fills the GPU), or the whole
- * space when that is no larger; best of 3 passes (one pass above 100 ms).
+ * the current, then past a winning +-2 one step at a time, at most 3 more),
+ * the static block (+-1, then on the winning side one step at a time, at most
+ * 3 more), the threads per workgroup (64, 128, 256), the block queue of
+ * zero-aware kernels (off, 16, 32, 64 slots) and the compiled occupancy (-1,
+ * 4, 5, 6), keeping a candidate only if it is at least 2 % faster.  Every
+ * candidate runs on the same sample of the Gray-index space: 8 evenly spaced
+ * slices, each of 2^19 chunks of the current chunk + 2 (so every launch fills
+ * the GPU; chunks past that run fewer), or the whole space when that is no
+ * larger; best of 3 passes (one pass above 100 ms).
  * Candidates that the planner rejects are skipped.  *best receives the winning options (pass them to
  * perm_sparse_ex); candidates' plans and code stay in the plan cache.  The
  * result of the permanent does not depend on these options beyond FP64
