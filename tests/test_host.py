@@ -335,6 +335,31 @@ def test_generated_chunk_start_at_high_indices(P, oracle_mod):
             assert abs(got - (h + l)) <= 1e-12 * (ah + al), (zs, m, got, h + l)
 
 
+def test_wave_shares_high_gray_bits_of_chunk_starts(P):
+    """The generated chunk start reads the Gray bits from chunk_log2 + 6 up
+    once per wave.  That is exact because a wave's 64 chunks are consecutive
+    and 64-aligned: workgroups are whole multiples of 64 lanes (other sizes
+    are refused) and every launch starts at a multiple of the workgroup."""
+    rng = np.random.default_rng(3)
+    for kappa in (0, 1, 5, 14, 16, 20):
+        for _ in range(50):
+            c0 = int(rng.integers(0, 1 << (39 - kappa - 6))) * 64
+            high = {((m << kappa) ^ ((m << kappa) >> 1)) >> (kappa + 6) for m in range(c0, c0 + 64)}
+            assert len(high) == 1, (kappa, c0)
+    # the generator reads per wave exactly the bits from chunk_log2 + 6 up
+    for ccs in (W.single_01(40, 0.10, 1), W.single_real(36, 0.30, 1)):
+        kappa = P.compile_info(ccs)["chunk_log2"]
+        src = P.perm_codegen(ccs)
+        wave = [int(j) for j in re.findall(r"\(Gw >> (\d+)\)", src)]
+        lane = [int(j) for j in re.findall(r"\(double\)\(\(G >> (\d+)\)", src)]
+        assert wave and min(wave) >= kappa + 6 and max(lane) < kappa + 6, (kappa, wave, lane)
+    ccs = W.single_01(20, 0.2, 1)
+    for b in (32, 96, 100):
+        with pytest.raises(P.PermError) as e:
+            P.compile_info(ccs, block=b)
+        assert e.value.status == P.PERM_EINVAL, b
+
+
 def test_generated_code_tiny_n_on_cpu(P, oracle_mod):
     O = oracle_mod
     rng = np.random.default_rng(6)
