@@ -127,7 +127,19 @@ typedef struct {
                               (used if the queue fits 40 KiB of LDS per workgroup); 0 =
                               the most of those that fit; -1 = off.  Only where the
                               block's rows live in VGPRs */
-    int32_t pad;
+    int32_t exact;         /* exact integer results for integer-valued matrices: the kernels
+                              run on y = 2x (then an integer), keep the term sum modulo a
+                              prime below 2^24 and a rigorous bound on the FP64 sum's
+                              rounding error; the integer congruent to the residue nearest
+                              the FP64 estimate is returned when the bound is below half the
+                              modulus, else the kernel runs again with the next prime (at
+                              most three, residues combined by the Chinese remainder
+                              theorem) while |perm| may be below 2^53.  0 = auto (on for
+                              integer values whose rows' sums of |a| are at most 2^20),
+                              1 = required (PERM_EINVAL otherwise), -1 = off (FP64 only) */
+    int32_t exact_passes;  /* exact mode: run at least this many passes (primes), 1..3;
+                              0 = as many as the certificate needs */
+    int32_t pad2;
 } perm_opts;
 
 /* Statistics of one call (all optional to read). */
@@ -164,6 +176,14 @@ typedef struct {
     int32_t singular;       /* 1 if answered as 0 by the structural check */
     int32_t waves_hint;     /* waves per SIMD the kernel was compiled for; 0 = none */
     int32_t vgpr_spills;    /* VGPRs the compiler spilled to scratch */
+    int32_t exact;          /* 1: the result is the exact integer permanent (certified, or the
+                               structural zero); 0: exact mode ran but the result is the FP64
+                               estimate (|perm| at least 2^53, or no certificate after three
+                               primes); -1: not in exact mode */
+    int32_t exact_passes;   /* kernel passes (primes) of the exact mode */
+    double estimate;        /* the FP64 estimate of the permanent */
+    double err_bound;       /* exact mode: rigorous bound on |estimate - perm| */
+    double exact_ops_per_step; /* of ops_per_step: the exact mode's residue and bound operations */
 } perm_stats;
 
 /* Permanent of one matrix (Alg. 1 end to end).  Returns NaN on error
@@ -198,6 +218,12 @@ typedef struct {
     double fp64_ops;       /* FP64 operations the batch kernels execute (an FMA is one),
                               counted exactly per chunk without zero-aware skipping */
     double flops;          /* the same with an FMA counted as 2 */
+    double exact_ops;      /* of fp64_ops: the exact mode's residue and bound operations */
+    int32_t exact_certified;   /* matrices whose result is the exact integer (exact mode, or
+                                  structurally singular) */
+    int32_t exact_uncertified; /* exact-mode matrices left at the FP64 estimate */
+    int32_t passes;        /* kernel passes run (exact mode: one per prime needed) */
+    int32_t pad2;
 } perm_batch_stats;
 
 /* perm_batch with statistics (st may be NULL). */
@@ -324,13 +350,31 @@ perm_status perm_codegen(const perm_csc *a, const perm_opts *opts, char *buf, si
 perm_status perm_compile_info(const perm_csc *a, const perm_opts *opts, perm_stats *st);
 
 /* The data the precompiled batch kernels use for one matrix (introspection
- * for tests): desc[0..5] = n, ng (4-row groups), chunk log2, zero-skip flag,
- * highest group of the in-chunk columns, structurally singular flag;
+ * for tests): desc[0..7] = n, ng (4-row groups), chunk log2, zero-skip flag,
+ * highest group of the in-chunk columns, structurally singular flag, exact
+ * mode flag (values then doubled: x holds y = 2x), 0;
  * vals (cap doubles) = column groups [j][ng][4] for flipped columns j, then
  * the 4*ng starting values of x; tops (cap ints) = highest group per flipped
  * column.  *nvals / *ntops receive the needed sizes. */
-perm_status perm_batch_describe(const perm_csc *a, const perm_opts *opts, int32_t desc[6], double *vals,
+perm_status perm_batch_describe(const perm_csc *a, const perm_opts *opts, int32_t desc[8], double *vals,
                                 size_t vals_cap, size_t *nvals, int32_t *tops, size_t tops_cap, size_t *ntops);
+
+/* The exact mode's integer recovery (introspection for tests; exact mode,
+ * Sec. II Alg. 1 on y = 2x).  Input: an n x n integer-valued matrix's Gray
+ * term sum in y units (products of 2x) as a double-double (hi, lo), the sum
+ * of |terms| A, the chunk log2 (no accumulator took more than 2^chunk_log2
+ * terms), and resid[0..passes-1], the term sum modulo the library's primes
+ * (perm_exact_primes; any representatives, exact integers).  Output:
+ * out[0] = the permanent (the exact integer when *certified), out[1] = the
+ * FP64 estimate (4 (n mod 2) - 2) 2^-n (hi + lo), out[2] = the rigorous bound
+ * on |estimate - perm|; *more = 1 when another prime could certify a result
+ * that may be below 2^53 in magnitude.  PERM_EINVAL for n outside 1..64 or
+ * passes outside 0..3. */
+perm_status perm_exact_recover(int32_t n, double hi, double lo, double abs_sum, int32_t chunk_log2, int32_t passes,
+                               const double *resid, double out[3], int32_t *certified, int32_t *more);
+
+/* The exact mode's primes, in the order of the passes (3 values). */
+void perm_exact_primes(double out[3]);
 
 /* Description of the last error on the calling thread (never NULL; valid
  * until the next library call on that thread). */

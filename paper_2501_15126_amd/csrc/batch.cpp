@@ -75,6 +75,29 @@ perm_status prepare_batch_matrix(const perm_csc *m, const BatchOptions &bo, Prep
         for (int r = 0; r < 4 * ng; ++r) base[r] = r < n ? (double)(last[r] - rowsum[r] / 2) : 1.0;
     }
     pm->base_index = (size_t)std::max(1, n - 1) * CS;
+    // exact mode: integer values, and every 4-row group's bound (the product
+    // of its rows' sums of |a|, a bound on |product of y|) within
+    // kExactPartMax, so that a group product times a residue stays exact
+    {
+        bool ok = bo.exact >= 0;
+        for (double v : B.val)
+            if (v != std::floor(v)) ok = false;
+        std::vector<double> rowabs(4 * ng, 1.0);
+        for (int r = 0; r < n; ++r) rowabs[r] = 0.0;
+        for (int q = 0; q < B.nnz(); ++q) rowabs[B.rowidx[q]] += std::fabs(B.val[q]);
+        for (int g = 0; g < ng && ok; ++g)
+            ok = rowabs[4 * g] * rowabs[4 * g + 1] * rowabs[4 * g + 2] * rowabs[4 * g + 3] <= kExactPartMax;
+        if (bo.exact == 1 && !ok) {
+            *err = "exact = 1 needs integer values with every 4-row group's bound at most 2^20";
+            return PERM_EINVAL;
+        }
+        pm->exact = ok;
+        if (ok) {
+            // y = 2x: the column values and the start values of the n real rows
+            for (size_t i = 0; i < pm->base_index; ++i) pm->vals[i] *= 2.0;
+            for (int r = 0; r < n; ++r) base[r] *= 2.0;
+        }
+    }
     pm->chunk_top = 0;
     for (int j = 0; j < std::min(pm->kappa, n - 1); ++j) pm->chunk_top = std::max(pm->chunk_top, pm->tops[j]);
     if (bo.zero_skip > 0) {
@@ -115,6 +138,22 @@ perm_status prepare_batch_matrix(const perm_csc *m, const BatchOptions &bo, Prep
         const double init_fmas = (double)(n - 1 - std::max(kap - 1, 0)) * 4.0 * ng;
         ops += init_fmas + 4.0 * (ng - 1) + 4.0;
         fmas += init_fmas;
+        if (pm->exact) {
+            // per step: a residue reduction (two multiplies, a rounding, an
+            // FMA) per refreshed group below the top one, the residue FMA and
+            // the |term| FMA; per 512 steps a reduction of the residue sum
+            double xo = 0.0, xf = 0.0;
+            for (int j = 0; j < kap; ++j) {
+                const double cnt = std::ldexp(1.0, kap - 1 - j);
+                const int t = std::min(pm->tops[j], ng - 2);
+                xo += cnt * (4.0 * std::max(t, 0) + 2.0);
+                xf += cnt * (1.0 * std::max(t, 0) + 2.0);
+            }
+            xo += 3.0 * (std::ldexp(1.0, kap) / 512.0 + 1.0) + 4.0 * std::max(ng - 2, 0) + 2.0;
+            ops += xo;
+            fmas += xf;
+            pm->exact_ops = xo * (double)((uint64_t)1 << (n - 1 - kap));
+        }
         pm->fp64_ops = ops * (double)pm->nchunks;
         pm->fp64_fmas = fmas * (double)pm->nchunks;
     }
@@ -205,20 +244,82 @@ BatchJob::~BatchJob() {
 }
 
 perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, double *out, hipStream_t stream,
-                          BatchLaunch how, double *kernel_ms, std::string *err) {
+                          BatchLaunch how, double *kernel_ms, std::string *err, int *exact_state, int *passes) {
     const int count = (int)mats.size();
-    // order the matrices by kernel instance (ng), largest work first within
-    // an instance; results go back to the caller's order
+    std::vector<double> raw((size_t)kPartStride * std::max(count, 1), 0.0);
+    std::vector<int> prime(count, 0);
+    double kms = 0.0;
+    perm_status s = run_pass(mats, prime, raw.data(), stream, how, &kms, err);
+    if (s != PERM_OK) return s;
+    int npass = 1;
+    std::vector<ExactSums> es(count);
+    std::vector<int> todo;  // exact-mode matrices still to recover
+    for (int i = 0; i < count; ++i) {
+        const PreparedMatrix &pm = *mats[i];
+        const double *r = &raw[(size_t)kPartStride * i];
+        if (exact_state) exact_state[i] = pm.singular ? 1 : pm.exact ? 0 : -1;
+        if (pm.singular) {
+            out[i] = 0.0;
+        } else if (!pm.exact) {
+            out[i] = (r[0] + r[1]) * ((pm.n % 2 == 1) ? 2.0 : -2.0);  // final factor 4 (n mod 2) - 2
+        } else {
+            es[i].hi = r[0];
+            es[i].lo = r[1];
+            es[i].abs_sum = r[3];
+            es[i].chunk_log2 = pm.kappa;
+            es[i].resid[0] = r[2];
+            es[i].passes = 1;
+            todo.push_back(i);
+        }
+    }
+    // exact mode: recover; the uncertified ones run again with the next prime
+    while (!todo.empty()) {
+        std::vector<int> again;
+        for (int i : todo) {
+            const ExactOutcome eo = exact_recover(mats[i]->n, es[i]);
+            out[i] = eo.value;
+            if (exact_state) exact_state[i] = eo.certified ? 1 : 0;
+            if (!eo.certified && eo.more) again.push_back(i);
+        }
+        if (again.empty()) break;
+        std::vector<const PreparedMatrix *> sub;
+        std::vector<int> pr;
+        for (int i : again) {
+            sub.push_back(mats[i]);
+            pr.push_back(es[i].passes);
+        }
+        std::vector<double> raw2((size_t)kPartStride * sub.size(), 0.0);
+        double k2 = 0.0;
+        s = run_pass(sub, pr, raw2.data(), stream, how, &k2, err);
+        if (s != PERM_OK) return s;
+        kms += k2;
+        ++npass;
+        for (size_t q = 0; q < again.size(); ++q) {
+            ExactSums &e = es[again[q]];
+            e.resid[e.passes++] = raw2[kPartStride * q + 2];
+        }
+        todo = again;
+    }
+    if (kernel_ms) *kernel_ms = kms;
+    if (passes) *passes = npass;
+    return PERM_OK;
+}
+
+perm_status BatchJob::run_pass(const std::vector<const PreparedMatrix *> &mats, const std::vector<int> &prime,
+                               double *raw, hipStream_t stream, BatchLaunch how, double *kernel_ms,
+                               std::string *err) {
+    const int count = (int)mats.size();
+    // order the matrices by kernel instance (ng, zero skip, exact), largest
+    // work first within an instance; results go back to the caller's order
     std::vector<int> order;
     for (int i = 0; i < count; ++i)
         if (!mats[i]->singular) order.push_back(i);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         if (mats[x]->ng != mats[y]->ng) return mats[x]->ng < mats[y]->ng;
         if (mats[x]->zero_skip != mats[y]->zero_skip) return mats[y]->zero_skip;
+        if (mats[x]->exact != mats[y]->exact) return mats[y]->exact;
         return mats[x]->n > mats[y]->n;
     });
-    for (int i = 0; i < count; ++i)
-        if (mats[i]->singular) out[i] = 0.0;
     const int nm = (int)order.size();
     if (nm == 0) {
         if (kernel_ms) *kernel_ms = 0.0;
@@ -237,21 +338,25 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
         d.kappa = pm.kappa;
         d.zero_skip = pm.zero_skip ? 1 : 0;
         d.chunk_top = pm.chunk_top;
-        d.pad = 0;
+        d.exact = pm.exact ? 1 : 0;
         d.nchunks = pm.nchunks;
         d.col_off = nvals;
         d.base_off = nvals + pm.base_index;
         d.top_off = ntops;
+        d.pmod = pm.exact ? kExactPrimes[prime[order[k]]] : 0.0;
+        d.pinv = pm.exact ? 1.0 / d.pmod : 0.0;
         nvals += pm.vals.size();
         ntops += pm.tops.size();
         const uint64_t items = (pm.nchunks + 63) / 64;
-        if (plans.empty() || plans.back().ng != pm.ng || plans.back().zero_skip != pm.zero_skip) {
+        if (plans.empty() || plans.back().ng != pm.ng || plans.back().zero_skip != pm.zero_skip ||
+            plans.back().exact != pm.exact) {
             plans.emplace_back();
             plans.back().ng = pm.ng;
             plans.back().zero_skip = pm.zero_skip;
+            plans.back().exact = pm.exact;
         }
         plans.back().add(k, 0, items, nparts);
-        fin[k] = FinishDesc{nparts, items, pm.n, 0};
+        fin[k] = FinishDesc{nparts, items, pm.n, pm.exact ? 1 : 0, d.pmod, d.pinv};
         nparts += items;
     }
     size_t nranges = 0, nblk = 0;
@@ -266,13 +371,13 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
     if ((s = grow(&d_vals, &cap_vals, nvals, err)) != PERM_OK) return s;
     if ((s = grow(&d_tops, &cap_tops, ntops, err)) != PERM_OK) return s;
     if ((s = grow(&d_fin, &cap_fin, (size_t)nm, err)) != PERM_OK) return s;
-    if ((s = grow(&d_partials, &cap_partials, 2 * nparts, err)) != PERM_OK) return s;
-    if ((s = grow(&d_out, &cap_out, (size_t)nm, err)) != PERM_OK) return s;
+    if ((s = grow(&d_partials, &cap_partials, (size_t)kPartStride * nparts, err)) != PERM_OK) return s;
+    if ((s = grow(&d_out, &cap_out, (size_t)kPartStride * nm, err)) != PERM_OK) return s;
     // one pinned staging buffer for all inputs
     const size_t bytes = nm * sizeof(BatchMat) + nranges * sizeof(BatchRange) + nblk * sizeof(int32_t) +
                          nvals * sizeof(double) + ntops * sizeof(int32_t) + nm * sizeof(FinishDesc) + 64;
     if ((s = grow_host(&h_stage, &cap_stage, bytes, err)) != PERM_OK) return s;
-    if ((s = grow_host(&h_out, &cap_hout, (size_t)nm, err)) != PERM_OK) return s;
+    if ((s = grow_host(&h_out, &cap_hout, (size_t)kPartStride * nm, err)) != PERM_OK) return s;
     char *p = h_stage;
     auto align8 = [&]() { p = h_stage + ((size_t)(p - h_stage) + 7) / 8 * 8; };
     char *s_mats = p;
@@ -333,8 +438,8 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
                 if (!used[c]) HIP_OK(hipStreamWaitEvent(st, ev0, 0));
                 used[c] = true;
             }
-            HIP_OK(launch_batch_ranges(w.ng, w.zero_skip, d_ranges + r0, (int)w.ranges.size(), d_blk + b0,
-                                       (int64_t)w.nwaves, d_mats, d_vals, d_tops, d_partials, st));
+            HIP_OK(launch_batch_ranges(w.ng, w.zero_skip, w.exact, d_ranges + r0, (int)w.ranges.size(),
+                                       d_blk + b0, (int64_t)w.nwaves, d_mats, d_vals, d_tops, d_partials, st));
             r0 += w.ranges.size();
             b0 += w.blk_first.size();
         }
@@ -375,14 +480,15 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
         if (es != PERM_OK) return es;
     }
     HIP_OK(hipEventRecord(ev1, stream));
-    HIP_OK(hipMemcpyAsync(h_out, d_out, nm * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemcpyAsync(h_out, d_out, (size_t)kPartStride * nm * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     if (kernel_ms) {
         float ms = 0;
         HIP_OK(hipEventElapsedTime(&ms, ev0, ev1));
         *kernel_ms = ms;
     }
-    for (int k = 0; k < nm; ++k) out[order[k]] = h_out[k];
+    for (int k = 0; k < nm; ++k)
+        for (int c = 0; c < kPartStride; ++c) raw[(size_t)kPartStride * order[k] + c] = h_out[kPartStride * k + c];
     return PERM_OK;
 }
 

@@ -19,18 +19,20 @@ namespace permx {
 
 // Launches the batch kernel for waves [0, nwaves) described by ranges[0,
 // nranges) (sorted by wave0, each non-empty, ranges[0].wave0 = 0) whose
-// matrices all have ng groups and the same zero_skip; blk_first[b] is the
-// range holding wave 4b.
-hipError_t launch_batch_ranges(int ng, bool zero_skip, const BatchRange *ranges, int nranges,
+// matrices all have ng groups and the same zero_skip and exact flags;
+// blk_first[b] is the range holding wave 4b.
+hipError_t launch_batch_ranges(int ng, bool zero_skip, bool exact, const BatchRange *ranges, int nranges,
                                const int32_t *blk_first, int64_t nwaves, const BatchMat *mats, const double *vals,
                                const int32_t *tops, double *partials, hipStream_t stream);
 
-// out[i] = (4 (n mod 2) - 2) * (partials of d[i], double-double, in an order
-// fixed by the partials' count), i = 0..count-1.
+// out[kPartStride i ..] = the sum of the partials of d[i] (double-double term
+// sum, residue, sum of |term|), added in an order fixed by the partials'
+// count, i = 0..count-1.
 hipError_t launch_batch_finish(const FinishDesc *d, int count, const double *partials, double *out,
                                hipStream_t stream);
 
-// Resources of the compiled batch kernel for ng groups (VGPRs, scratch).
-int batch_kernel_attributes(int ng, int *vgprs, int *scratch);
+// Resources of the compiled batch kernel for ng groups (VGPRs, scratch); the
+// exact-mode zero-skip instance when exact, else the plain one.
+int batch_kernel_attributes(int ng, bool exact, int *vgprs, int *scratch);
 
 }  // namespace permx

@@ -33,7 +33,7 @@ constexpr int batch_waves_per_eu() {
     return NG == 8 ? 4 : 1;
 }
 
-template <int NG, bool ZS>
+template <int NG, bool ZS, bool EX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<NG>()))) batch_kernel(const BatchRange *__restrict__ ranges, int nranges,
                                                     const int32_t *__restrict__ blk_first, long long nwaves,
                                                     const BatchMat *__restrict__ mats,
@@ -56,81 +56,114 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_
     const u64 m0 = chunk0 + (u64)lane;
     const bool active = m0 < md.nchunks;
     const u64 m = active ? m0 : chunk0;  // inactive lanes replay a valid chunk and add nothing
-    dd cs = batch_lane<NG, ZS>(md, vals, tops_all, m);
+    double xo[2] = {0.0, 0.0};
+    dd cs = batch_lane<NG, ZS, EX>(md, vals, tops_all, m, xo);
     if (!active) {
         cs.h = 0.0;
         cs.l = 0.0;
+        xo[0] = 0.0;
+        xo[1] = 0.0;
     }
     for (int off = 32; off > 0; off >>= 1) {
         dd o;
         o.h = __shfl_xor(cs.h, off, 64);
         o.l = __shfl_xor(cs.l, off, 64);
         cs = dd_add(cs, o);
+        if constexpr (EX) {
+            // residues: exact integer sums (64 lanes: below 2^30)
+            xo[0] += __shfl_xor(xo[0], off, 64);
+            xo[1] += __shfl_xor(xo[1], off, 64);
+        }
     }
     if (lane == 0) {
         const u64 out = rg.out0 + k;
-        partials[2 * out] = cs.h;
-        partials[2 * out + 1] = cs.l;
+        partials[kPartStride * out] = cs.h;
+        partials[kPartStride * out + 1] = cs.l;
+        partials[kPartStride * out + 2] = EX ? reduce_mod(xo[0], md.pmod, md.pinv) : 0.0;
+        partials[kPartStride * out + 3] = xo[1];
     }
 }
 
 // One workgroup per matrix: thread t adds partials t, t + 256, ... and a
 // fixed binary tree in LDS combines the 256 sums, so the order depends only
-// on the number of partials.
+// on the number of partials.  Residues (each below 2^23 + 2, at most 2^22 of
+// them) add exactly.
 __global__ void __launch_bounds__(256) batch_finish(const FinishDesc *__restrict__ d,
                                                     const double *__restrict__ partials, double *__restrict__ out) {
-    __shared__ double sh[2 * 256];
+    __shared__ double sh[4 * 256];
     const FinishDesc fd = d[blockIdx.x];
     const int t = threadIdx.x;
     dd acc;
     acc.h = 0.0;
     acc.l = 0.0;
+    double r = 0.0, a = 0.0;
     for (u64 k = t; k < fd.count; k += 256) {
+        const double *q = partials + kPartStride * (fd.part + k);
         dd v;
-        v.h = partials[2 * (fd.part + k)];
-        v.l = partials[2 * (fd.part + k) + 1];
+        v.h = q[0];
+        v.l = q[1];
         acc = dd_add(acc, v);
+        r += q[2];
+        a += q[3];
     }
-    sh[2 * t] = acc.h;
-    sh[2 * t + 1] = acc.l;
+    sh[4 * t] = acc.h;
+    sh[4 * t + 1] = acc.l;
+    sh[4 * t + 2] = r;
+    sh[4 * t + 3] = a;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if (t < s) {
-            dd a, b;
-            a.h = sh[2 * t];
-            a.l = sh[2 * t + 1];
-            b.h = sh[2 * (t + s)];
-            b.l = sh[2 * (t + s) + 1];
-            a = dd_add(a, b);
-            sh[2 * t] = a.h;
-            sh[2 * t + 1] = a.l;
+            dd x, y;
+            x.h = sh[4 * t];
+            x.l = sh[4 * t + 1];
+            y.h = sh[4 * (t + s)];
+            y.l = sh[4 * (t + s) + 1];
+            x = dd_add(x, y);
+            sh[4 * t] = x.h;
+            sh[4 * t + 1] = x.l;
+            sh[4 * t + 2] += sh[4 * (t + s) + 2];
+            sh[4 * t + 3] += sh[4 * (t + s) + 3];
         }
         __syncthreads();
     }
     if (t == 0) {
-        const double f = (fd.n % 2 == 1) ? 2.0 : -2.0;  // 4 (n mod 2) - 2
-        out[blockIdx.x] = (sh[0] + sh[1]) * f;
+        double *o = out + kPartStride * (u64)blockIdx.x;
+        o[0] = sh[0];
+        o[1] = sh[1];
+        o[2] = fd.exact ? reduce_mod(sh[2], fd.pmod, fd.pinv) : 0.0;
+        o[3] = sh[3];
     }
 }
 
+template <int NG, bool ZS, bool EX>
+void launch_one(unsigned blocks, const BatchRange *ranges, int nranges, const int32_t *blk_first, int64_t nwaves,
+                const BatchMat *mats, const double *vals, const int32_t *tops, double *partials, hipStream_t stream) {
+    hipLaunchKernelGGL((batch_kernel<NG, ZS, EX>), dim3(blocks), dim3(256), 0, stream, ranges, nranges, blk_first,
+                       (long long)nwaves, mats, vals, tops, partials);
+}
+
 template <int NG>
-hipError_t launch_t(bool zs, const BatchRange *ranges, int nranges, const int32_t *blk_first, int64_t nwaves,
-                    const BatchMat *mats, const double *vals, const int32_t *tops, double *partials,
+hipError_t launch_t(bool zs, bool ex, const BatchRange *ranges, int nranges, const int32_t *blk_first,
+                    int64_t nwaves, const BatchMat *mats, const double *vals, const int32_t *tops, double *partials,
                     hipStream_t stream) {
     const unsigned blocks = (unsigned)((nwaves + 3) / 4);
-    if (zs)
-        hipLaunchKernelGGL((batch_kernel<NG, true>), dim3(blocks), dim3(256), 0, stream, ranges, nranges, blk_first,
-                           (long long)nwaves, mats, vals, tops, partials);
+    if (zs && ex)
+        launch_one<NG, true, true>(blocks, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
+    else if (zs)
+        launch_one<NG, true, false>(blocks, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
+    else if (ex)
+        launch_one<NG, false, true>(blocks, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
     else
-        hipLaunchKernelGGL((batch_kernel<NG, false>), dim3(blocks), dim3(256), 0, stream, ranges, nranges,
-                           blk_first, (long long)nwaves, mats, vals, tops, partials);
+        launch_one<NG, false, false>(blocks, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
     return hipGetLastError();
 }
 
 template <int NG>
-void attrs_t(int *vgprs, int *scratch) {
+void attrs_t(bool ex, int *vgprs, int *scratch) {
     hipFuncAttributes a;
-    if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&batch_kernel<NG, false>)) == hipSuccess) {
+    const void *f = ex ? reinterpret_cast<const void *>(&batch_kernel<NG, true, true>)
+                       : reinterpret_cast<const void *>(&batch_kernel<NG, false, false>);
+    if (hipFuncGetAttributes(&a, f) == hipSuccess) {
         *vgprs = a.numRegs;
         *scratch = (int)a.localSizeBytes;
     }
@@ -140,14 +173,14 @@ void attrs_t(int *vgprs, int *scratch) {
 
 }  // namespace
 
-hipError_t launch_batch_ranges(int ng, bool zero_skip, const BatchRange *ranges, int nranges,
+hipError_t launch_batch_ranges(int ng, bool zero_skip, bool exact, const BatchRange *ranges, int nranges,
                                const int32_t *blk_first, int64_t nwaves, const BatchMat *mats, const double *vals,
                                const int32_t *tops, double *partials, hipStream_t stream) {
     if (nwaves <= 0) return hipSuccess;
     if (nranges <= 0 || (nwaves + 3) / 4 > 0x7fffffff) return hipErrorInvalidValue;
 #define PERM_CASE(NGV) \
     case NGV:          \
-        return launch_t<NGV>(zero_skip, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
+        return launch_t<NGV>(zero_skip, exact, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
     switch (ng) {
         PERM_NG_TABLE(PERM_CASE)
         default:
@@ -163,12 +196,12 @@ hipError_t launch_batch_finish(const FinishDesc *d, int count, const double *par
     return hipGetLastError();
 }
 
-int batch_kernel_attributes(int ng, int *vgprs, int *scratch) {
+int batch_kernel_attributes(int ng, bool exact, int *vgprs, int *scratch) {
     *vgprs = -1;
     *scratch = -1;
-#define PERM_CASE(NGV)                  \
-    case NGV:                           \
-        attrs_t<NGV>(vgprs, scratch);   \
+#define PERM_CASE(NGV)                       \
+    case NGV:                                \
+        attrs_t<NGV>(exact, vgprs, scratch); \
         return 0;
     switch (ng) {
         PERM_NG_TABLE(PERM_CASE)

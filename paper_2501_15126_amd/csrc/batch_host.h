@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "batch.h"
+#include "exact.h"
 #include "perm_internal.h"
 
 namespace permx {
@@ -15,6 +16,7 @@ namespace permx {
 struct BatchOptions {
     int zero_skip = 0;    // 0 auto (integer-valued matrices), 1 on, -1 off
     int kappa_shift = 0;  // added to the default chunk log2 (autotuning)
+    int exact = 0;        // 0 auto (integer-valued matrices whose groups' bounds allow it), 1 required, -1 off
 };
 
 // One matrix made ready for the batch kernels.
@@ -23,6 +25,7 @@ struct PreparedMatrix {
     int n = 0, ng = 0, kappa = 0;
     bool singular = false;
     bool zero_skip = false;
+    bool exact = false;        // values doubled (y = 2x); residues and the error bound's sum kept
     int chunk_top = 0;
     uint64_t nchunks = 0;
     std::vector<double> vals;  // [j][ng][4] column groups, then 4*ng base values
@@ -30,6 +33,7 @@ struct PreparedMatrix {
     std::vector<int32_t> tops; // top group per flipped column
     double fp64_ops = 0.0;     // FP64 operations of all chunks (an FMA is one), no skipping
     double fp64_fmas = 0.0;    // the FMAs among them
+    double exact_ops = 0.0;    // of fp64_ops: the exact mode's residue and bound operations
 };
 
 int batch_kappa(int n, int shift);
@@ -40,6 +44,7 @@ perm_status prepare_batch_matrix(const perm_csc *m, const BatchOptions &bo, Prep
 struct WavePlan {
     int ng = 0;
     bool zero_skip = false;
+    bool exact = false;
     std::vector<BatchRange> ranges;
     std::vector<int32_t> blk_first;
     uint64_t nwaves = 0;
@@ -88,9 +93,19 @@ struct BatchJob {
 
     ~BatchJob();
     // Runs all matrices (singular ones are answered 0 without work) and writes
-    // out[i] for mats[i].  Synchronous on `stream`.
+    // out[i] for mats[i].  Exact-mode matrices whose result is not certified
+    // after a pass run again with the next prime (exact.h).  Synchronous on
+    // `stream`.  Optional: exact_state[i] = 1 certified exact, 0 exact mode
+    // but uncertified, -1 not in exact mode; *passes = passes run.
     perm_status run(const std::vector<const PreparedMatrix *> &mats, double *out, hipStream_t stream,
-                    BatchLaunch how, double *kernel_ms, std::string *err);
+                    BatchLaunch how, double *kernel_ms, std::string *err, int *exact_state = nullptr,
+                    int *passes = nullptr);
+
+  private:
+    // One pass: raw[kPartStride i ..] = (term sum hi, lo, residue, sum |term|)
+    // of mats[i] with the prime kExactPrimes[prime[i]] for exact ones.
+    perm_status run_pass(const std::vector<const PreparedMatrix *> &mats, const std::vector<int> &prime,
+                         double *raw, hipStream_t stream, BatchLaunch how, double *kernel_ms, std::string *err);
 };
 
 }  // namespace permx

@@ -71,7 +71,8 @@ struct Gen {
     int qslots = 0;
     int qtop = 0;
     std::vector<int> qrows;
-    int qfields() const { return (int)qrows.size() + 2; }
+    // (exact mode: then R_{qtop+1}, the residue of S_{qtop+1})
+    int qfields() const { return (int)qrows.size() + 2 + (p.exact ? 1 : 0); }
 
     std::string fresh() { return "t" + std::to_string(tmp++); }
     std::string xname(int r) const { return "x" + std::to_string(r); }
@@ -96,23 +97,62 @@ struct Gen {
         return vals[0];
     }
 
-    // Names of the current x values of level l's rows; cold rows not in
-    // `cur` are loaded from global memory.
+    // Name of row r's current x value; a cold row not in `cur` is loaded
+    // from global memory (or LDS).
+    std::string value_of(int r, std::map<int, std::string> &cur, const char *ind) {
+        if (r < p.k) return xname(r);
+        auto it = cur.find(r);
+        if (it != cur.end()) return it->second;
+        std::string t = fresh();
+        os << ind << "const double " << t << " = " << cold_addr(r) << ";\n";
+        cur[r] = t;
+        return t;
+    }
+
+    // Names of the current x values of level l's rows.
     std::vector<std::string> level_values(int l, std::map<int, std::string> &cur, const char *ind) {
         std::vector<std::string> v;
-        for (int r : level_rows[l]) {
-            if (r < p.k) {
-                v.push_back(xname(r));
-            } else if (cur.count(r)) {
-                v.push_back(cur[r]);
-            } else {
-                std::string t = fresh();
-                os << ind << "const double " << t << " = " << cold_addr(r) << ";\n";
-                cur[r] = t;
-                v.push_back(t);
-            }
-        }
+        for (int r : level_rows[l]) v.push_back(value_of(r, cur, ind));
         return v;
+    }
+
+    // ---- exact mode (integer-valued matrices, x holds y = 2x) ----
+    // The products of level l's sub-products (each an exact integer of at
+    // most 2^20 in magnitude); `weight` (0 or 1) joins the first.
+    std::vector<std::string> part_products(int l, std::map<int, std::string> &cur, const char *I,
+                                           const char *weight = nullptr) {
+        std::vector<std::string> qs;
+        const auto &parts = p.level_parts[l];
+        for (size_t pi = 0; pi < parts.size(); ++pi) {
+            std::vector<std::string> v;
+            for (int r : parts[pi]) v.push_back(value_of(r, cur, I));
+            if (pi == 0 && weight) v.push_back(weight);
+            qs.push_back(product(v, I));
+        }
+        return qs;
+    }
+
+    // q * r reduced modulo the prime: |q| <= 2^20 and |r| < 2^23 + 2, so the
+    // product is exact (< 2^44) and rint(t / p) is within one of its quotient;
+    // the result lies in (-p/2 - 2, p/2 + 2).
+    std::string mulmod(const std::string &q, const std::string &r, const char *I) {
+        const std::string t = fresh(), m = fresh();
+        os << I << "const double " << t << " = " << q << " * " << r << ";\n";
+        os << I << "const double " << m << " = fma(-rint(" << t << " * pinv), pmod, " << t << ");\n";
+        return m;
+    }
+
+    // residue of sub-products qs[from..] times `r` (r empty: no factor)
+    std::string residue_chain(const std::vector<std::string> &qs, size_t from, std::string r, const char *I) {
+        for (size_t i = qs.size(); i-- > from;) r = r.empty() ? qs[i] : mulmod(qs[i], r, I);
+        return r;
+    }
+
+    // racc back to (-p/2 - 2, p/2 + 2): after at most 1023 terms of at most
+    // 2^20 (2^23 + 2) each it is below 2^53, where rint(racc / p) is exact
+    // enough for an exact remainder.
+    void reduce_racc(const char *I) {
+        if (p.exact) os << I << "racc = fma(-rint(racc * pinv), pmod, racc);\n";
     }
 
     // x updates of one Gray step flipping column j in direction sg; updated
@@ -144,6 +184,18 @@ struct Gen {
 
     // Recompute the cached product of level l: S_l = prod(level l) * S_{l+1}.
     void refresh_level(int l, std::map<int, std::string> &cur, const char *I) {
+        if (p.exact) {
+            // S_l = P_l * S_{l+1} in FP64; R_l = P_l R_{l+1} modulo the prime
+            const std::vector<std::string> qs = part_products(l, cur, I);
+            const std::string pl = product(qs, I);
+            const bool top = l + 1 >= p.nlevels;
+            os << I << "S" << l << " = " << pl;
+            if (!top) os << " * S" << l + 1;
+            os << ";\n";
+            const std::string r = residue_chain(qs, 0, top ? "" : "R" + std::to_string(l + 1), I);
+            os << I << "R" << l << " = " << r << ";\n";
+            return;
+        }
         std::vector<std::string> v = level_values(l, cur, I);
         if (l + 1 < p.nlevels) v.push_back("S" + std::to_string(l + 1));
         std::string prod = product(v, I);
@@ -169,6 +221,28 @@ struct Gen {
     // acc += term_sign * (product of level 0) * S_1   (one FMA)
     void accumulate(int term_sign, int acc, std::map<int, std::string> &cur, const char *I,
                     const char *weight = nullptr) {
+        if (p.exact) {
+            // the term is pr * last (exact inside the FMA); its residue is the
+            // first sub-product times the residue of the rest; A (the error
+            // bound's sum) takes |term|
+            const std::vector<std::string> qs = part_products(0, cur, I, weight);
+            const char *sg = term_sign < 0 ? "-" : "";
+            std::string pr, last, rest;
+            if (p.nlevels > 1) {
+                pr = product(qs, I);
+                last = "S1";
+                rest = residue_chain(qs, 1, "R1", I);
+            } else {
+                std::vector<std::string> head(qs.begin(), qs.end() - 1);
+                pr = product(head, I);
+                last = qs.back();
+                rest = qs.size() > 1 ? residue_chain(qs, 1, "", I) : "1.0";
+            }
+            os << I << "acc" << acc << " = fma(" << sg << pr << ", " << last << ", acc" << acc << ");\n";
+            os << I << "racc = fma(" << sg << qs[0] << ", " << rest << ", racc);\n";
+            os << I << "accA = fma(fabs(" << pr << "), fabs(" << last << "), accA);\n";
+            return;
+        }
         std::vector<std::string> v = level_values(0, cur, I);
         if (weight) v.push_back(weight);
         std::string last;
@@ -255,6 +329,7 @@ struct Gen {
                 neg = second;              // bit u of the local index
             step(j, neg ? Sign::Minus : Sign::Plus, (i & 1) ? -1 : 1, (i >> 1) & 1, ind);
         }
+        if (U > 1) reduce_racc(ind);
     }
 
     std::string run() {
@@ -319,32 +394,41 @@ struct Gen {
         // block_eval: the 2^(u+1) - 1 steps of a queued block pair from its
         // start state it[field * QS] (rows of levels <= qtop, S_{qtop+1}, the
         // direction of the middle step), the same arithmetic as in place.
-        os << "__device__ __forceinline__ dd block_eval(const double* __restrict__ it, u32 &ev) {\n";
+        os << "__device__ __forceinline__ dd block_eval(const double* __restrict__ it, u32 &ev, double* __restrict__ xo,\n"
+              "                                         const double pmod, const double pinv) {\n";
         if (use_queue) {
             for (size_t i = 0; i < qrows.size(); ++i)
                 os << "  double " << xname(qrows[i]) << " = it[" << i * QS << "];\n";
             os << "  double S" << qtop + 1 << " = it[" << qrows.size() * QS << "];\n";
             os << "  const double lsgn = it[" << (qrows.size() + 1) * QS << "];\n";
-            for (int l = qtop; l >= 1; --l) os << "  double S" << l << ";\n";
+            if (p.exact) os << "  double R" << qtop + 1 << " = it[" << (qrows.size() + 2) * QS << "];\n";
+            for (int l = qtop; l >= 1; --l) os << "  double S" << l << (p.exact ? ", R" + std::to_string(l) : "") << ";\n";
             {
                 std::map<int, std::string> cur;
                 for (int l = qtop; l >= 1; --l) refresh_level(l, cur, "  ");
             }
             os << "  double acc0 = 0.0, acc1 = 0.0;\n";
+            if (p.exact) os << "  double racc = 0.0, accA = 0.0;\n";
             os << "  ev += " << (2 * U - 1) << "u;\n";
             static_block(false, "  ");
             step(u, Sign::Lane, 1, 0, "  ");
             static_block(true, "  ");
+            if (p.exact) os << "  xo[0] += racc; xo[1] += accA;\n";
+            else os << "  (void)xo; (void)pmod; (void)pinv;\n";
             os << "  return two_sum(acc0, acc1);\n";
         } else {
-            os << "  (void)it; (void)ev;\n  dd r; r.h = 0.0; r.l = 0.0; return r;\n";
+            os << "  (void)it; (void)ev; (void)xo; (void)pmod; (void)pinv;\n  dd r; r.h = 0.0; r.l = 0.0; return r;\n";
         }
         os << "}\n";
         // perm_lane: `act` is false for a lane past the last chunk (it queues
         // nothing); qw is this wave's queue region and qc its fill (uniform).
+        // exact mode: xo receives the lane's residue of its term sum modulo
+        // pmod and its sum |term| (the error bound's sum)
         os << "__device__ __forceinline__ dd perm_lane(const u64 m, double* __restrict__ xg, const u64 xs,\n"
               "                                        const u64 lid, const bool act, double* __restrict__ qw,\n"
-              "                                        u32 &qc, u32 &ev) {\n";
+              "                                        u32 &qc, u32 &ev, double* __restrict__ xo,\n"
+              "                                        const double pmod, const double pinv) {\n";
+        if (!p.exact) os << "  (void)xo; (void)pmod; (void)pinv;\n";
         if (!use_queue) os << "  (void)act; (void)qw; (void)qc;\n";
         os << "  ev = 1u;\n";
         os << "  const u64 g0 = m << "
@@ -388,12 +472,21 @@ struct Gen {
             cur[r] = "cx" + std::to_string(r);
         }
         for (int l = L - 1; l >= 1; --l) {
+            if (p.exact) {
+                const std::vector<std::string> qs = part_products(l, cur, "  ");
+                const std::string pl = product(qs, "  ");
+                os << "  double S" << l << " = " << pl << (l + 1 < L ? " * S" + std::to_string(l + 1) : "") << ";\n";
+                const std::string r = residue_chain(qs, 0, l + 1 < L ? "R" + std::to_string(l + 1) : "", "  ");
+                os << "  double R" << l << " = " << r << ";\n";
+                continue;
+            }
             std::vector<std::string> v = level_values(l, cur, "  ");
             if (l + 1 < L) v.push_back("S" + std::to_string(l + 1));
             std::string prod = product(v, "  ");
             os << "  double S" << l << " = " << prod << ";\n";
         }
         os << "  double acc0 = 0.0, acc1 = 0.0;\n";
+        if (p.exact) os << "  double racc = 0.0, accA = 0.0;\n";
         accumulate(+1, 0, cur, "  ");  // term g = m 2^kappa (even index: sign +)
         // ---- Gray loop over local steps 1 .. 2^kappa - 1 ----
         if (kappa >= 1) {
@@ -466,6 +559,8 @@ struct Gen {
                         for (size_t i = 0; i < qrows.size(); ++i)
                             os << in3 << "qw[" << i * QS << "u + sl] = " << xname(qrows[i]) << ";\n";
                         os << in3 << "qw[" << qrows.size() * QS << "u + sl] = S" << block_top + 1 << ";\n";
+                        if (p.exact)
+                            os << in3 << "qw[" << (qrows.size() + 2) * QS << "u + sl] = R" << block_top + 1 << ";\n";
                         os << in3 << "qw[" << (qrows.size() + 1) * QS << "u + sl] = ";
                         if (u + 1 == kappa)
                             os << "lsgn;\n";
@@ -497,6 +592,7 @@ struct Gen {
                     os << bi << "}\n";
                 }
                 static_block(true, bi);
+                if (U == 1) reduce_racc(bi);
                 if (skip_block) os << ind << "}\n";
             };
             // local step ell (a multiple of 2^(u+1)): column jj = ctz(ell) >= u + 1,
@@ -570,6 +666,10 @@ struct Gen {
             }
             if (skip_chunk) os << "  }\n";
         }
+        if (p.exact) {
+            reduce_racc("  ");
+            os << "  xo[0] = racc; xo[1] = accA;\n";
+        }
         os << "  return two_sum(acc0, acc1);\n}\n";
         // ---- the kernel: one chunk per lane, then a deterministic reduction
         //      lane -> wave (butterfly) -> workgroup ----
@@ -578,7 +678,9 @@ struct Gen {
         if (p.waves_per_simd > 0) os << "__attribute__((amdgpu_waves_per_eu(" << p.waves_per_simd << "))) ";
         os << kGrayKernelName
            << "(const u64 chunk_begin, const u64 chunk_end, double* __restrict__ partials,\n"
-              "    u64* __restrict__ counts, double* __restrict__ xg, const u64 xs) {\n";
+              "    u64* __restrict__ counts, double* __restrict__ xg, const u64 xs,\n"
+              "    double* __restrict__ xparts, const double pmod, const double pinv) {\n";
+        if (!p.exact) os << "  (void)xparts;\n";
         os << "  const u64 lid = (u64)blockIdx.x * " << p.block << "u + threadIdx.x;\n"
               "  const bool active = chunk_begin + lid < chunk_end;\n"
               "  // an inactive lane (past the last chunk) replays a valid chunk and contributes 0\n"
@@ -589,8 +691,9 @@ struct Gen {
             os << "  double* qw = bq + wid * " << qfields() * QS << "u;\n";
         else
             os << "  double* qw = nullptr;\n";
-        os << "  dd cs = perm_lane(m, xg, xs, lid, active, qw, qc, ev);\n"
-              "  if (!active) { cs.h = 0.0; cs.l = 0.0; }\n";
+        os << "  double xo[2] = {0.0, 0.0};\n"
+              "  dd cs = perm_lane(m, xg, xs, lid, active, qw, qc, ev, xo, pmod, pinv);\n"
+              "  if (!active) { cs.h = 0.0; cs.l = 0.0; xo[0] = 0.0; xo[1] = 0.0; }\n";
         if (use_queue) {
             // the workgroup's queued blocks, item g (waves in order, then
             // slots) evaluated by thread g: at most 64 per wave, so one pass
@@ -603,7 +706,7 @@ struct Gen {
                   "    if (g < total) {\n"
                   "      u32 ww = 0u, b0 = 0u;\n"
                   "      while (g >= b0 + bqn[ww]) { b0 += bqn[ww]; ++ww; }\n"
-                  "      cs = dd_add(cs, block_eval(bq + ww * " << qfields() * QS << "u + (g - b0), ev));\n"
+                  "      cs = dd_add(cs, block_eval(bq + ww * " << qfields() * QS << "u + (g - b0), ev, xo, pmod, pinv));\n"
                   "    }\n"
                   "  }\n";
         }
@@ -613,6 +716,16 @@ struct Gen {
               "    cs = dd_add(cs, o);\n"
               "    e64 += __shfl_xor(e64, off, 64);\n"
               "  }\n";
+        if (p.exact) {
+            // residues: each lane's back in (-p/2 - 2, p/2 + 2), then exact sums
+            // (64 lanes, then the waves: below 2^34); A: a plain sum
+            os << "  double xr = fma(-rint(xo[0] * pinv), pmod, xo[0]), xa = xo[1];\n"
+                  "  for (int off = 32; off > 0; off >>= 1) {\n"
+                  "    xr += __shfl_xor(xr, off, 64); xa += __shfl_xor(xa, off, 64);\n"
+                  "  }\n";
+            os << "  __shared__ double wx[" << 2 * nw << "];\n"
+                  "  if ((threadIdx.x & 63u) == 0) { wx[2 * wid] = xr; wx[2 * wid + 1] = xa; }\n";
+        }
         os << "  __shared__ double wsum[" << 2 * nw << "];\n"
               "  __shared__ u64 wev[" << nw << "];\n"
               "  if ((threadIdx.x & 63u) == 0) { wsum[2 * wid] = cs.h; wsum[2 * wid + 1] = cs.l; wev[wid] = e64; }\n"
@@ -623,8 +736,13 @@ struct Gen {
         os << "    u64 te = 0;\n    for (int w = 0; w < " << nw << "; ++w) te += wev[w];  // lane-terms\n";
         os << "    counts[blockIdx.x] = te;\n";
         os << "    partials[2 * (u64)blockIdx.x] = t.h;\n"
-              "    partials[2 * (u64)blockIdx.x + 1] = t.l;\n"
-              "  }\n"
+              "    partials[2 * (u64)blockIdx.x + 1] = t.l;\n";
+        if (p.exact)
+            os << "    double r = 0.0, a = 0.0;\n"
+                  "    for (int w = 0; w < " << nw << "; ++w) { r += wx[2 * w]; a += wx[2 * w + 1]; }\n"
+                  "    xparts[2 * (u64)blockIdx.x] = fma(-rint(r * pinv), pmod, r);\n"
+                  "    xparts[2 * (u64)blockIdx.x + 1] = a;\n";
+        os << "  }\n"
               "}\n";
         return os.str();
     }

@@ -76,8 +76,15 @@ struct Plan {
     int queue_slots = 0;                // per-wave queue of partly needed blocks: slots,
                                         // 0 = the most that fit, -1 = none
     bool zero_skip = true;              // skip chunks / blocks whose terms are exactly 0
+    // Exact mode (integer-valued matrices): B holds 2a, so x is y = 2x, an
+    // integer; the kernel also keeps the term sum modulo a prime and the two
+    // sums of its error bound (exact.h).  Each level's product is formed from
+    // sub-products of the rows in level_parts[l], each bounded by kExactPartMax.
+    bool exact = false;
+    std::vector<std::vector<std::vector<int>>> level_parts;
     double base_x_hi[PERM_MAX_N];       // x_r at Gray index 0 (Alg. 1's initialisation)
     double ops_per_step = 0, flops_per_step = 0;
+    double exact_ops_per_step = 0;      // of ops_per_step: residue and error-bound operations
     std::vector<double> ops_of_col;     // FP64 VALU ops of one step flipping column j
 };
 

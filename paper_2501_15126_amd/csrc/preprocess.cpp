@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 
+#include "exact.h"
 #include "perm_internal.h"
 
 namespace permx {
@@ -120,6 +121,11 @@ namespace {
 // reduction.  Used only by the plan's budget (the real count comes from the
 // compiled code object).
 constexpr int kBaseVgprs = 28;
+// Exact mode's further registers in the plan's budget: the residue and |term|
+// accumulators and the prime with its reciprocal.  (The compiler's count did
+// not follow the level count here: the n = 40 0/1 kernel took 136 VGPRs with
+// 12 levels and 138 with 9.)
+constexpr int kExactBaseVgprs = 6;
 
 // Chunk log2 (Gray steps per lane) and static block log2, measured on
 // MI355X.  All-terms kernels: about 2^21 lanes (8 resident rounds of the 4096
@@ -164,11 +170,32 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         *err = "unknown mode";
         return PERM_EINVAL;
     }
+    // Exact mode: every value an integer, and every row's |y| bound (the sum
+    // of its |a|) within one sub-product bound.  0 = auto (on when possible).
+    if (o.exact < -1 || o.exact > 1) {
+        *err = "exact must be -1 (off), 0 (automatic) or 1 (required)";
+        return PERM_EINVAL;
+    }
+    bool ex = false;
+    if (o.exact >= 0) {
+        bool ok = integer_valued(a);
+        std::vector<double> rowabs(n, 0.0);
+        for (int q = 0; q < a.nnz(); ++q) rowabs[a.rowidx[q]] += std::fabs(a.val[q]);
+        for (int r = 0; r < n && ok; ++r) ok = rowabs[r] <= kExactPartMax;
+        if (o.exact == 1 && !ok) {
+            *err = "exact = 1 needs integer values with every row's sum of |a| at most 2^20";
+            return PERM_EINVAL;
+        }
+        ex = ok;
+    }
     if (o.mode == PERM_MODE_PURE)
         degree_ordering(a, p->rowPerm, p->colPerm);
     else
         permanent_ordering(a, p->rowPerm, p->colPerm);
     p->B = permute(a, p->rowPerm, p->colPerm);
+    if (ex)
+        for (double &v : p->B.val) v *= 2.0;  // y = 2x: every x update and start value an integer
+    p->exact = ex;
     const Ccs &B = p->B;
 
     // first flipped column (0..n-2) touching each ordered row; n-1 if none
@@ -230,7 +257,11 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         int live_rows = 0;
         for (int r = 0; r < k; ++r)
             if (first[r] < kap) ++live_rows;
-        auto vgprs = [&](int nlev) { return 2 * live_rows + 2 * (nlev + cold_levels - 1) + kBaseVgprs; };
+        // exact mode: a residue beside each cached product, and the residue
+        // and error-bound accumulators
+        auto vgprs = [&](int nlev) {
+            return 2 * live_rows + (ex ? 4 : 2) * (nlev + cold_levels - 1) + kBaseVgprs + (ex ? kExactBaseVgprs : 0);
+        };
         int cap = o.max_levels > 0 ? o.max_levels : INT_MAX;
         while ((int)lev_begin.size() > 1 && ((int)lev_begin.size() > cap || vgprs((int)lev_begin.size()) > budget))
             lev_begin.pop_back();  // merge the two highest (least often touched) levels
@@ -252,6 +283,24 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         int l = 0;
         while (l + 1 < nreg_levels && lev_begin[l + 1] <= f) ++l;
         p->row_level[r] = l;
+    }
+    // exact mode: each level's rows in consecutive sub-products whose bound
+    // (product of the rows' sums of |a|) stays within kExactPartMax
+    if (ex) {
+        std::vector<double> bound(n, 0.0);
+        for (int q = 0; q < B.nnz(); ++q) bound[B.rowidx[q]] += std::fabs(B.val[q]) / 2;
+        p->level_parts.assign(p->nlevels, {});
+        std::vector<double> cur(p->nlevels, 0.0);
+        for (int r = 0; r < n; ++r) {
+            const int l = p->row_level[r];
+            auto &parts = p->level_parts[l];
+            if (parts.empty() || cur[l] * bound[r] > kExactPartMax) {
+                parts.push_back({});
+                cur[l] = 1.0;
+            }
+            parts.back().push_back(r);
+            cur[l] *= bound[r];
+        }
     }
     p->col_top.assign(n, 0);
     for (int j = 0; j < n - 1; ++j) {
@@ -330,7 +379,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
     std::vector<int> level_size(p->nlevels, 0);
     for (int r = 0; r < n; ++r) level_size[p->row_level[r]]++;
     p->ops_of_col.assign(n, 0.0);
-    double ops = 0.0;
+    double ops = 0.0, exact_ops = 0.0;
     const double steps = std::ldexp(1.0, n - 1);
     const int L = p->nlevels;
     // A level that the flipped column does not touch keeps its x values, so
@@ -348,10 +397,22 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         for (int l = 1; l <= t; ++l)
             if (l < L - 1) oj += 1;  // chain multiply by S_{l+1}
         if (L > 1) oj += 1;          // accumulate: fma(P_0, S_1, acc)
+        if (ex) {
+            // residue chain: one reduction (4 operations) per sub-product of
+            // each refreshed level (the top level's first needs none), the
+            // level-0 sub-products but one, then the residue FMA and the two
+            // error-bound sums
+            double xo = 0.0;
+            for (int l = 1; l <= t; ++l) xo += 4.0 * ((double)p->level_parts[l].size() - (l + 1 < L ? 0.0 : 1.0));
+            xo += 4.0 * ((double)p->level_parts[0].size() - 1.0) + 3.0;
+            oj += xo;
+            exact_ops += std::ldexp(1.0, n - j - 2) * xo;
+        }
         p->ops_of_col[j] = oj;
         ops += std::ldexp(1.0, n - j - 2) * oj;
     }
     p->ops_per_step = ops / steps;
+    p->exact_ops_per_step = exact_ops / steps;
     // the accumulate FMA replaces a multiply and an add of Alg. 1 (counts 2)
     p->flops_per_step = (ops + (steps - 1.0)) / steps;
     return PERM_OK;

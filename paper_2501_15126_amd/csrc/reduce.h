@@ -11,4 +11,8 @@ namespace permx {
 hipError_t launch_final_reduce(const double *partials, const unsigned long long *counts, long long count,
                                double *out, unsigned long long *count_out, hipStream_t stream);
 
+// Exact mode: out[0..1] = column sums of count (residue, sum |term|) pairs,
+// in an order fixed by the index.
+hipError_t launch_final_reduce_x(const double *xparts, long long count, double *out, hipStream_t stream);
+
 }  // namespace permx

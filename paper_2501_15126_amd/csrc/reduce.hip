@@ -100,9 +100,42 @@ __global__ void __launch_bounds__(kThreads) final_reduce(const double *__restric
     }
 }
 
+// Exact mode: per-workgroup (residue, sum |term|) pairs summed column by
+// column in the same fixed order.  Residues are integers below 2^23 + 2 in
+// magnitude, so their sum over at most 2^23 workgroups is exact.
+__global__ void __launch_bounds__(kThreads) final_reduce_x(const double *__restrict__ xparts, long long count,
+                                                            double *__restrict__ out) {
+    __shared__ double sh[2 * kThreads];
+    const int t = threadIdx.x;
+    double r = 0.0, a = 0.0;
+    for (long long b = t; b < count; b += kThreads) {
+        r += xparts[2 * b];
+        a += xparts[2 * b + 1];
+    }
+    sh[2 * t] = r;
+    sh[2 * t + 1] = a;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            sh[2 * t] += sh[2 * (t + s)];
+            sh[2 * t + 1] += sh[2 * (t + s) + 1];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = sh[0];
+        out[1] = sh[1];
+    }
+}
+
 }  // namespace
 
 namespace permx {
+
+hipError_t launch_final_reduce_x(const double *xparts, long long count, double *out, hipStream_t stream) {
+    hipLaunchKernelGGL(final_reduce_x, dim3(1), dim3(kThreads), 0, stream, xparts, count, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_final_reduce(const double *partials, const unsigned long long *counts, long long count,
                                double *out, unsigned long long *count_out, hipStream_t stream) {

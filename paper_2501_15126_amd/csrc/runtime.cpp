@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "batch_host.h"
+#include "exact.h"
 #include "jit.h"
 #include "perm_internal.h"
 #include "reduce.h"
@@ -64,7 +65,9 @@ struct DeviceState {
     size_t xg_cap = 0;        // doubles
     unsigned long long *counts = nullptr;  // evaluated terms per workgroup
     size_t counts_cap = 0;
-    double *out = nullptr;    // 2 doubles, then the evaluated-term total (u64)
+    double *xparts = nullptr;  // exact mode: (residue, sum |term|) per workgroup
+    size_t xparts_cap = 0;
+    double *out = nullptr;    // 2 doubles, the evaluated-term total (u64), then the 3 exact-mode sums
     double *host_out = nullptr;  // pinned host copy of out
     std::unordered_map<std::string, LoadedKernel> kernels;  // source -> module
 };
@@ -88,8 +91,8 @@ perm_status ensure_device() {
         return fail(PERM_EDEVICE, "device " + g_dev.arch + " is not gfx950 (MI355X); kernels are built for gfx950 only");
     HIP_TRY(hipStreamCreateWithFlags(&g_dev.stream, hipStreamNonBlocking));
     for (auto &ev : g_dev.ev) HIP_TRY(hipEventCreate(&ev));
-    HIP_TRY(hipMalloc(&g_dev.out, 4 * sizeof(double)));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&g_dev.host_out), 4 * sizeof(double), hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&g_dev.out, 8 * sizeof(double)));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&g_dev.host_out), 8 * sizeof(double), hipHostMallocDefault));
     g_dev.ready = true;
     return PERM_OK;
 }
@@ -204,6 +207,8 @@ void fill_plan_stats(const Prepared &p, perm_stats *st) {
     st->block = pl.block;
     st->ops_per_step = pl.ops_per_step;
     st->flops_per_step = pl.flops_per_step;
+    st->exact_ops_per_step = pl.exact_ops_per_step;
+    st->exact = pl.exact ? 0 : -1;  // set to 1 once a result is certified
     st->nchunks = (int64_t)1 << (pl.n - 1 - pl.kappa);
     st->nblocks = (st->nchunks + pl.block - 1) / pl.block;
 }
@@ -237,7 +242,7 @@ bool plan_key(const perm_csc *m, const perm_opts &o, std::string *key) {
     }
     const int32_t f[] = {o.mode,     o.chunk_log2, o.unroll_log2, o.block,     o.vgpr_budget,
                          o.force_k,  o.force_c,    o.max_levels,  o.zero_skip, o.cold_tier,
-                         o.waves_per_simd, o.block_queue};
+                         o.waves_per_simd, o.block_queue, o.exact};
     put(f, sizeof f);
     put(&o.gr_ratio, sizeof o.gr_ratio);
     return true;
@@ -274,63 +279,40 @@ perm_status acquire_plan(const perm_csc *m, const perm_opts &o, std::shared_ptr<
     return PERM_OK;
 }
 
-perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_stats *st_out) {
-    auto t0 = std::chrono::steady_clock::now();
-    perm_stats st;
-    memset(&st, 0, sizeof st);
-    const perm_opts o = defaults(opts);
-    std::shared_ptr<CachedPlan> cp;
-    bool plan_hit = false;
-    {
-        perm_status s = acquire_plan(m, o, &cp, &plan_hit);
-        if (s != PERM_OK) return s;
-    }
-    const Prepared &p = cp->p;
-    const CodeObject &co = cp->co;
-    fill_plan_stats(p, &st);
-    st.host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() -
-                 (plan_hit ? 0.0 : co.compile_ms);
-    if (p.singular) {
-        *out = 0.0;  // no perfect matching: every permutation product has a zero factor
-        st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        if (st_out) *st_out = st;
-        return PERM_OK;
-    }
-    st.compile_ms = plan_hit ? 0.0 : co.compile_ms;
-    st.cache_hit = (plan_hit || co.cache_hit) ? 1 : 0;
-    st.vgprs = co.vgprs;
-    st.sgprs = co.sgprs;
-    st.scratch_bytes = co.scratch_bytes;
-    st.lds_bytes = co.lds_bytes;
-    st.waves_hint = p.plan.waves_per_simd;
-    st.vgpr_spills = co.vgpr_spills;
-    std::lock_guard<std::mutex> g(g_mu);
-    perm_status s = ensure_device();
-    if (s != PERM_OK) return s;
-    if (!cp->kern) {
-        s = load_kernel(p.src, co, p.plan.block, &cp->kern);
-        if (s != PERM_OK) return s;
-    }
-    LoadedKernel *kern = cp->kern;
-    st.waves_per_simd = kern->waves_per_simd;
+// What one pass of a plan's kernel over the whole Gray-index space returns.
+struct PassOut {
+    double hi = 0.0, lo = 0.0;            // term sum (double-double), before the final factor
+    double evaluated = 0.0;               // lane-terms evaluated
+    double resid = 0.0, abs_sum = 0.0;    // exact mode sums
+    double kernel_ms = 0.0, reduce_ms = 0.0;
+};
 
-    const Plan &pl = p.plan;
-    const int64_t nchunks = st.nchunks;
-    const int64_t nblocks = st.nblocks;
+// All launches of one pass (prime: the residue's modulus in exact mode),
+// the fixed-order reductions and the copy of the result to the host.  g_mu held.
+perm_status run_pass(CachedPlan &cp, double prime, const perm_opts &o, hipStream_t stream, double *block_partials,
+                     int64_t block_partials_cap, PassOut *po) {
+    const Plan &pl = cp.p.plan;
+    LoadedKernel *kern = cp.kern;
+    const int64_t nchunks = (int64_t)1 << (pl.n - 1 - pl.kappa);
+    const int64_t nblocks = (nchunks + pl.block - 1) / pl.block;
     const double steps_per_block = std::ldexp((double)pl.block, pl.kappa);
     const int64_t launch_blocks = std::max<int64_t>(
         1, std::min<int64_t>(std::min<int64_t>(nblocks, kMaxBlocksPerLaunch),
                              (int64_t)(kMaxStepsPerLaunch / steps_per_block)));
-    s = ensure_buffer(&g_dev.partials, &g_dev.partials_cap, 2 * (size_t)nblocks);
+    perm_status s = ensure_buffer(&g_dev.partials, &g_dev.partials_cap, 2 * (size_t)nblocks);
     if (s != PERM_OK) return s;
     s = ensure_buffer(reinterpret_cast<double **>(&g_dev.counts), &g_dev.counts_cap, (size_t)nblocks);
     if (s != PERM_OK) return s;
+    if (pl.exact) {
+        s = ensure_buffer(&g_dev.xparts, &g_dev.xparts_cap, 2 * (size_t)nblocks);
+        if (s != PERM_OK) return s;
+    }
     const uint64_t xs = (uint64_t)launch_blocks * pl.block;  // lanes of one launch
     if (pl.cold && !pl.cold_lds) {
         s = ensure_buffer(&g_dev.xg, &g_dev.xg_cap, (size_t)(pl.n - pl.k) * xs);
         if (s != PERM_OK) return s;
     }
-    hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : g_dev.stream;
+    const double pmod = prime, pinv = prime > 0.0 ? 1.0 / prime : 0.0;
     HIP_TRY(hipEventRecord(g_dev.ev[0], stream));
     const int64_t nlaunch = (nblocks + launch_blocks - 1) / launch_blocks;
     std::vector<hipEvent_t> done;  // per launch, only with o.progress
@@ -342,7 +324,9 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
         unsigned long long *cnt = g_dev.counts + b0;
         double *xg = g_dev.xg;
         uint64_t xs_arg = xs;
-        void *args[] = {&chunk_begin, &chunk_end, &part, &cnt, &xg, &xs_arg};
+        double *xp = pl.exact ? g_dev.xparts + 2 * b0 : nullptr;
+        double pm = pmod, pi = pinv;
+        void *args[] = {&chunk_begin, &chunk_end, &part, &cnt, &xg, &xs_arg, &xp, &pm, &pi};
         HIP_TRY(hipModuleLaunchKernel(kern->fn, (unsigned)nb, 1, 1, (unsigned)pl.block, 1, 1, 0, stream, args,
                                       nullptr));
         if (o.progress > 0 && nlaunch > 1) {
@@ -367,28 +351,120 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
     HIP_TRY(hipEventRecord(g_dev.ev[1], stream));
     unsigned long long *count_out = reinterpret_cast<unsigned long long *>(g_dev.out + 2);
     HIP_TRY(launch_final_reduce(g_dev.partials, g_dev.counts, (long long)nblocks, g_dev.out, count_out, stream));
+    if (pl.exact) HIP_TRY(launch_final_reduce_x(g_dev.xparts, (long long)nblocks, g_dev.out + 3, stream));
     HIP_TRY(hipEventRecord(g_dev.ev[2], stream));
-    double *hl = g_dev.host_out;  // pinned: the 24-byte result copy is a plain DMA
-    HIP_TRY(hipMemcpyAsync(hl, g_dev.out, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
-    if (o.block_partials && o.block_partials_cap >= nblocks)
-        HIP_TRY(hipMemcpyAsync(o.block_partials, g_dev.partials, 2 * sizeof(double) * (size_t)nblocks,
+    double *hl = g_dev.host_out;  // pinned: the result copy is a plain DMA
+    HIP_TRY(hipMemcpyAsync(hl, g_dev.out, (pl.exact ? 5 : 3) * sizeof(double), hipMemcpyDeviceToHost, stream));
+    if (block_partials && block_partials_cap >= nblocks)
+        HIP_TRY(hipMemcpyAsync(block_partials, g_dev.partials, 2 * sizeof(double) * (size_t)nblocks,
                                hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, g_dev.ev[0], g_dev.ev[1]));
-    st.kernel_ms = ms;
+    po->kernel_ms = ms;
     HIP_TRY(hipEventElapsedTime(&ms, g_dev.ev[1], g_dev.ev[2]));
-    st.reduce_ms = ms;
-    st.sum_hi = hl[0];
-    st.sum_lo = hl[1];
-    {
-        unsigned long long ev = 0;
-        memcpy(&ev, &hl[2], sizeof ev);
-        st.evaluated_steps = (double)ev;
+    po->reduce_ms = ms;
+    po->hi = hl[0];
+    po->lo = hl[1];
+    unsigned long long ev = 0;
+    memcpy(&ev, &hl[2], sizeof ev);
+    po->evaluated = (double)ev;
+    if (pl.exact) {
+        po->resid = hl[3];
+        po->abs_sum = hl[4];
     }
-    // final factor of Alg. 1: 4 (n mod 2) - 2 = (-1)^(n-1) * 2 (exact scaling)
-    const double f = (pl.n % 2 == 1) ? 2.0 : -2.0;
-    *out = (hl[0] + hl[1]) * f;
+    return PERM_OK;
+}
+
+perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_stats *st_out) {
+    auto t0 = std::chrono::steady_clock::now();
+    perm_stats st;
+    memset(&st, 0, sizeof st);
+    const perm_opts o = defaults(opts);
+    std::shared_ptr<CachedPlan> cp;
+    bool plan_hit = false;
+    {
+        perm_status s = acquire_plan(m, o, &cp, &plan_hit);
+        if (s != PERM_OK) return s;
+    }
+    const Prepared &p = cp->p;
+    const CodeObject &co = cp->co;
+    fill_plan_stats(p, &st);
+    st.host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() -
+                 (plan_hit ? 0.0 : co.compile_ms);
+    if (p.singular) {
+        *out = 0.0;  // no perfect matching: every permutation product has a zero factor
+        st.exact = 1;
+        st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (st_out) *st_out = st;
+        return PERM_OK;
+    }
+    st.compile_ms = plan_hit ? 0.0 : co.compile_ms;
+    st.cache_hit = (plan_hit || co.cache_hit) ? 1 : 0;
+    st.vgprs = co.vgprs;
+    st.sgprs = co.sgprs;
+    st.scratch_bytes = co.scratch_bytes;
+    st.lds_bytes = co.lds_bytes;
+    st.waves_hint = p.plan.waves_per_simd;
+    st.vgpr_spills = co.vgpr_spills;
+    std::lock_guard<std::mutex> g(g_mu);
+    perm_status s = ensure_device();
+    if (s != PERM_OK) return s;
+    if (!cp->kern) {
+        s = load_kernel(p.src, co, p.plan.block, &cp->kern);
+        if (s != PERM_OK) return s;
+    }
+    st.waves_per_simd = cp->kern->waves_per_simd;
+
+    const Plan &pl = p.plan;
+    if (o.exact_passes < 0 || o.exact_passes > kExactMaxPasses)
+        return fail(PERM_EINVAL, "exact_passes must be 0..3");
+    hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : g_dev.stream;
+    // one pass per prime: the FP64 sum, A and E are the same in every pass
+    // (same code, same order); only the residue's prime changes
+    PassOut po;
+    ExactSums es;
+    double kernel_ms = 0.0, reduce_ms = 0.0;
+    ExactOutcome eo;
+    for (int pass = 0;; ++pass) {
+        const double prime = pl.exact ? kExactPrimes[pass] : 0.0;
+        s = run_pass(*cp, prime, o, stream, pass == 0 ? o.block_partials : nullptr,
+                     pass == 0 ? o.block_partials_cap : 0, &po);
+        if (s != PERM_OK) return s;
+        kernel_ms += po.kernel_ms;
+        reduce_ms += po.reduce_ms;
+        if (!pl.exact) break;
+        es.hi = po.hi;
+        es.lo = po.lo;
+        es.abs_sum = po.abs_sum;
+        es.chunk_log2 = pl.kappa;
+        es.resid[pass] = po.resid;
+        es.passes = pass + 1;
+        eo = exact_recover(pl.n, es);
+        if (es.passes >= kExactMaxPasses) break;
+        if (es.passes < o.exact_passes) continue;
+        if (eo.certified || !eo.more) break;
+    }
+    st.kernel_ms = kernel_ms;
+    st.reduce_ms = reduce_ms;
+    st.sum_hi = po.hi;
+    st.sum_lo = po.lo;
+    st.evaluated_steps = po.evaluated;
+    if (pl.exact) {
+        // the term sums are in y = 2x units: 2^n times Alg. 1's
+        st.sum_hi = std::ldexp(po.hi, -pl.n);
+        st.sum_lo = std::ldexp(po.lo, -pl.n);
+        st.exact = eo.certified ? 1 : 0;
+        st.exact_passes = es.passes;
+        st.estimate = eo.estimate;
+        st.err_bound = eo.err_bound;
+        *out = eo.value;
+    } else {
+        // final factor of Alg. 1: 4 (n mod 2) - 2 = (-1)^(n-1) * 2 (exact scaling)
+        const double f = (pl.n % 2 == 1) ? 2.0 : -2.0;
+        *out = (po.hi + po.lo) * f;
+        st.estimate = *out;
+    }
     st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (st_out) *st_out = st;
     return PERM_OK;
@@ -448,6 +524,12 @@ perm_status time_sample(CachedPlan &cp, const TuneSample &ts, hipStream_t stream
         s = ensure_buffer(&g_dev.xg, &g_dev.xg_cap, (size_t)(pl.n - pl.k) * xs);
         if (s != PERM_OK) return s;
     }
+    if (pl.exact) {
+        s = ensure_buffer(&g_dev.xparts, &g_dev.xparts_cap, 2 * (size_t)nblocks);
+        if (s != PERM_OK) return s;
+    }
+    // exact mode: timed with the first prime, as a first pass runs
+    double pmod = pl.exact ? kExactPrimes[0] : 0.0, pinv = pl.exact ? 1.0 / kExactPrimes[0] : 0.0;
     HIP_TRY(hipEventRecord(g_dev.ev[0], stream));
     int64_t off = 0;
     for (int sl = 0; sl < ts.slices; ++sl) {
@@ -462,7 +544,8 @@ perm_status time_sample(CachedPlan &cp, const TuneSample &ts, hipStream_t stream
             unsigned long long *cnt = g_dev.counts + off;
             double *xg = g_dev.xg;
             uint64_t xs_arg = xs;
-            void *args[] = {&chunk_begin, &chunk_end, &part, &cnt, &xg, &xs_arg};
+            double *xp = pl.exact ? g_dev.xparts + 2 * off : nullptr;
+            void *args[] = {&chunk_begin, &chunk_end, &part, &cnt, &xg, &xs_arg, &xp, &pmod, &pinv};
             HIP_TRY(hipModuleLaunchKernel(cp.kern->fn, (unsigned)nb, 1, 1, (unsigned)B, 1, 1, 0, stream, args,
                                           nullptr));
             off += nb;
@@ -799,6 +882,8 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
     BatchOptions bo;
     bo.zero_skip = o.zero_skip;
     bo.kappa_shift = o.batch_kappa_shift;
+    bo.exact = o.exact;
+    if (o.exact < -1 || o.exact > 1) return fail(PERM_EINVAL, "exact must be -1, 0 or 1");
     std::vector<PreparedMatrix> prep(count);
     std::string err;
     double steps = 0.0, ops = 0.0, fmas = 0.0;
@@ -834,15 +919,18 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
     if (s != PERM_OK) return s;
     hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : g_dev.stream;
     double kms = 0.0;
-    int launches = 0;
+    int launches = 0, passes = 0;
+    std::vector<int> xs((size_t)std::max(count, 1), -1);
     if (o.batch_mode == 2) {
         for (int32_t i = 0; i < count; ++i) {
             std::vector<const PreparedMatrix *> one{&prep[i]};
             double k1 = 0.0;
-            s = g_batch_job.run(one, &out[i], stream, BatchLaunch::Single, &k1, &err);
+            int np = 0;
+            s = g_batch_job.run(one, &out[i], stream, BatchLaunch::Single, &k1, &err, &xs[i], &np);
             if (s != PERM_OK) return fail(s, err);
             kms += k1;
-            launches += prep[i].singular ? 0 : 2;
+            launches += prep[i].singular ? 0 : 2 * np;
+            passes = std::max(passes, np);
         }
     } else {
         std::vector<const PreparedMatrix *> all;
@@ -850,7 +938,7 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
         const BatchLaunch how = o.batch_mode == 0   ? BatchLaunch::Streams
                                 : o.batch_mode == 1 ? BatchLaunch::Graph
                                                     : BatchLaunch::Single;
-        s = g_batch_job.run(all, out, stream, how, &kms, &err);
+        s = g_batch_job.run(all, out, stream, how, &kms, &err, xs.data(), &passes);
         if (s != PERM_OK) return fail(s, err);
         launches = -1;
     }
@@ -865,6 +953,15 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
         st->launches = launches;
         st->fp64_ops = ops;
         st->flops = ops + fmas;
+        st->passes = passes;
+        for (int32_t i = 0; i < count; ++i) {
+            if (xs[i] == 1 && !prep[i].singular) st->exact_certified++;
+            if (xs[i] == 0) st->exact_uncertified++;
+        }
+        double xo = 0.0;
+        for (int32_t i = 0; i < count; ++i)
+            if (!prep[i].singular) xo += prep[i].exact_ops;
+        st->exact_ops = xo;
     }
     return PERM_OK;
 }
@@ -947,12 +1044,13 @@ perm_status perm_compile_info(const perm_csc *a, const perm_opts *opts, perm_sta
     return PERM_OK;
 }
 
-perm_status perm_batch_describe(const perm_csc *a, const perm_opts *opts, int32_t desc[6], double *vals,
+perm_status perm_batch_describe(const perm_csc *a, const perm_opts *opts, int32_t desc[8], double *vals,
                                 size_t vals_cap, size_t *nvals, int32_t *tops, size_t tops_cap, size_t *ntops) {
     const perm_opts o = defaults(opts);
     BatchOptions bo;
     bo.zero_skip = o.zero_skip;
     bo.kappa_shift = o.batch_kappa_shift;
+    bo.exact = o.exact;
     PreparedMatrix pm;
     std::string err;
     perm_status s = prepare_batch_matrix(a, bo, &pm, &err);
@@ -964,11 +1062,38 @@ perm_status perm_batch_describe(const perm_csc *a, const perm_opts *opts, int32_
     desc[3] = pm.zero_skip ? 1 : 0;
     desc[4] = pm.chunk_top;
     desc[5] = pm.singular ? 1 : 0;
+    desc[6] = pm.exact ? 1 : 0;
+    desc[7] = 0;
     if (nvals) *nvals = pm.vals.size();
     if (ntops) *ntops = pm.tops.size();
     if (vals && vals_cap >= pm.vals.size()) memcpy(vals, pm.vals.data(), pm.vals.size() * sizeof(double));
     if (tops && tops_cap >= pm.tops.size()) memcpy(tops, pm.tops.data(), pm.tops.size() * sizeof(int32_t));
     return PERM_OK;
+}
+
+perm_status perm_exact_recover(int32_t n, double hi, double lo, double abs_sum, int32_t chunk_log2, int32_t passes,
+                               const double *resid, double out[3], int32_t *certified, int32_t *more) {
+    if (n < 1 || n > PERM_MAX_N || passes < 0 || passes > kExactMaxPasses || chunk_log2 < 0 || chunk_log2 > 40 ||
+        !out || !certified || !more || (passes > 0 && !resid))
+        return fail(PERM_EINVAL, "bad perm_exact_recover arguments");
+    ExactSums es;
+    es.hi = hi;
+    es.lo = lo;
+    es.abs_sum = abs_sum;
+    es.chunk_log2 = chunk_log2;
+    es.passes = passes;
+    for (int i = 0; i < passes; ++i) es.resid[i] = resid[i];
+    const ExactOutcome eo = exact_recover(n, es);
+    out[0] = eo.value;
+    out[1] = eo.estimate;
+    out[2] = eo.err_bound;
+    *certified = eo.certified ? 1 : 0;
+    *more = eo.more ? 1 : 0;
+    return PERM_OK;
+}
+
+void perm_exact_primes(double out[3]) {
+    for (int i = 0; i < kExactMaxPasses; ++i) out[i] = kExactPrimes[i];
 }
 
 const char *perm_last_error(void) { return t_err.c_str(); }

@@ -33,6 +33,7 @@
 
 #include "batch.h"
 #include "batch_host.h"
+#include "exact.h"
 #include "perm.h"
 #include "perm_internal.h"
 
@@ -110,12 +111,16 @@ struct Request {
     size_t vals_bytes = 0;
     uint64_t items_total = 0, next_item = 0;
     Clock::time_point t_submit, t_done;
+    // exact mode: sums of the passes so far; pass = index of the running prime
+    ExactSums es;
+    int pass = 0;
+    int exact_state = -1;  // 1 certified exact, 0 exact mode without a certificate, -1 not exact mode
 };
 
 size_t request_bytes(const PreparedMatrix &pm, uint64_t items, size_t *vals_bytes) {
     *vals_bytes = (pm.vals.size() * sizeof(double) + kAlign - 1) / kAlign * kAlign;
     const size_t tops = (pm.tops.size() * sizeof(int32_t) + kAlign - 1) / kAlign * kAlign;
-    const size_t parts = (items * 2 * sizeof(double) + kAlign - 1) / kAlign * kAlign;
+    const size_t parts = (items * kPartStride * sizeof(double) + kAlign - 1) / kAlign * kAlign;
     return *vals_bytes + tops + parts;
 }
 
@@ -198,7 +203,7 @@ struct perm_server {
     std::thread worker;
 
     // statistics
-    uint64_t n_submitted = 0, n_completed = 0, n_rounds = 0;
+    uint64_t n_submitted = 0, n_completed = 0, n_rounds = 0, n_extra_passes = 0;
     size_t peak_bytes = 0;
     double busy_ms = 0.0;
     Clock::time_point busy_since;
@@ -299,7 +304,8 @@ bool perm_server::issue(Slot &slot, const std::vector<Request *> &newly, std::st
         // launches ordered by kernel instance, larger instances first
         std::stable_sort(takes[c].begin(), takes[c].end(), [](const Take &x, const Take &y) {
             if (x.r->pm.ng != y.r->pm.ng) return x.r->pm.ng > y.r->pm.ng;
-            return x.r->pm.zero_skip && !y.r->pm.zero_skip;
+            if (x.r->pm.zero_skip != y.r->pm.zero_skip) return x.r->pm.zero_skip;
+            return x.r->pm.exact && !y.r->pm.exact;
         });
         std::vector<BatchMat> mats;
         std::vector<WavePlan> plans;
@@ -313,24 +319,28 @@ bool perm_server::issue(Slot &slot, const std::vector<Request *> &newly, std::st
             d.kappa = pm.kappa;
             d.zero_skip = pm.zero_skip ? 1 : 0;
             d.chunk_top = pm.chunk_top;
-            d.pad = 0;
+            d.exact = pm.exact ? 1 : 0;
             d.nchunks = pm.nchunks;
             d.col_off = r->arena_off / sizeof(double);
             d.base_off = d.col_off + pm.base_index;
             d.top_off = (r->arena_off + r->vals_bytes) / sizeof(int32_t);
+            d.pmod = pm.exact ? kExactPrimes[r->pass] : 0.0;
+            d.pinv = pm.exact ? 1.0 / d.pmod : 0.0;
             const int32_t mi = (int32_t)mats.size();
             mats.push_back(d);
             const size_t tops_bytes = (pm.tops.size() * sizeof(int32_t) + kAlign - 1) / kAlign * kAlign;
-            const uint64_t part0 = (r->arena_off + r->vals_bytes + tops_bytes) / (2 * sizeof(double));
-            if (plans.empty() || plans.back().ng != pm.ng || plans.back().zero_skip != pm.zero_skip) {
+            const uint64_t part0 = (r->arena_off + r->vals_bytes + tops_bytes) / (kPartStride * sizeof(double));
+            if (plans.empty() || plans.back().ng != pm.ng || plans.back().zero_skip != pm.zero_skip ||
+                plans.back().exact != pm.exact) {
                 plans.emplace_back();
                 plans.back().ng = pm.ng;
                 plans.back().zero_skip = pm.zero_skip;
+                plans.back().exact = pm.exact;
             }
             plans.back().add(mi, r->next_item, t.items, part0 + r->next_item);
             r->next_item += t.items;
             if (r->next_item == r->items_total) {
-                fin.push_back(FinishDesc{part0, r->items_total, pm.n, 0});
+                fin.push_back(FinishDesc{part0, r->items_total, pm.n, pm.exact ? 1 : 0, d.pmod, d.pinv});
                 cb.finishing.push_back(r);
             }
         }
@@ -345,13 +355,14 @@ bool perm_server::issue(Slot &slot, const std::vector<Request *> &newly, std::st
             !grow_dev(&cb.d_ranges, &cb.cap_ranges, std::max<size_t>(nranges, 1)) ||
             !grow_dev(&cb.d_blk, &cb.cap_blk, std::max<size_t>(nblk, 1)) ||
             !grow_dev(&cb.d_fin, &cb.cap_fin, std::max<size_t>(nf, 1)) ||
-            !grow_dev(&cb.d_out, &cb.cap_out, std::max<size_t>(nf, 1))) {
+            !grow_dev(&cb.d_out, &cb.cap_out, kPartStride * std::max<size_t>(nf, 1))) {
             *err = "device allocation for a round failed";
             return false;
         }
         const size_t bytes = nm * sizeof(BatchMat) + nranges * sizeof(BatchRange) + nblk * sizeof(int32_t) +
                              nf * sizeof(FinishDesc) + up_bytes + 256;
-        if (!grow_host(&cb.h_stage, &cb.cap_stage, bytes) || !grow_host(&cb.h_out, &cb.cap_hout, std::max<size_t>(nf, 1))) {
+        if (!grow_host(&cb.h_stage, &cb.cap_stage, bytes) ||
+            !grow_host(&cb.h_out, &cb.cap_hout, kPartStride * std::max<size_t>(nf, 1))) {
             *err = "pinned host allocation for a round failed";
             return false;
         }
@@ -396,14 +407,15 @@ bool perm_server::issue(Slot &slot, const std::vector<Request *> &newly, std::st
             }
             size_t r0 = 0, b0 = 0;
             for (const WavePlan &w : plans) {
-                SRV_HIP(launch_batch_ranges(w.ng, w.zero_skip, cb.d_ranges + r0, (int)w.ranges.size(),
+                SRV_HIP(launch_batch_ranges(w.ng, w.zero_skip, w.exact, cb.d_ranges + r0, (int)w.ranges.size(),
                                             cb.d_blk + b0, (int64_t)w.nwaves, cb.d_mats, vals, tops, parts, st));
                 r0 += w.ranges.size();
                 b0 += w.blk_first.size();
             }
             if (nf) {
                 SRV_HIP(launch_batch_finish(cb.d_fin, (int)nf, parts, cb.d_out, st));
-                SRV_HIP(hipMemcpyAsync(cb.h_out, cb.d_out, nf * sizeof(double), hipMemcpyDeviceToHost, st));
+                SRV_HIP(hipMemcpyAsync(cb.h_out, cb.d_out, kPartStride * nf * sizeof(double), hipMemcpyDeviceToHost,
+                                       st));
             }
         }
         SRV_HIP(hipEventRecord(cb.done, st));
@@ -428,7 +440,29 @@ bool perm_server::complete(Slot &slot, std::string *err) {
         if (!cb.used) continue;
         for (size_t i = 0; i < cb.finishing.size(); ++i) {
             Request *r = cb.finishing[i];
-            r->result = cb.h_out[i];
+            const double *o = cb.h_out + kPartStride * i;
+            if (r->pm.exact) {
+                // exact mode: recover the integer; without a certificate the
+                // request runs again with the next prime (same arena data)
+                ExactSums &es = r->es;
+                es.hi = o[0];
+                es.lo = o[1];
+                es.abs_sum = o[3];
+                es.chunk_log2 = r->pm.kappa;
+                es.resid[r->pass] = o[2];
+                es.passes = r->pass + 1;
+                const ExactOutcome eo = exact_recover(r->pm.n, es);
+                r->result = eo.value;
+                r->exact_state = eo.certified ? 1 : 0;
+                if (!eo.certified && eo.more) {
+                    ++r->pass;
+                    r->next_item = 0;
+                    ++n_extra_passes;
+                    continue;
+                }
+            } else {
+                r->result = (o[0] + o[1]) * ((r->pm.n % 2 == 1) ? 2.0 : -2.0);  // 4 (n mod 2) - 2
+            }
             r->state = State::Done;
             r->t_done = now;
             alloc.release(r->arena_off, r->bytes);
@@ -512,6 +546,11 @@ perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget,
     if (opts) s->opts = *opts;
     s->bo.zero_skip = s->opts.zero_skip;
     s->bo.kappa_shift = s->opts.batch_kappa_shift + kServerChunkShift;
+    s->bo.exact = s->opts.exact;
+    if (s->opts.exact < -1 || s->opts.exact > 1) {
+        set_last_error("exact must be -1, 0 or 1");
+        return nullptr;
+    }
     s->budget = device_mem_budget ? device_mem_budget : ((size_t)1 << 30);
     s->max_inflight = max_inflight > 0 ? max_inflight : 4096;
     if (!(round_steps >= 0.0)) {
@@ -606,13 +645,20 @@ perm_status perm_poll(perm_server *s, uint64_t ticket, double *out) {
 perm_status perm_wait(perm_server *s, uint64_t ticket, double *out) {
     if (!s || !out) return sfail(PERM_EINVAL, "null server or output");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->tickets.find(ticket);
-    if (it == s->tickets.end()) return sfail(PERM_EINVAL, "unknown ticket");
-    Request *r = it->second.get();
-    s->cv_done.wait(lk, [&] { return r->state == State::Done; });
+    if (s->tickets.find(ticket) == s->tickets.end()) return sfail(PERM_EINVAL, "unknown ticket");
+    // The ticket is looked up again on every wake-up: while the lock is
+    // released, a submit may rehash the map and another caller may collect
+    // the request (then this wait reports an unknown ticket).
+    Request *r = nullptr;
+    s->cv_done.wait(lk, [&] {
+        auto it = s->tickets.find(ticket);
+        r = it == s->tickets.end() ? nullptr : it->second.get();
+        return r == nullptr || r->state == State::Done;
+    });
+    if (!r) return sfail(PERM_EINVAL, "ticket collected by another caller");
     const perm_status st = r->status;
     *out = r->result;
-    s->tickets.erase(it);
+    s->tickets.erase(ticket);
     if (st != PERM_OK) return sfail(st, s->fatal.empty() ? "request failed" : s->fatal);
     return PERM_OK;
 }

@@ -53,17 +53,19 @@ class PermOpts(ctypes.Structure):
                 ("cold_tier", ctypes.c_int32), ("gr_ratio", ctypes.c_double),
                 ("hip_stream", ctypes.c_void_p), ("block_partials", ctypes.POINTER(ctypes.c_double)),
                 ("block_partials_cap", ctypes.c_int64), ("progress", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("block_queue", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("block_queue", ctypes.c_int32), ("exact", ctypes.c_int32), ("exact_passes", ctypes.c_int32),
+                ("pad2", ctypes.c_int32)]
 
 
 class PermBatchStats(ctypes.Structure):
     _fields_ = [("wall_ms", ctypes.c_double), ("prep_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("steps", ctypes.c_double), ("count", ctypes.c_int32), ("singular", ctypes.c_int32),
                 ("launches", ctypes.c_int32), ("pad", ctypes.c_int32), ("fp64_ops", ctypes.c_double),
-                ("flops", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("exact_ops", ctypes.c_double), ("exact_certified", ctypes.c_int32),
+                ("exact_uncertified", ctypes.c_int32), ("passes", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+        return {name: getattr(self, name) for name, _ in self._fields_ if name not in ("pad", "pad2")}
 
 
 class PermStats(ctypes.Structure):
@@ -77,7 +79,9 @@ class PermStats(ctypes.Structure):
                 ("chunk_log2", ctypes.c_int32), ("unroll_log2", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("vgprs", ctypes.c_int32), ("sgprs", ctypes.c_int32), ("scratch_bytes", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("cache_hit", ctypes.c_int32),
-                ("singular", ctypes.c_int32), ("waves_hint", ctypes.c_int32), ("vgpr_spills", ctypes.c_int32)]
+                ("singular", ctypes.c_int32), ("waves_hint", ctypes.c_int32), ("vgpr_spills", ctypes.c_int32),
+                ("exact", ctypes.c_int32), ("exact_passes", ctypes.c_int32), ("estimate", ctypes.c_double),
+                ("err_bound", ctypes.c_double), ("exact_ops_per_step", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -151,7 +155,31 @@ _lib.perm_server_destroy.argtypes = [ctypes.c_void_p]
 EXPORTED = ["perm_sparse", "perm_sparse_ex", "perm_batch", "perm_batch_ex", "perm_server_create", "perm_submit",
             "perm_poll", "perm_wait", "perm_server_get_stats", "perm_server_destroy", "perm_batch_describe",
             "perm_plan", "perm_partition", "perm_codegen",
-            "perm_compile_info", "perm_autotune", "perm_batch_autotune", "perm_last_error", "perm_version"]
+            "perm_compile_info", "perm_autotune", "perm_batch_autotune", "perm_exact_recover", "perm_exact_primes",
+            "perm_last_error", "perm_version"]
+
+
+_lib.perm_exact_recover.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_double),
+                                    _P(ctypes.c_int32), _P(ctypes.c_int32)]
+_lib.perm_exact_primes.restype = None
+_lib.perm_exact_primes.argtypes = [_P(ctypes.c_double)]
+
+
+def exact_primes():
+    out = (ctypes.c_double * 3)()
+    _lib.perm_exact_primes(out)
+    return [int(v) for v in out]
+
+
+def exact_recover(n, hi, lo, abs_sum, chunk_log2, resid):
+    """perm_exact_recover: returns (value, estimate, err_bound, certified, more)."""
+    r = (ctypes.c_double * 3)(*[float(v) for v in resid])
+    out = (ctypes.c_double * 3)()
+    cert, more = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.perm_exact_recover(int(n), float(hi), float(lo), float(abs_sum), int(chunk_log2), len(resid), r,
+                                   out, ctypes.byref(cert), ctypes.byref(more)))
+    return out[0], out[1], out[2], bool(cert.value), bool(more.value)
 
 
 def library():
@@ -191,7 +219,7 @@ def _stream_handle(stream):
 def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, force_k=0, force_c=0,
               max_levels=0, gr_ratio=0.0, stream=None, zero_skip="auto", batch_mode="streams",
               batch_kappa_shift=0, cold_tier="global", progress=False, waves_per_simd=0,
-              block_queue=True):
+              block_queue=True, exact="auto", exact_passes=0):
     o = PermOpts()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.chunk_log2, o.unroll_log2, o.block = chunk_log2, unroll_log2, block
@@ -204,6 +232,8 @@ def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, 
     o.progress = 1 if progress else 0
     o.waves_per_simd = waves_per_simd
     o.block_queue = (0 if block_queue is True else -1 if block_queue is False else int(block_queue))
+    o.exact = {"auto": 0, True: 1, False: -1}[exact]
+    o.exact_passes = exact_passes
     o.hip_stream = _stream_handle(stream)
     return o
 
@@ -264,7 +294,8 @@ def _opts_kwargs(o):
             "batch_mode": {0: "streams", 1: "graph", 2: "sequential", 3: "one_stream"}[o.batch_mode],
             "batch_kappa_shift": o.batch_kappa_shift, "cold_tier": {0: "global", 1: "lds"}[o.cold_tier],
             "waves_per_simd": o.waves_per_simd,
-            "block_queue": {0: True, -1: False}.get(o.block_queue, o.block_queue)}
+            "block_queue": {0: True, -1: False}.get(o.block_queue, o.block_queue),
+            "exact": {0: "auto", 1: True, -1: False}[o.exact], "exact_passes": o.exact_passes}
 
 
 def perm_autotune(ccs, **opts):
@@ -337,7 +368,7 @@ def batch_describe(ccs, **opts):
     """The batch kernels' data for one matrix (see perm_batch_describe)."""
     m = _Csc(ccs)
     o = make_opts(**opts)
-    desc = (ctypes.c_int32 * 6)()
+    desc = (ctypes.c_int32 * 8)()
     nv, nt = ctypes.c_size_t(), ctypes.c_size_t()
     _check(_lib.perm_batch_describe(ctypes.byref(m.c), ctypes.byref(o), desc, None, 0, ctypes.byref(nv), None, 0,
                                     ctypes.byref(nt)))
@@ -346,7 +377,7 @@ def batch_describe(ccs, **opts):
     _check(_lib.perm_batch_describe(ctypes.byref(m.c), ctypes.byref(o), desc,
                                     vals.ctypes.data_as(_P(ctypes.c_double)), vals.size, ctypes.byref(nv),
                                     tops.ctypes.data_as(_P(ctypes.c_int32)), tops.size, ctypes.byref(nt)))
-    keys = ["n", "ng", "kappa", "zero_skip", "chunk_top", "singular"]
+    keys = ["n", "ng", "kappa", "zero_skip", "chunk_top", "singular", "exact"]
     return dict(zip(keys, list(desc))), vals[:nv.value], tops[:nt.value]
 
 

@@ -24,5 +24,7 @@ static inline unsigned __builtin_amdgcn_mbcnt_hi(unsigned, unsigned acc) { retur
 // one emulated lane is the whole "wave"
 static inline int __all(int p) { return p; }
 using std::fma;
+using std::rint;
+using std::fabs;
 // a one-lane wave: the first lane's value is the value
 static inline int __builtin_amdgcn_readfirstlane(int v) { return v; }  // int, as the device builtin

@@ -211,7 +211,9 @@ def test_codegen_resources(P):
             else:
                 assert auto["waves_hint"] == want, (ccs[0], mode, plain["vgprs"])
                 assert auto["vgprs"] <= 512 // want and auto["scratch_bytes"] <= 128
-        assert P.compile_info(ccs, waves_per_simd=-1)["vgprs"] <= 128
+        # x in VGPRs at 4 waves (exact mode, with its residue per level: 3)
+        own = P.compile_info(ccs, waves_per_simd=-1)
+        assert own["vgprs"] <= (168 if own["exact"] >= 0 else 128)
         # the LDS tier: cold rows in LDS ([row][lane]), at most 40 KiB per workgroup
         lds = P.compile_info(ccs, mode="hybrid", cold_tier="lds")
         plan = P.perm_plan(ccs, mode="hybrid")
@@ -220,40 +222,64 @@ def test_codegen_resources(P):
         assert lds["lds_bytes"] <= 40960 + 1024
 
 
-def _emulate(P, ccs, chunks=None, **opts):
+def _emulate(P, ccs, chunks=None, prime=None, **opts):
     """Run the generated perm_lane() of every chunk (or of the chunks listed)
-    on the CPU (g++); the listed chunks' sums are returned in info["sums"]."""
+    on the CPU (g++); the listed chunks' sums are returned in info["sums"].
+    Exact mode (integer values): the kernel works on y = 2x; the value is
+    scaled back, and info holds the term sum (hi, lo), the residue sum modulo
+    `prime` (default: the first of the library's) and the sum of |term|."""
     src = P.perm_codegen(ccs, **opts)
     info = P.compile_info(ccs, **opts)
+    exact = info["exact"] >= 0
+    pm = float(prime if prime is not None else P.exact_primes()[0]) if exact else 0.0
     d = tempfile.mkdtemp(prefix="permemu")
     f = os.path.join(d, "g.cpp")
     with open(f, "w") as fh:
         # one lane: its own queued blocks (if any) are evaluated after its walk
-        fh.write(src + '\nextern "C" void cpu_lane(u64 m, double* xg, u64 xs, u64 lid, double* o) {'
-                 ' static double q[kBlockQueueWords]; u32 ev = 0, qc = 0;'
-                 ' dd r = perm_lane(m, xg, xs, lid, true, q, qc, ev);'
-                 ' for (u32 s = 0; s < qc; ++s) r = dd_add(r, block_eval(q + s, ev));'
-                 ' o[0] = r.h; o[1] = r.l; o[2] = ev; o[3] = qc; }\n')
+        fh.write(src + '\nextern "C" void cpu_lane(u64 m, double* xg, u64 xs, u64 lid, double* o, double pm) {'
+                 ' static double q[kBlockQueueWords]; u32 ev = 0, qc = 0; double xo[2] = {0.0, 0.0};'
+                 ' const double pi = pm > 0.0 ? 1.0 / pm : 0.0;'
+                 ' dd r = perm_lane(m, xg, xs, lid, true, q, qc, ev, xo, pm, pi);'
+                 ' for (u32 s = 0; s < qc; ++s) r = dd_add(r, block_eval(q + s, ev, xo, pm, pi));'
+                 ' o[0] = r.h; o[1] = r.l; o[2] = ev; o[3] = qc; o[4] = xo[0]; o[5] = xo[1]; }\n')
     so = os.path.join(d, "g.so")
     subprocess.run(["g++", "-O1", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-include", SHIM,
                     "-o", so, f], check=True)
     lib = ctypes.CDLL(so)
-    lib.cpu_lane.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
+    lib.cpu_lane.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
+                             ctypes.c_double]
     n = ccs[0]
     xg = np.zeros(max(1, n), np.float64)
-    o = np.zeros(4)
+    o = np.zeros(6)
     tot = 0.0
+    hi, lo = 0.0, 0.0
     info["evaluated"] = 0
     info["queued"] = 0
     info["sums"] = []
+    info["resid"] = 0
+    info["abs_sum"] = 0.0
     for m in range(info["nchunks"]) if chunks is None else chunks:
-        lib.cpu_lane(m, xg.ctypes.data, 1, 0, o.ctypes.data)
+        lib.cpu_lane(m, xg.ctypes.data, 1, 0, o.ctypes.data, pm)
         tot += o[0] + o[1]
+        hi, lo = _dd_add(hi, lo, o[0], o[1])
         if chunks is not None:
-            info["sums"].append(o[0] + o[1])
+            info["sums"].append((o[0] + o[1]) * (2.0 ** -n if exact else 1.0))
         info["evaluated"] += int(o[2])
         info["queued"] += int(o[3])
-    return tot * (2.0 if n % 2 else -2.0), info
+        info["resid"] += int(o[4])
+        info["abs_sum"] += o[5]
+    info["hi"], info["lo"] = hi, lo
+    scale = 2.0 ** -n if exact else 1.0
+    return tot * scale * (2.0 if n % 2 else -2.0), info
+
+
+def _dd_add(h1, l1, h2, l2):
+    """Double-double sum (Knuth's two-sum of the high parts, then the low parts)."""
+    s = h1 + h2
+    bb = s - h1
+    e = (h1 - (s - bb)) + (h2 - bb) + (l1 + l2)
+    h = s + e
+    return h, e - (h - s)
 
 
 def test_generated_code_on_cpu_matches_oracle(P, oracle_mod):
@@ -382,22 +408,32 @@ def _batch_lane_lib():
                     "-I", csrc, "-o", so, os.path.join(os.path.dirname(SHIM), "batch_lane_cpu.cpp")], check=True)
     lib = ctypes.CDLL(so)
     lib.cpu_batch_lane.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
-                                   ctypes.c_uint64, ctypes.c_void_p]
+                                   ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p]
     return lib
 
 
-def _batch_emulate(P, lib, ccs, **opts):
+def _batch_emulate(P, lib, ccs, prime=None, with_info=False, **opts):
     info, vals, tops = P.batch_describe(ccs, **opts)
     if info["singular"]:
-        return 0.0
-    desc = np.array([info[k] for k in ("n", "ng", "kappa", "zero_skip", "chunk_top", "singular")], np.int32)
-    o = np.zeros(2)
+        return (0.0, info) if with_info else 0.0
+    desc = np.array([info[k] for k in ("n", "ng", "kappa", "zero_skip", "chunk_top", "singular", "exact")] + [0],
+                    np.int32)
+    pm = float(prime if prime is not None else P.exact_primes()[0]) if info["exact"] else 0.0
+    o = np.zeros(4)
     tot = 0.0
+    hi, lo = 0.0, 0.0
+    info["resid"], info["abs_sum"] = 0, 0.0
     for m in range(1 << (info["n"] - 1 - info["kappa"])):
-        assert lib.cpu_batch_lane(desc.ctypes.data, vals.ctypes.data, vals.size, tops.ctypes.data, m,
+        assert lib.cpu_batch_lane(desc.ctypes.data, vals.ctypes.data, vals.size, tops.ctypes.data, m, pm,
                                   o.ctypes.data) == 0
         tot += o[0] + o[1]
-    return tot * (2.0 if info["n"] % 2 else -2.0)
+        hi, lo = _dd_add(hi, lo, o[0], o[1])
+        info["resid"] += int(o[2])
+        info["abs_sum"] += o[3]
+    info["hi"], info["lo"] = hi, lo
+    n = info["n"]
+    v = tot * (2.0 ** -n if info["exact"] else 1.0) * (2.0 if n % 2 else -2.0)
+    return (v, info) if with_info else v
 
 
 def test_batch_lane_code_on_cpu_matches_oracle(P, oracle_mod):
