@@ -1,10 +1,13 @@
 """Benchmark: Gray-code steps/s of the sparse permanent on one MI355X.
 
 One benchmark step = one full permanent of the n=40, density-0.10 0/1 matrix
-(random permutation pattern OR Bernoulli(0.10), seed 1): all 2^39 Gray-code
-steps, through the C ABI (validation, structural check, ordering, partition,
-code generation with a cached code object, launch, fixed-order reduction,
-result on the host).  Prints one JSON line.
+(random permutation pattern OR Bernoulli(0.10), seed 1) with every one of its
+2^39 Gray-code terms evaluated (Alg. 1 as the paper's generated kernels run
+it), through the C ABI (validation, structural check, ordering, partition,
+code generation with a cached code object, launches, fixed-order reduction,
+the exact integer count on the host).  Beside it: the same permanent with
+exact zero-aware pruning (permanents/s), the 2000-matrix batch, the serving
+run, and the CPU oracle.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--mode auto]
                     [--workload n40_p0.10_01] [--seed 1] [--no-cpu-baseline]
@@ -29,59 +32,107 @@ METRIC = "Gray-code steps/s & % FP64 peak (n=40); batched permanents/s; p50/p99 
 FP64_PEAK_TFLOPS = 78.6  # MI355X published FP64 vector peak (an FMA counts 2)
 
 
-def cpu_baseline(ccs, seconds_target=25.0):
-    """The oracle (Alg. 1 in long double, all host cores) on a bounded prefix of
-    the same Gray-index range; returns steps/s."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(ccs, seconds_target=20.0, one_core_seconds=6.0, int_seconds=8.0):
+    """The oracle on bounded samples of the same matrix's Gray-index range:
+    Alg. 1 in long double with every term evaluated (like the headline), on
+    all host threads and on one; and the exact integer form with zero
+    skipping (products with a zero factor skipped, as the pruned GPU path
+    does), on all host threads.  Rates in Gray-code steps/s."""
     from oracle import oracle as O
     O.build(force=False)
     threads = O.default_threads()
     n = ccs[0]
     total = 1 << (n - 1)
-    # calibrate on a small prefix, then run about seconds_target of work
-    probe = min(total, 1 << 22)
-    t0 = time.perf_counter()
-    O.nw_range(ccs, 0, probe, threads)
-    dt = max(time.perf_counter() - t0, 1e-3)
-    steps = int(min(total, max(probe, probe * seconds_target / dt)))
-    t0 = time.perf_counter()
-    O.nw_range(ccs, 0, steps, threads)
-    dt = time.perf_counter() - t0
-    return {"value": steps / dt, "unit": "Gray-code steps/s", "cores": threads, "kind": "oracle",
-            "sample": "Gray indices [0, %d) = 2^%.2f of the same matrix (of 2^%d), long double Alg. 1, %.1f s"
-                      % (steps, math.log2(steps), n - 1, dt)}
+
+    def timed(fn, target, nthreads):
+        probe = min(total, 1 << 20)
+        t0 = time.perf_counter()
+        fn(0, probe, nthreads)
+        dt = max(time.perf_counter() - t0, 1e-3)
+        steps = int(min(total, max(probe, probe * target / dt)))
+        t0 = time.perf_counter()
+        fn(0, steps, nthreads)
+        return steps, time.perf_counter() - t0
+
+    s_all, t_all = timed(lambda b, e, t: O.nw_range(ccs, b, e, t), seconds_target, threads)
+    s_one, t_one = timed(lambda b, e, t: O.nw_range(ccs, b, e, t), one_core_seconds, 1)
+    out = {"value": s_all / t_all, "unit": "Gray-code steps/s", "cores": threads, "kind": "oracle",
+           "sample": "Gray indices [0, %d) = 2^%.2f of the same matrix (of 2^%d), long double Alg. 1, every term "
+                     "evaluated, %.1f s" % (s_all, math.log2(s_all), n - 1, t_all),
+           "one_core": {"value": s_one / t_one, "sample": "Gray indices [0, %d), %.1f s" % (s_one, t_one)},
+           "cpu_model": _cpu_model(), "host_threads": os.cpu_count()}
+    if (ccs[3] == 1.0).all():
+        s_int, t_int = timed(lambda b, e, t: O.nw_int_range(ccs, b, e, t), int_seconds, threads)
+        out["zero_skipping_int"] = {
+            "value": s_int / t_int, "unit": "Gray-code steps/s (terms with a zero factor skipped)",
+            "cores": threads, "kind": "oracle",
+            "sample": "Gray indices [0, %d) = 2^%.2f, exact integer Alg. 1, %.1f s" % (s_int, math.log2(s_int), t_int)}
+    return out
 
 
-def batch_bench(seed=1, count=2000, reps=3, sequential=True):
+def batch_bench(seed=1, count=2000, reps=3, sequential=True, opts=None):
     """The batch workload (2000 matrices, n ~ U{16..30}, density ~ U[0.15, 0.40],
-    U(-1,1) values): one call of perm_batch (one launch per kernel instance on
-    its class stream, host preparation included) against one matrix per
-    launch, synchronised after each, with the same kernels."""
+    U(-1,1) values), host preparation included, in the launch forms of
+    perm_batch: one wave per work item on the class streams, and the
+    persistent instances captured in one graph (captured on the warm-up call,
+    relaunched after), against one matrix per launch, synchronised after
+    each, with the same kernels.  `opts` (perm_batch keywords, e.g. from
+    perm_batch_autotune) apply to both batched forms."""
     import paper_2501_15126_amd.perm as P
     from paper_2501_15126_amd import workloads as W
     mats = W.batch(seed, count)
-    P.perm_batch(mats)  # warm-up: device buffers, graph
-    best = None
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        out, st = P.perm_batch_ex(mats)
-        dt = time.perf_counter() - t0
-        best = (dt, st, out) if best is None or dt < best[0] else best
-    dt, st, out = best
+    opts = dict(opts or {})
+    opts.pop("batch_mode", None)
+
+    def best_of(mode):
+        P.perm_batch(mats, batch_mode=mode, **opts)  # warm-up: device buffers, graph capture
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out, st = P.perm_batch_ex(mats, batch_mode=mode, **opts)
+            dt = time.perf_counter() - t0
+            best = (dt, st, out) if best is None or dt < best[0] else best
+        return best
+
+    forms = {}
+    for mode in ("streams", "graph"):
+        dt, st, out = best_of(mode)
+        forms[mode] = (dt, st, out)
+    dt, st, out = min(forms.values(), key=lambda t: t[0])
+    best_mode = min(forms, key=lambda m: forms[m][0])
+
+    def roof(st):
+        ks = st["kernel_ms"] / 1e3
+        return {"bound": "alu", "achieved": st["flops"] / ks / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": st["flops"] / ks / 1e12 / FP64_PEAK_TFLOPS, "fp64_ops": st["fp64_ops"],
+                "fp64_issue_frac": st["fp64_ops"] / ks / 3.93216e13}
+
     res = {"workload": "%d sparse real matrices, n ~ U{16..30}, density ~ U[0.15,0.40], U(-1,1), seed %d"
-                        % (count, seed),
-            "permanents_per_s": count / dt, "wall_ms": dt * 1e3, "kernel_ms": st["kernel_ms"],
-            "prep_ms": st["prep_ms"], "gray_steps": st["steps"], "gray_steps_per_s": st["steps"] / dt,
-            "structurally_singular": st["singular"],
-            # the batch kernels' own FP64 work (counted exactly per chunk from
-            # their code) over the device time of the launches
-            "roofline": {"bound": "alu", "achieved": st["flops"] / (st["kernel_ms"] / 1e3) / 1e12,
-                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": st["flops"] / (st["kernel_ms"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
-                         "fp64_ops": st["fp64_ops"],
-                         "fp64_issue_frac": st["fp64_ops"] / (st["kernel_ms"] / 1e3) / 3.93216e13}}
+                       % (count, seed),
+           "permanents_per_s": count / dt, "wall_ms": dt * 1e3, "kernel_ms": st["kernel_ms"], "form": best_mode,
+           "options": opts,
+           "prep_ms": st["prep_ms"], "gray_steps": st["steps"], "gray_steps_per_s": st["steps"] / dt,
+           "structurally_singular": st["singular"],
+           # the batch kernels' own FP64 work (counted exactly per chunk from
+           # their code) over the device time of the launches
+           "roofline": roof(st),
+           "forms": {m: {"permanents_per_s": count / f[0], "wall_ms": f[0] * 1e3, "kernel_ms": f[1]["kernel_ms"],
+                         "graph_captures": f[1]["graph_captures"]} for m, f in forms.items()},
+           "forms_bitwise_equal": bool(np.array_equal(forms["streams"][2], forms["graph"][2]))}
     if sequential:
         t0 = time.perf_counter()
-        out_seq, st_seq = P.perm_batch_ex(mats, batch_mode="sequential")
+        out_seq, st_seq = P.perm_batch_ex(mats, batch_mode="sequential", **opts)
         dt_seq = time.perf_counter() - t0
         res.update({"sequential_permanents_per_s": count / dt_seq, "sequential_wall_ms": dt_seq * 1e3,
                     "speedup_vs_sequential": dt_seq / dt,
@@ -89,7 +140,7 @@ def batch_bench(seed=1, count=2000, reps=3, sequential=True):
     return res
 
 
-def serving_bench(duration_s=20.0, rate_hz=200.0, seed=1, compare_fifo=True, round_steps=0.0):
+def serving_bench(duration_s=60.0, rate_hz=200.0, seed=1, compare_fifo=True, round_steps=0.0):
     """Poisson arrivals at rate_hz of requests with n ~ U{12..36}, density ~
     U[0.10,0.35], 70 % 0/1 else U(0,1).  Latency = time the result is seen by
     the client minus the scheduled arrival time (queueing included)."""
@@ -155,7 +206,9 @@ def serving_bench(duration_s=20.0, rate_hz=200.0, seed=1, compare_fifo=True, rou
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
            "permanents_per_s": len(reqs) / span, "rounds": st["rounds"], "arena_peak_bytes": st["arena_peak"],
-           "server_busy_fraction": st["busy_ms"] / 1e3 / span}
+           "server_busy_fraction": st["busy_ms"] / 1e3 / span,
+           "exact_certified": st["exact_certified"], "exact_uncertified": st["exact_uncertified"],
+           "exact_extra_passes": st["extra_passes"]}
     if compare_fifo:
         flat, fspan = run_fifo()
         out["fifo_sequential"] = {"p50_ms": float(np.percentile(flat, 50)), "p99_ms": float(np.percentile(flat, 99)),
@@ -247,9 +300,9 @@ def main():
     ap.add_argument("--opts", default="",
                     help="time these options (JSON of perm_sparse_ex keywords) instead of searching, e.g. for "
                          "profiling the kernel an earlier run chose")
-    ap.add_argument("--no-unpruned", action="store_true",
-                    help="skip the context run of the same permanent with zero-aware skipping off")
-    ap.add_argument("--serving-seconds", type=float, default=20.0,
+    ap.add_argument("--no-pruned", action="store_true",
+                    help="skip the run of the same permanent with exact zero-aware pruning")
+    ap.add_argument("--serving-seconds", type=float, default=60.0,
                     help="length of the Poisson serving run (0 skips it)")
     ap.add_argument("--serving-rate", type=float, default=200.0,
                     help="Poisson arrival rate of the serving run (requests/s)")
@@ -296,50 +349,74 @@ def main():
     if args.serving_only:
         print(json.dumps({"serving": serving_bench(args.serving_seconds, rate_hz=args.serving_rate)}), flush=True)
         return
-    zs = {"auto": "auto", "on": True, "off": False}[args.zero_skip]
     ccs = W.WORKLOADS[args.workload](args.seed)
     n = ccs[0]
+    steps_per_perm = 2.0 ** (n - 1)
     print("bench: workload %s seed %d n=%d nnz=%d mode %s" % (args.workload, args.seed, n, len(ccs[2]), args.mode),
           file=sys.stderr, flush=True)
-    # launch options: the autotuner's pick for this matrix (searched once,
-    # before and outside the timed region), given ones, or the defaults
-    opts = {"mode": args.mode, "zero_skip": zs}
-    tune = None
-    if args.opts:
-        opts.update(json.loads(args.opts))
-    elif not args.no_tune:
-        t = time.perf_counter()
-        opts, tune = P.perm_autotune(ccs, **opts)
-        tune["wall_s"] = time.perf_counter() - t
-        print("bench: autotuned in %.1f s" % tune["wall_s"], file=sys.stderr, flush=True)
+
+    def tuned(**base):
+        """Launch options: the autotuner's pick (searched before and outside
+        the timed region), given ones, or the defaults."""
+        opts = dict(base)
+        tune = None
+        if args.opts:
+            opts.update(json.loads(args.opts))
+        elif not args.no_tune:
+            t = time.perf_counter()
+            opts, tune = P.perm_autotune(ccs, **opts)
+            tune["wall_s"] = time.perf_counter() - t
+            print("bench: autotuned %s in %.1f s" % (base, tune["wall_s"]), file=sys.stderr, flush=True)
+        return opts, tune
+
+    def timed_calls(opts, steps, warmup):
+        first = None
+        for _ in range(warmup):
+            v, st = P.perm_sparse_ex(ccs, **opts)
+            first = st if first is None else first
+        kernel_ms, evaluated, values, stats = [], [], [], None
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            v, st = P.perm_sparse_ex(ccs, **opts)  # synchronous: result on the host
+            kernel_ms.append(st["kernel_ms"])
+            evaluated.append(st["evaluated_steps"])
+            values.append(v)
+            stats = st
+        elapsed = time.perf_counter() - t0
+        return elapsed, kernel_ms, evaluated, values, stats, first
+
+    def kernel_record(st, kernel_ms, evaluated, first):
+        avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+        eval_steps = sum(evaluated) / len(evaluated)
+        return {"name": "perm_gray", "avg_ms": avg_kernel_s * 1e3, "evaluated_steps_per_launch_set": eval_steps,
+                "evaluated_steps_per_s": eval_steps / avg_kernel_s, "flops_per_step": st["flops_per_step"],
+                "fp64_ops_per_step": st["ops_per_step"], "exact_ops_per_step": st["exact_ops_per_step"],
+                "fp64_issue_frac": st["ops_per_step"] * eval_steps / avg_kernel_s / 3.93216e13,
+                "vgprs": st["vgprs"], "sgprs": st["sgprs"], "scratch_bytes": st["scratch_bytes"],
+                "waves_per_simd": st["waves_per_simd"], "waves_hint": st["waves_hint"],
+                "vgpr_spills": st["vgpr_spills"], "chunk_log2": st["chunk_log2"], "unroll_log2": st["unroll_log2"],
+                "levels": st["levels"], "k": st["k"], "c": st["c"], "nblocks": st["nblocks"],
+                "reduce_ms": st["reduce_ms"], "host_ms": st["host_ms"],
+                "compile_ms_cold": first["compile_ms"] if first else None,
+                "exact": st["exact"], "exact_passes": st["exact_passes"], "err_bound": st["err_bound"],
+                "estimate": st["estimate"], "skipped_fraction": 1.0 - eval_steps / steps_per_perm}
+
+    # ---- headline: every Gray-code term evaluated (no pruning) ----
+    opts, tune = tuned(mode=args.mode, zero_skip=False)
     chosen = {k: opts.get(k) for k in ("mode", "chunk_log2", "unroll_log2", "block", "waves_per_simd",
                                           "block_queue", "cold_tier") if k in opts}
-    first = None
-    for _ in range(args.warmup):
-        v, st = P.perm_sparse_ex(ccs, **opts)
-        first = st if first is None else first
-    kernel_ms = []
-    evaluated = []
-    values = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        v, st = P.perm_sparse_ex(ccs, **opts)  # synchronous: result on the host
-        kernel_ms.append(st["kernel_ms"])
-        evaluated.append(st["evaluated_steps"])
-        values.append(v)
-    elapsed = time.perf_counter() - t0
-    steps_per_perm = 2.0 ** (n - 1)
-    value = steps_per_perm * args.steps / elapsed
-    avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
-    # algorithmic work of one launch = the Gray steps whose product the kernel
-    # evaluated (all of them without zero-aware skipping) x FP64 flops per step
-    eval_steps = sum(evaluated) / len(evaluated)
-    flops = st["flops_per_step"] * eval_steps
+    elapsed, kernel_ms, evaluated, values, st, first = timed_calls(opts, args.steps, args.warmup)
+    kern = kernel_record(st, kernel_ms, evaluated, first)
+    avg_kernel_s = kern["avg_ms"] / 1e3
+    # algorithmic work: the FP64 operations of the generated code per step
+    # (Alg. 1's updates, products and accumulation, plus the exact mode's
+    # residue and bound operations) over every evaluated step
+    flops = st["flops_per_step"] * kern["evaluated_steps_per_launch_set"]
     achieved_tflops = flops / avg_kernel_s / 1e12
-    ops_rate = st["ops_per_step"] * eval_steps / avg_kernel_s
+    src = P.perm_codegen(ccs, **dict(opts, waves_per_simd=st["waves_hint"] or -1))
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": steps_per_perm * args.steps / elapsed,
         "unit": "Gray-code steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -350,51 +427,47 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "single sparse 0/1 matrix n=%d, permutation pattern OR Bernoulli(0.10), seed %d"
-                               % (n, args.seed), "n": n, "nnz": len(ccs[2]), "mode": args.mode,
-                   "zero_skip": args.zero_skip,
+        "config": {"workload": "single sparse 0/1 matrix n=%d, permutation pattern OR Bernoulli(0.10), seed %d, "
+                               "all 2^%d Gray-code terms evaluated, exact integer count" % (n, args.seed, n - 1),
+                   "n": n, "nnz": len(ccs[2]), "mode": args.mode,
                    "options": "given" if args.opts else ("library defaults" if args.no_tune else
                                                          "perm_autotune, searched before the timed region"),
                    "chosen": chosen, "gray_steps_per_permanent": steps_per_perm},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(P.perm_codegen(ccs, **dict(opts, waves_per_simd=st["waves_hint"] or -1)))},
-        "kernel": {"name": "perm_gray", "avg_ms": avg_kernel_s * 1e3, "steps_per_s": steps_per_perm / avg_kernel_s,
-                   "flops_per_step": st["flops_per_step"], "fp64_ops_per_step": st["ops_per_step"],
-                   "fp64_issue_frac": ops_rate / 3.93216e13, "vgprs": st["vgprs"], "sgprs": st["sgprs"],
-                   "scratch_bytes": st["scratch_bytes"], "waves_per_simd": st["waves_per_simd"], "waves_hint": st["waves_hint"],
-                   "vgpr_spills": st["vgpr_spills"],
-                   "chunk_log2": st["chunk_log2"], "unroll_log2": st["unroll_log2"], "levels": st["levels"],
-                   "k": st["k"], "c": st["c"], "nblocks": st["nblocks"], "reduce_ms": st["reduce_ms"],
-                   "host_ms": st["host_ms"], "compile_ms_cold": first["compile_ms"] if first else None,
-                   "evaluated_steps_per_launch": eval_steps,
-                   "skipped_fraction": 1.0 - eval_steps / steps_per_perm},
+                     "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": measured_traffic(src)},
+        "kernel": kern,
         "permanent": values[-1],
         "deterministic": all(x == values[0] for x in values),
     }
     if tune is not None:
-        # context: the search, and the same permanent with the library's defaults
-        ks = []
-        for _ in range(3):
-            _, std = P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=zs)
-            ks.append(std["kernel_ms"])
-        kd = sum(ks) / len(ks)
-        out["autotune"] = dict(tune, default_options_kernel_ms=kd, default_options_steps_per_s=steps_per_perm / kd * 1e3)
-    if zs is not False and not args.no_unpruned:
-        # context: the same permanent with every term evaluated (pruning off)
-        P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=False)
-        ks = []
-        for _ in range(3):
-            _, st0 = P.perm_sparse_ex(ccs, mode=args.mode, zero_skip=False)
-            ks.append(st0["kernel_ms"] / 1e3)
-        k0 = sum(ks) / len(ks)
-        tf0 = st0["flops_per_step"] * steps_per_perm / k0 / 1e12
-        out["no_skip"] = {"kernel_ms": k0 * 1e3, "steps_per_s": steps_per_perm / k0, "achieved_tflops": tf0,
-                          "frac": tf0 / FP64_PEAK_TFLOPS,
-                          "fp64_issue_frac": st0["ops_per_step"] * steps_per_perm / k0 / 3.93216e13,
-                          "vgprs": st0["vgprs"], "waves_per_simd": st0["waves_per_simd"]}
+        out["autotune"] = tune
+    # ---- the same permanent with exact zero-aware pruning (beyond the paper) ----
+    if args.zero_skip != "off" and not args.no_pruned:
+        popts, ptune = tuned(mode=args.mode, zero_skip={"auto": "auto", "on": True}[args.zero_skip])
+        pel, pk, pev, pvals, pst, pfirst = timed_calls(popts, max(args.steps, 20), args.warmup)
+        pkern = kernel_record(pst, pk, pev, pfirst)
+        pflops = pst["flops_per_step"] * pkern["evaluated_steps_per_launch_set"]
+        out["pruned"] = {
+            "permanents_per_s": len(pk) / pel, "ms_per_permanent": pel / len(pk) * 1e3,
+            "step_equivalent_per_s": steps_per_perm * len(pk) / pel,
+            "note": "step_equivalent_per_s counts all 2^(n-1) terms, most of them skipped as exactly zero; "
+                    "evaluated_steps_per_s counts the terms the kernel evaluated",
+            "kernel": pkern, "permanent": pvals[-1], "same_as_headline": pvals[-1] == values[-1],
+            "roofline": {"bound": "alu", "achieved": pflops / (pkern["avg_ms"] / 1e3) / 1e12,
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": pflops / (pkern["avg_ms"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+                         "traffic": measured_traffic(P.perm_codegen(
+                             ccs, **dict(popts, waves_per_simd=pst["waves_hint"] or -1)))},
+            "options": {k: popts.get(k) for k in ("chunk_log2", "unroll_log2", "block", "waves_per_simd",
+                                                   "block_queue")},
+            "autotune": ptune}
     if not args.no_batch:
-        out["batch"] = batch_bench()
+        bopts = None
+        if not args.no_tune:
+            from paper_2501_15126_amd import workloads as W2
+            bopts, btune = P.perm_batch_autotune(W2.batch(1, 2000))
+            print("bench: batch autotuned: %s" % bopts, file=sys.stderr, flush=True)
+        out["batch"] = batch_bench(opts={k: bopts[k] for k in ("block", "batch_kappa_shift")} if bopts else None)
     if args.serving_seconds > 0:
         out["serving"] = serving_bench(args.serving_seconds, rate_hz=args.serving_rate)
     if not args.no_cpu_baseline:

@@ -89,12 +89,16 @@ typedef struct {
                               factor that is exactly 0 in every lane.  0 = auto (on
                               when every value is an integer, where such zeros are
                               common), 1 = on, -1 = off */
-    int32_t batch_mode;    /* perm_batch: 0 = one launch per kernel instance, each on
-                              its own class stream so instances overlap (default);
-                              1 = the same launches on one stream, captured as a graph
-                              and launched; 2 = one matrix per launch, synchronised
-                              after each (the sequential baseline); 3 = the launches of
-                              0 on one stream */
+    int32_t batch_mode;    /* perm_batch: 0 = one launch per kernel instance, one wave per
+                              work item (64 chunks of one matrix), each instance on its own
+                              class stream so instances overlap (default); 1 = persistent
+                              instances (a grid of resident waves taking work items from an
+                              atomic counter) on those streams, captured in one graph that is
+                              launched again, without a new capture, for later batches with
+                              the same launch layout; 2 = one matrix per launch, synchronised
+                              after each (the sequential baseline); 3 = the launches of 0 on
+                              one stream.  perm_batch also reads `block` (64, 128 or 256
+                              threads per workgroup; 0 = 256) */
     int32_t batch_kappa_shift; /* perm_batch: added to the default chunk log2 */
     int32_t cold_tier;     /* HYBRID: where rows >= k live; 0 = global memory (the paper's
                               scheme), 1 = LDS, [row][lane] per workgroup (the block is
@@ -223,7 +227,8 @@ typedef struct {
                                   structurally singular) */
     int32_t exact_uncertified; /* exact-mode matrices left at the FP64 estimate */
     int32_t passes;        /* kernel passes run (exact mode: one per prime needed) */
-    int32_t pad2;
+    int32_t graph_captures; /* graph captures of the process so far (batch_mode 1 captures
+                              once per launch layout and relaunches the graph after) */
 } perm_batch_stats;
 
 /* perm_batch with statistics (st may be NULL). */
@@ -263,11 +268,13 @@ typedef struct {
 perm_status perm_autotune(const perm_csc *a, const perm_opts *opts, perm_opts *best, perm_tune_stats *st);
 
 /* Picks perm_batch options for a batch by running it whole: the launch form
- * (batch_mode 0, instances on their own streams, or 1, one captured graph)
+ * (batch_mode 0, one wave per item on the class streams, or 1, persistent
+ * instances in one captured graph), the threads per workgroup (64, 128, 256)
  * and then batch_kappa_shift (+-1, +-2), each kept if at least 2 % faster
  * in device time (best of 3 runs).  Results are bitwise independent of
- * batch_mode; batch_kappa_shift changes the chunking, so results may differ
- * in the last bits. */
+ * batch_mode and block; batch_kappa_shift changes the chunking, so results
+ * may differ in the last bits (integer-valued matrices: not at all, their
+ * results are exact). */
 perm_status perm_batch_autotune(int32_t count, const perm_csc *mats, const perm_opts *opts, perm_opts *best,
                                 perm_tune_stats *st);
 
@@ -312,6 +319,9 @@ typedef struct {
     uint64_t pending, active;       /* queued (not admitted) / admitted, running */
     uint64_t arena_bytes, arena_used, arena_peak;
     double busy_ms;                 /* wall time with at least one round in flight */
+    uint64_t exact_certified;       /* exact-mode requests answered with the certified integer */
+    uint64_t exact_uncertified;     /* exact-mode requests left at the FP64 estimate */
+    uint64_t extra_passes;          /* exact-mode passes beyond each request's first (next primes) */
 } perm_server_stats;
 perm_status perm_server_get_stats(perm_server *s, perm_server_stats *st);
 

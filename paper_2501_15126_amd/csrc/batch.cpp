@@ -237,6 +237,7 @@ BatchJob::~BatchJob() {
     if (d_fin) (void)hipFree(d_fin);
     if (d_partials) (void)hipFree(d_partials);
     if (d_out) (void)hipFree(d_out);
+    if (d_counters) (void)hipFree(d_counters);
     if (h_stage) (void)hipHostFree(h_stage);
     if (h_out) (void)hipHostFree(h_out);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -244,7 +245,8 @@ BatchJob::~BatchJob() {
 }
 
 perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, double *out, hipStream_t stream,
-                          BatchLaunch how, double *kernel_ms, std::string *err, int *exact_state, int *passes) {
+                          BatchLaunch how, double *kernel_ms, std::string *err, int *exact_state, int *passes,
+                          int min_passes) {
     const int count = (int)mats.size();
     std::vector<double> raw((size_t)kPartStride * std::max(count, 1), 0.0);
     std::vector<int> prime(count, 0);
@@ -279,7 +281,8 @@ perm_status BatchJob::run(const std::vector<const PreparedMatrix *> &mats, doubl
             const ExactOutcome eo = exact_recover(mats[i]->n, es[i]);
             out[i] = eo.value;
             if (exact_state) exact_state[i] = eo.certified ? 1 : 0;
-            if (!eo.certified && eo.more) again.push_back(i);
+            const bool forced = es[i].passes < std::min(min_passes, kExactMaxPasses);
+            if ((!eo.certified && eo.more) || forced) again.push_back(i);
         }
         if (again.empty()) break;
         std::vector<const PreparedMatrix *> sub;
@@ -421,25 +424,56 @@ perm_status BatchJob::run_pass(const std::vector<const PreparedMatrix *> &mats, 
     if (!ev0) {
         HIP_OK(hipEventCreate(&ev0));
         HIP_OK(hipEventCreate(&ev1));
+        HIP_OK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
         for (int i = 0; i < kBatchStreams; ++i) HIP_OK(hipEventCreateWithFlags(&ev_join[i], hipEventDisableTiming));
+    }
+    const bool persistent = how == BatchLaunch::Graph;
+    const bool branches = how == BatchLaunch::Streams || how == BatchLaunch::Graph;
+    // persistent form: one item counter and a resident-size grid per instance
+    std::vector<int> grids(plans.size(), 0);
+    if (persistent) {
+        if ((s = grow(&d_counters, &cap_counters, plans.size(), err)) != PERM_OK) return s;
+        for (size_t i = 0; i < plans.size(); ++i) {
+            const WavePlan &w = plans[i];
+            const int rb = batch_resident_blocks(w.ng, w.zero_skip, w.exact, block);
+            if (rb <= 0) {
+                *err = "occupancy query of the persistent batch kernel failed";
+                return PERM_EDEVICE;
+            }
+            const int64_t need = ((int64_t)w.nwaves + block / 64 - 1) / (block / 64);
+            grids[i] = (int)std::min<int64_t>(rb, need);
+        }
     }
     HIP_OK(hipEventRecord(ev0, stream));
     hipStream_t cls[kBatchStreams];
-    if (how == BatchLaunch::Streams) HIP_OK(batch_class_streams(cls));
-    // the launches: one per kernel instance, then the per-matrix finish
+    if (branches) HIP_OK(batch_class_streams(cls));
+    // the launches: one per kernel instance (each instance on its class
+    // stream, forked from and joined to `stream`), then the per-matrix finish
     auto enqueue = [&]() -> perm_status {
         bool used[kBatchStreams] = {};
         size_t r0 = 0, b0 = 0;
-        for (const WavePlan &w : plans) {
+        if (persistent) HIP_OK(launch_counters_reset(d_counters, (int)plans.size(), stream));
+        if (branches) HIP_OK(hipEventRecord(ev_fork, stream));
+        for (size_t i = 0; i < plans.size(); ++i) {
+            const WavePlan &w = plans[i];
             hipStream_t st = stream;
-            if (how == BatchLaunch::Streams) {
+            if (branches) {
                 const int c = w.ng % kBatchStreams;
                 st = cls[c];
-                if (!used[c]) HIP_OK(hipStreamWaitEvent(st, ev0, 0));
+                if (!used[c]) HIP_OK(hipStreamWaitEvent(st, ev_fork, 0));
                 used[c] = true;
             }
-            HIP_OK(launch_batch_ranges(w.ng, w.zero_skip, w.exact, d_ranges + r0, (int)w.ranges.size(),
-                                       d_blk + b0, (int64_t)w.nwaves, d_mats, d_vals, d_tops, d_partials, st));
+            BatchLaunchArgs la;
+            la.ranges = d_ranges + r0;
+            la.nranges = (int)w.ranges.size();
+            la.blk_first = d_blk + b0;
+            la.nwaves = (int64_t)w.nwaves;
+            la.mats = d_mats;
+            la.vals = d_vals;
+            la.tops = d_tops;
+            la.partials = d_partials;
+            HIP_OK(launch_batch_ranges(w.ng, w.zero_skip, w.exact, la, block, persistent ? d_counters + i : nullptr,
+                                       grids[i], st));
             r0 += w.ranges.size();
             b0 += w.blk_first.size();
         }
@@ -452,28 +486,47 @@ perm_status BatchJob::run_pass(const std::vector<const PreparedMatrix *> &mats, 
         return PERM_OK;
     };
     if (how == BatchLaunch::Graph) {
-        if (graph_exec) {
-            hipGraphExecDestroy(graph_exec);
-            graph_exec = nullptr;
+        // The captured graph depends only on the launch layout and the device
+        // buffers (the data are copied in before it runs), so a later batch
+        // with the same layout relaunches it without capturing again.
+        std::string sig;
+        auto put = [&](const void *q, size_t n) { sig.append(static_cast<const char *>(q), n); };
+        const void *ptrs[] = {d_ranges, d_blk, d_mats, d_vals, d_tops, d_partials, d_fin, d_out, d_counters};
+        put(ptrs, sizeof ptrs);
+        put(&nm, sizeof nm);
+        put(&block, sizeof block);
+        for (size_t i = 0; i < plans.size(); ++i) {
+            const WavePlan &w = plans[i];
+            const int64_t f[] = {w.ng, w.zero_skip, w.exact, (int64_t)w.ranges.size(), (int64_t)w.nwaves, grids[i]};
+            put(f, sizeof f);
         }
-        if (graph) {
-            hipGraphDestroy(graph);
-            graph = nullptr;
+        if (!graph_exec || sig != graph_sig) {
+            if (graph_exec) {
+                (void)hipGraphExecDestroy(graph_exec);
+                graph_exec = nullptr;
+            }
+            if (graph) {
+                (void)hipGraphDestroy(graph);
+                graph = nullptr;
+            }
+            graph_sig.clear();
+            HIP_OK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            perm_status es = enqueue();
+            hipGraph_t g = nullptr;
+            hipError_t ce = hipStreamEndCapture(stream, &g);
+            if (es != PERM_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return es;
+            }
+            if (ce != hipSuccess) {
+                *err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ce);
+                return PERM_EDEVICE;
+            }
+            graph = g;
+            HIP_OK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+            graph_sig = sig;
+            ++graph_captures;
         }
-        HIP_OK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        perm_status es = enqueue();
-        hipGraph_t g = nullptr;
-        hipError_t ce = hipStreamEndCapture(stream, &g);
-        if (es != PERM_OK) {
-            if (g) hipGraphDestroy(g);
-            return es;
-        }
-        if (ce != hipSuccess) {
-            *err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ce);
-            return PERM_EDEVICE;
-        }
-        graph = g;
-        HIP_OK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
         HIP_OK(hipGraphLaunch(graph_exec, stream));
     } else {
         perm_status es = enqueue();

@@ -17,13 +17,33 @@
 
 namespace permx {
 
-// Launches the batch kernel for waves [0, nwaves) described by ranges[0,
-// nranges) (sorted by wave0, each non-empty, ranges[0].wave0 = 0) whose
-// matrices all have ng groups and the same zero_skip and exact flags;
-// blk_first[b] is the range holding wave 4b.
-hipError_t launch_batch_ranges(int ng, bool zero_skip, bool exact, const BatchRange *ranges, int nranges,
-                               const int32_t *blk_first, int64_t nwaves, const BatchMat *mats, const double *vals,
-                               const int32_t *tops, double *partials, hipStream_t stream);
+// The waves of one launch: ranges[0, nranges) (sorted by wave0, each
+// non-empty, ranges[0].wave0 = 0), blk_first[b] = the range holding wave 4b,
+// matrices, their column data and tops, and the partials written.
+struct BatchLaunchArgs {
+    const BatchRange *ranges = nullptr;
+    int nranges = 0;
+    const int32_t *blk_first = nullptr;
+    int64_t nwaves = 0;
+    const BatchMat *mats = nullptr;
+    const double *vals = nullptr;
+    const int32_t *tops = nullptr;
+    double *partials = nullptr;
+};
+
+// Launches the batch kernel instance (ng groups, zero_skip, exact) for waves
+// [0, nwaves) with `block` threads (64, 128 or 256) per workgroup: one wave per
+// work item, or, with a counter, `grid` workgroups of the persistent form
+// taking items from *counter (which must start at 0).
+hipError_t launch_batch_ranges(int ng, bool zero_skip, bool exact, const BatchLaunchArgs &a, int block,
+                               unsigned long long *counter, int grid, hipStream_t stream);
+
+// Workgroups of `block` threads of the persistent instance resident on the
+// current device at once (occupancy API times compute units); -1 on error.
+int batch_resident_blocks(int ng, bool zero_skip, bool exact, int block);
+
+// c[0 .. n-1] = 0 with a kernel (graph-capturable).
+hipError_t launch_counters_reset(unsigned long long *c, int n, hipStream_t stream);
 
 // out[kPartStride i ..] = the sum of the partials of d[i] (double-double term
 // sum, residue, sum of |term|), added in an order fixed by the partials'
@@ -31,8 +51,7 @@ hipError_t launch_batch_ranges(int ng, bool zero_skip, bool exact, const BatchRa
 hipError_t launch_batch_finish(const FinishDesc *d, int count, const double *partials, double *out,
                                hipStream_t stream);
 
-// Resources of the compiled batch kernel for ng groups (VGPRs, scratch); the
-// exact-mode zero-skip instance when exact, else the plain one.
-int batch_kernel_attributes(int ng, bool exact, int *vgprs, int *scratch);
+// Resources of the compiled batch kernel instance (VGPRs, scratch).
+int batch_kernel_attributes(int ng, bool zero_skip, bool exact, int *vgprs, int *scratch);
 
 }  // namespace permx

@@ -11,10 +11,15 @@
 //  * S[g] = product of x over groups >= g is cached; a step refreshes groups
 //    top[j]..1 and accumulates fma(+-G_0, S[1], acc) (the cached-product idea
 //    of Sec. V with fixed 4-row groups);
-//  * each wave takes 64 consecutive chunks of one matrix and writes one
-//    double-double partial; a second kernel adds each matrix's partials in a
-//    fixed order, so a matrix's result does not depend on the rest of the batch.
+//  * each wave takes 64 consecutive chunks of one matrix (a work item) and
+//    writes one partial; a second kernel adds each matrix's partials in a
+//    fixed order, so a matrix's result does not depend on the rest of the
+//    batch, nor on which wave ran which item;
+//  * launch forms: one wave per item, or persistent (a grid of resident
+//    waves taking items from an atomic counter).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "batch.h"
 #include "batch_lane.h"
@@ -33,20 +38,18 @@ constexpr int batch_waves_per_eu() {
     return NG == 8 ? 4 : 1;
 }
 
+// The work of wave w of a launch (wave-uniform w): the 64 chunks of item
+// item0 + (w - wave0) of its range's matrix, one per lane, and the wave's
+// partial (double-double term sum, then in exact mode the residue and the
+// sum of |term|) at partials[kPartStride (out0 + w - wave0) ..].
 template <int NG, bool ZS, bool EX>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<NG>()))) batch_kernel(const BatchRange *__restrict__ ranges, int nranges,
-                                                    const int32_t *__restrict__ blk_first, long long nwaves,
-                                                    const BatchMat *__restrict__ mats,
-                                                    const double *__restrict__ vals,
-                                                    const int32_t *__restrict__ tops_all,
-                                                    double *__restrict__ partials) {
-    // the wave's index is uniform: readfirstlane lets the compiler keep the
-    // range, the matrix descriptor and the column data in scalar registers
-    const long long w = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (w >= nwaves) return;  // the whole wave leaves together
-    // blk_first holds the range of the workgroup's first wave; ranges are
-    // non-empty, so the other three waves are at most three ranges further
-    int r = blk_first[blockIdx.x];
+__device__ __forceinline__ void wave_item(long long w, const BatchRange *__restrict__ ranges, int nranges,
+                                          const int32_t *__restrict__ blk_first, const BatchMat *__restrict__ mats,
+                                          const double *__restrict__ vals, const int32_t *__restrict__ tops_all,
+                                          double *__restrict__ partials) {
+    // blk_first[b] holds the range of wave 4b; ranges are non-empty, so wave w
+    // is at most three ranges further
+    int r = blk_first[w >> 2];
     while (r + 1 < nranges && (long long)ranges[r + 1].wave0 <= w) ++r;
     const BatchRange rg = ranges[r];
     const u64 k = (u64)(w - (long long)rg.wave0);
@@ -82,6 +85,54 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_
         partials[kPartStride * out + 2] = EX ? reduce_mod(xo[0], md.pmod, md.pinv) : 0.0;
         partials[kPartStride * out + 3] = xo[1];
     }
+}
+
+// One wave per work item: wave w = blockIdx.x * (waves per block) + its index
+// in the block.
+template <int NG, bool ZS, bool EX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<NG>()))) batch_kernel(const BatchRange *__restrict__ ranges, int nranges,
+                                                    const int32_t *__restrict__ blk_first, long long nwaves,
+                                                    const BatchMat *__restrict__ mats,
+                                                    const double *__restrict__ vals,
+                                                    const int32_t *__restrict__ tops_all,
+                                                    double *__restrict__ partials) {
+    // the wave's index is uniform: readfirstlane lets the compiler keep the
+    // range, the matrix descriptor and the column data in scalar registers
+    const long long w = (long long)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= nwaves) return;  // the whole wave leaves together
+    wave_item<NG, ZS, EX>(w, ranges, nranges, blk_first, mats, vals, tops_all, partials);
+}
+
+// Persistent form: a grid of at most the resident waves; each wave takes the
+// next work item from a counter (one atomic add per item) until none is
+// left, so every wave reaches the exit.  Results do not depend on which
+// wave ran an item (each item writes its own partial).
+template <int NG, bool ZS, bool EX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<NG>()))) batch_persistent(const BatchRange *__restrict__ ranges, int nranges,
+                                                    const int32_t *__restrict__ blk_first, long long nwaves,
+                                                    const BatchMat *__restrict__ mats,
+                                                    const double *__restrict__ vals,
+                                                    const int32_t *__restrict__ tops_all,
+                                                    double *__restrict__ partials,
+                                                    unsigned long long *__restrict__ counter) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned long long got = 0;
+        if (lane == 0) got = atomicAdd(counter, 1ull);
+        // the item index is the same in every lane: both halves to scalars
+        const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)got);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(got >> 32));
+        const long long w = (long long)(((unsigned long long)hi << 32) | lo);
+        if (w >= nwaves) break;
+        wave_item<NG, ZS, EX>(w, ranges, nranges, blk_first, mats, vals, tops_all, partials);
+    }
+}
+
+// Clears the persistent kernels' item counters (a kernel, not a memset, so
+// that it can sit in a captured graph).
+__global__ void batch_counters_reset(unsigned long long *__restrict__ c, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = 0ull;
 }
 
 // One workgroup per matrix: thread t adds partials t, t + 256, ... and a
@@ -136,34 +187,48 @@ __global__ void __launch_bounds__(256) batch_finish(const FinishDesc *__restrict
 }
 
 template <int NG, bool ZS, bool EX>
-void launch_one(unsigned blocks, const BatchRange *ranges, int nranges, const int32_t *blk_first, int64_t nwaves,
-                const BatchMat *mats, const double *vals, const int32_t *tops, double *partials, hipStream_t stream) {
-    hipLaunchKernelGGL((batch_kernel<NG, ZS, EX>), dim3(blocks), dim3(256), 0, stream, ranges, nranges, blk_first,
-                       (long long)nwaves, mats, vals, tops, partials);
-}
-
-template <int NG>
-hipError_t launch_t(bool zs, bool ex, const BatchRange *ranges, int nranges, const int32_t *blk_first,
-                    int64_t nwaves, const BatchMat *mats, const double *vals, const int32_t *tops, double *partials,
-                    hipStream_t stream) {
-    const unsigned blocks = (unsigned)((nwaves + 3) / 4);
-    if (zs && ex)
-        launch_one<NG, true, true>(blocks, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
-    else if (zs)
-        launch_one<NG, true, false>(blocks, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
-    else if (ex)
-        launch_one<NG, false, true>(blocks, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
-    else
-        launch_one<NG, false, false>(blocks, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
+hipError_t launch_one(const BatchLaunchArgs &a, int block, unsigned long long *counter, int grid,
+                      hipStream_t stream) {
+    if (counter) {
+        hipLaunchKernelGGL((batch_persistent<NG, ZS, EX>), dim3((unsigned)grid), dim3((unsigned)block), 0, stream,
+                           a.ranges, a.nranges, a.blk_first, (long long)a.nwaves, a.mats, a.vals, a.tops, a.partials,
+                           counter);
+    } else {
+        const int wpb = block / 64;
+        const unsigned blocks = (unsigned)((a.nwaves + wpb - 1) / wpb);
+        hipLaunchKernelGGL((batch_kernel<NG, ZS, EX>), dim3(blocks), dim3((unsigned)block), 0, stream, a.ranges,
+                           a.nranges, a.blk_first, (long long)a.nwaves, a.mats, a.vals, a.tops, a.partials);
+    }
     return hipGetLastError();
 }
 
 template <int NG>
-void attrs_t(bool ex, int *vgprs, int *scratch) {
+hipError_t launch_t(bool zs, bool ex, const BatchLaunchArgs &a, int block, unsigned long long *counter, int grid,
+                    hipStream_t stream) {
+    if (zs && ex) return launch_one<NG, true, true>(a, block, counter, grid, stream);
+    if (zs) return launch_one<NG, true, false>(a, block, counter, grid, stream);
+    if (ex) return launch_one<NG, false, true>(a, block, counter, grid, stream);
+    return launch_one<NG, false, false>(a, block, counter, grid, stream);
+}
+
+template <int NG>
+const void *kernel_of(bool zs, bool ex, bool persistent) {
+    if (persistent) {
+        if (zs && ex) return reinterpret_cast<const void *>(&batch_persistent<NG, true, true>);
+        if (zs) return reinterpret_cast<const void *>(&batch_persistent<NG, true, false>);
+        if (ex) return reinterpret_cast<const void *>(&batch_persistent<NG, false, true>);
+        return reinterpret_cast<const void *>(&batch_persistent<NG, false, false>);
+    }
+    if (zs && ex) return reinterpret_cast<const void *>(&batch_kernel<NG, true, true>);
+    if (zs) return reinterpret_cast<const void *>(&batch_kernel<NG, true, false>);
+    if (ex) return reinterpret_cast<const void *>(&batch_kernel<NG, false, true>);
+    return reinterpret_cast<const void *>(&batch_kernel<NG, false, false>);
+}
+
+template <int NG>
+void attrs_t(bool zs, bool ex, int *vgprs, int *scratch) {
     hipFuncAttributes a;
-    const void *f = ex ? reinterpret_cast<const void *>(&batch_kernel<NG, true, true>)
-                       : reinterpret_cast<const void *>(&batch_kernel<NG, false, false>);
-    if (hipFuncGetAttributes(&a, f) == hipSuccess) {
+    if (hipFuncGetAttributes(&a, kernel_of<NG>(zs, ex, false)) == hipSuccess) {
         *vgprs = a.numRegs;
         *scratch = (int)a.localSizeBytes;
     }
@@ -173,20 +238,46 @@ void attrs_t(bool ex, int *vgprs, int *scratch) {
 
 }  // namespace
 
-hipError_t launch_batch_ranges(int ng, bool zero_skip, bool exact, const BatchRange *ranges, int nranges,
-                               const int32_t *blk_first, int64_t nwaves, const BatchMat *mats, const double *vals,
-                               const int32_t *tops, double *partials, hipStream_t stream) {
-    if (nwaves <= 0) return hipSuccess;
-    if (nranges <= 0 || (nwaves + 3) / 4 > 0x7fffffff) return hipErrorInvalidValue;
+hipError_t launch_batch_ranges(int ng, bool zero_skip, bool exact, const BatchLaunchArgs &a, int block,
+                               unsigned long long *counter, int grid, hipStream_t stream) {
+    if (a.nwaves <= 0) return hipSuccess;
+    if (a.nranges <= 0 || a.nwaves > 0x7fffffffLL || (block != 64 && block != 128 && block != 256) ||
+        (counter && grid <= 0))
+        return hipErrorInvalidValue;
 #define PERM_CASE(NGV) \
     case NGV:          \
-        return launch_t<NGV>(zero_skip, exact, ranges, nranges, blk_first, nwaves, mats, vals, tops, partials, stream);
+        return launch_t<NGV>(zero_skip, exact, a, block, counter, grid, stream);
     switch (ng) {
         PERM_NG_TABLE(PERM_CASE)
         default:
             return hipErrorInvalidValue;
     }
 #undef PERM_CASE
+}
+
+int batch_resident_blocks(int ng, bool zero_skip, bool exact, int block) {
+    const void *f = nullptr;
+#define PERM_CASE(NGV)                                     \
+    case NGV:                                              \
+        f = kernel_of<NGV>(zero_skip, exact, true);        \
+        break;
+    switch (ng) {
+        PERM_NG_TABLE(PERM_CASE)
+        default:
+            return -1;
+    }
+#undef PERM_CASE
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, block, 0) != hipSuccess) return -1;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+    return std::max(1, per_cu) * cus;
+}
+
+hipError_t launch_counters_reset(unsigned long long *c, int n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_counters_reset, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, c, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_finish(const FinishDesc *d, int count, const double *partials, double *out,
@@ -196,12 +287,12 @@ hipError_t launch_batch_finish(const FinishDesc *d, int count, const double *par
     return hipGetLastError();
 }
 
-int batch_kernel_attributes(int ng, bool exact, int *vgprs, int *scratch) {
+int batch_kernel_attributes(int ng, bool zero_skip, bool exact, int *vgprs, int *scratch) {
     *vgprs = -1;
     *scratch = -1;
-#define PERM_CASE(NGV)                       \
-    case NGV:                                \
-        attrs_t<NGV>(exact, vgprs, scratch); \
+#define PERM_CASE(NGV)                                  \
+    case NGV:                                           \
+        attrs_t<NGV>(zero_skip, exact, vgprs, scratch); \
         return 0;
     switch (ng) {
         PERM_NG_TABLE(PERM_CASE)

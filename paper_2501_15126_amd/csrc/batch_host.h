@@ -66,7 +66,9 @@ hipError_t batch_class_streams(hipStream_t out[kBatchStreams]);
 // How perm_batch issues its launches.
 enum class BatchLaunch {
     Streams,  // each kernel instance on its class stream, forked from and joined to the caller's stream
-    Graph,    // all launches on the caller's stream, captured into one graph and launched
+    Graph,    // persistent instances (resident waves taking items from a counter) on their class
+              // streams, captured into one graph; the graph is kept and launched again while
+              // the launch layout and buffers stay the same
     Single,   // all launches on the caller's stream
 };
 
@@ -86,20 +88,26 @@ struct BatchJob {
     size_t cap_stage = 0;
     double *h_out = nullptr;
     size_t cap_hout = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    unsigned long long *d_counters = nullptr;  // persistent form: one item counter per instance
+    size_t cap_counters = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_fork = nullptr;
     hipEvent_t ev_join[kBatchStreams] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    std::string graph_sig;   // launch layout the graph was captured for
+    int graph_captures = 0;  // captures so far (a relaunch does not count)
+    int block = 256;         // threads per workgroup of the batch kernels: 64, 128 or 256
 
     ~BatchJob();
     // Runs all matrices (singular ones are answered 0 without work) and writes
     // out[i] for mats[i].  Exact-mode matrices whose result is not certified
-    // after a pass run again with the next prime (exact.h).  Synchronous on
+    // after a pass run again with the next prime (exact.h), and all of them
+    // until min_passes primes have run.  Synchronous on
     // `stream`.  Optional: exact_state[i] = 1 certified exact, 0 exact mode
     // but uncertified, -1 not in exact mode; *passes = passes run.
     perm_status run(const std::vector<const PreparedMatrix *> &mats, double *out, hipStream_t stream,
                     BatchLaunch how, double *kernel_ms, std::string *err, int *exact_state = nullptr,
-                    int *passes = nullptr);
+                    int *passes = nullptr, int min_passes = 0);
 
   private:
     // One pass: raw[kPartStride i ..] = (term sum hi, lo, residue, sum |term|)

@@ -451,7 +451,9 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
     st.sum_lo = po.lo;
     st.evaluated_steps = po.evaluated;
     if (pl.exact) {
-        // the term sums are in y = 2x units: 2^n times Alg. 1's
+        // the term sums are in y = 2x units: 2^n times Alg. 1's (exact scaling)
+        if (o.block_partials && o.block_partials_cap >= st.nblocks)
+            for (int64_t i = 0; i < 2 * st.nblocks; ++i) o.block_partials[i] = std::ldexp(o.block_partials[i], -pl.n);
         st.sum_hi = std::ldexp(po.hi, -pl.n);
         st.sum_lo = std::ldexp(po.lo, -pl.n);
         st.exact = eo.certified ? 1 : 0;
@@ -818,11 +820,22 @@ perm_status autotune_batch(int32_t count, const perm_csc *mats, const perm_opts 
         }
         return PERM_OK;
     };
-    // launch form: instances on their own streams, or captured as one graph
+    // launch form: one wave per item on the class streams, or the persistent
+    // instances in one captured graph
     std::vector<perm_opts> cands;
     {
         perm_opts c = cur;
         c.batch_mode = cur.batch_mode == 1 ? 0 : 1;
+        cands.push_back(c);
+    }
+    s = try_all(cands);
+    if (s != PERM_OK) return s;
+    // threads per workgroup
+    cands.clear();
+    for (int b : {64, 128, 256}) {
+        if (b == (cur.block > 0 ? cur.block : 256)) continue;
+        perm_opts c = cur;
+        c.block = b;
         cands.push_back(c);
     }
     s = try_all(cands);
@@ -883,7 +896,8 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
     bo.zero_skip = o.zero_skip;
     bo.kappa_shift = o.batch_kappa_shift;
     bo.exact = o.exact;
-    if (o.exact < -1 || o.exact > 1) return fail(PERM_EINVAL, "exact must be -1, 0 or 1");
+    if (o.exact < -1 || o.exact > 1 || o.exact_passes < 0 || o.exact_passes > kExactMaxPasses)
+        return fail(PERM_EINVAL, "exact must be -1, 0 or 1 and exact_passes 0..3");
     std::vector<PreparedMatrix> prep(count);
     std::string err;
     double steps = 0.0, ops = 0.0, fmas = 0.0;
@@ -914,9 +928,12 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
         }
     }
     auto t1 = std::chrono::steady_clock::now();
+    if (!(o.block == 0 || o.block == 64 || o.block == 128 || o.block == 256))
+        return fail(PERM_EINVAL, "perm_batch: block must be 64, 128 or 256 (0 = 256)");
     std::lock_guard<std::mutex> g(g_mu);
     perm_status s = ensure_device();
     if (s != PERM_OK) return s;
+    g_batch_job.block = o.block > 0 ? o.block : 256;
     hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : g_dev.stream;
     double kms = 0.0;
     int launches = 0, passes = 0;
@@ -926,7 +943,7 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
             std::vector<const PreparedMatrix *> one{&prep[i]};
             double k1 = 0.0;
             int np = 0;
-            s = g_batch_job.run(one, &out[i], stream, BatchLaunch::Single, &k1, &err, &xs[i], &np);
+            s = g_batch_job.run(one, &out[i], stream, BatchLaunch::Single, &k1, &err, &xs[i], &np, o.exact_passes);
             if (s != PERM_OK) return fail(s, err);
             kms += k1;
             launches += prep[i].singular ? 0 : 2 * np;
@@ -938,7 +955,7 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
         const BatchLaunch how = o.batch_mode == 0   ? BatchLaunch::Streams
                                 : o.batch_mode == 1 ? BatchLaunch::Graph
                                                     : BatchLaunch::Single;
-        s = g_batch_job.run(all, out, stream, how, &kms, &err, xs.data(), &passes);
+        s = g_batch_job.run(all, out, stream, how, &kms, &err, xs.data(), &passes, o.exact_passes);
         if (s != PERM_OK) return fail(s, err);
         launches = -1;
     }
@@ -954,6 +971,7 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
         st->fp64_ops = ops;
         st->flops = ops + fmas;
         st->passes = passes;
+        st->graph_captures = g_batch_job.graph_captures;
         for (int32_t i = 0; i < count; ++i) {
             if (xs[i] == 1 && !prep[i].singular) st->exact_certified++;
             if (xs[i] == 0) st->exact_uncertified++;

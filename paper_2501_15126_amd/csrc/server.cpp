@@ -204,6 +204,7 @@ struct perm_server {
 
     // statistics
     uint64_t n_submitted = 0, n_completed = 0, n_rounds = 0, n_extra_passes = 0;
+    uint64_t n_exact_certified = 0, n_exact_uncertified = 0;
     size_t peak_bytes = 0;
     double busy_ms = 0.0;
     Clock::time_point busy_since;
@@ -407,8 +408,16 @@ bool perm_server::issue(Slot &slot, const std::vector<Request *> &newly, std::st
             }
             size_t r0 = 0, b0 = 0;
             for (const WavePlan &w : plans) {
-                SRV_HIP(launch_batch_ranges(w.ng, w.zero_skip, w.exact, cb.d_ranges + r0, (int)w.ranges.size(),
-                                            cb.d_blk + b0, (int64_t)w.nwaves, cb.d_mats, vals, tops, parts, st));
+                BatchLaunchArgs la;
+                la.ranges = cb.d_ranges + r0;
+                la.nranges = (int)w.ranges.size();
+                la.blk_first = cb.d_blk + b0;
+                la.nwaves = (int64_t)w.nwaves;
+                la.mats = cb.d_mats;
+                la.vals = vals;
+                la.tops = tops;
+                la.partials = parts;
+                SRV_HIP(launch_batch_ranges(w.ng, w.zero_skip, w.exact, la, 256, nullptr, 0, st));
                 r0 += w.ranges.size();
                 b0 += w.blk_first.size();
             }
@@ -454,7 +463,8 @@ bool perm_server::complete(Slot &slot, std::string *err) {
                 const ExactOutcome eo = exact_recover(r->pm.n, es);
                 r->result = eo.value;
                 r->exact_state = eo.certified ? 1 : 0;
-                if (!eo.certified && eo.more) {
+                const bool forced = es.passes < std::min(opts.exact_passes, kExactMaxPasses);
+                if ((!eo.certified && eo.more) || forced) {
                     ++r->pass;
                     r->next_item = 0;
                     ++n_extra_passes;
@@ -463,6 +473,8 @@ bool perm_server::complete(Slot &slot, std::string *err) {
             } else {
                 r->result = (o[0] + o[1]) * ((r->pm.n % 2 == 1) ? 2.0 : -2.0);  // 4 (n mod 2) - 2
             }
+            if (r->exact_state == 1) ++n_exact_certified;
+            if (r->exact_state == 0) ++n_exact_uncertified;
             r->state = State::Done;
             r->t_done = now;
             alloc.release(r->arena_off, r->bytes);
@@ -547,8 +559,8 @@ perm_server *perm_server_create(const perm_opts *opts, size_t device_mem_budget,
     s->bo.zero_skip = s->opts.zero_skip;
     s->bo.kappa_shift = s->opts.batch_kappa_shift + kServerChunkShift;
     s->bo.exact = s->opts.exact;
-    if (s->opts.exact < -1 || s->opts.exact > 1) {
-        set_last_error("exact must be -1, 0 or 1");
+    if (s->opts.exact < -1 || s->opts.exact > 1 || s->opts.exact_passes < 0 || s->opts.exact_passes > 3) {
+        set_last_error("exact must be -1, 0 or 1 and exact_passes 0..3");
         return nullptr;
     }
     s->budget = device_mem_budget ? device_mem_budget : ((size_t)1 << 30);
@@ -676,6 +688,9 @@ perm_status perm_server_get_stats(perm_server *s, perm_server_stats *st) {
     st->arena_used = s->alloc.used();
     st->arena_peak = s->peak_bytes;
     st->busy_ms = s->busy_ms;
+    st->exact_certified = s->n_exact_certified;
+    st->exact_uncertified = s->n_exact_uncertified;
+    st->extra_passes = s->n_extra_passes;
     return PERM_OK;
 }
 

@@ -62,7 +62,8 @@ class PermBatchStats(ctypes.Structure):
                 ("steps", ctypes.c_double), ("count", ctypes.c_int32), ("singular", ctypes.c_int32),
                 ("launches", ctypes.c_int32), ("pad", ctypes.c_int32), ("fp64_ops", ctypes.c_double),
                 ("flops", ctypes.c_double), ("exact_ops", ctypes.c_double), ("exact_certified", ctypes.c_int32),
-                ("exact_uncertified", ctypes.c_int32), ("passes", ctypes.c_int32), ("pad2", ctypes.c_int32)]
+                ("exact_uncertified", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("graph_captures", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name not in ("pad", "pad2")}
@@ -132,7 +133,9 @@ _lib.perm_version.argtypes = []
 class PermServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
                 ("pending", ctypes.c_uint64), ("active", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
-                ("arena_used", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64), ("busy_ms", ctypes.c_double)]
+                ("arena_used", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64), ("busy_ms", ctypes.c_double),
+                ("exact_certified", ctypes.c_uint64), ("exact_uncertified", ctypes.c_uint64),
+                ("extra_passes", ctypes.c_uint64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -226,7 +229,7 @@ def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, 
     o.vgpr_budget, o.force_k, o.force_c, o.max_levels = vgpr_budget, force_k, force_c, max_levels
     o.gr_ratio = gr_ratio
     o.zero_skip = {"auto": 0, True: 1, False: -1}[zero_skip]
-    o.batch_mode = {"streams": 0, "graph": 1, "sequential": 2, "one_stream": 3}[batch_mode]
+    o.batch_mode = {"streams": 0, "graph": 1, "persistent": 1, "sequential": 2, "one_stream": 3}[batch_mode]
     o.batch_kappa_shift = batch_kappa_shift
     o.cold_tier = {"global": 0, "lds": 1}[cold_tier]
     o.progress = 1 if progress else 0

@@ -164,4 +164,6 @@ WORKLOADS = {
     "n24_p0.15_01": lambda seed=1: single_01(24, 0.15, seed),
     "n36_p0.30_real": lambda seed=1: single_real(36, 0.30, seed),
     "n40_p0.10_01": lambda seed=1: single_01(40, 0.10, seed),
+    # a 0/1 matrix whose FP64 rounding error reaches units (exact-mode test case)
+    "n36_p0.15_01": lambda seed=1: single_01(36, 0.15, seed),
 }

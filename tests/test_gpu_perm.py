@@ -231,9 +231,9 @@ def test_full_size_closed_forms(P, oracle_mod):
             got, st = P.perm_sparse_ex(ccs, zero_skip=zs)
             print("closed form", want, got, zs, st["kernel_ms"], flush=True)
             if want == round(want) and (A == np.round(A)).all():
-                # products of 40 half-integers exceed 2^53, so terms round:
-                # a 0/1 result must round to the exact count
-                assert abs(got - want) < 0.5 and round(got) == want, (want, got, zs)
+                # products of 40 half-integers exceed 2^53, so FP64 terms
+                # round; the exact mode returns the count itself
+                assert got == want and st["exact"] == 1, (want, got, zs)
             else:
                 assert got == pytest.approx(want, rel=1e-10), (want, got, zs)
 
@@ -273,10 +273,12 @@ def test_n40_full_exact(P):
     exact = int(g[key]["perm_exact"])
     for mode, zs in (("auto", "auto"), ("auto", False), ("pure", "auto"), ("hybrid", "auto")):
         got, st = P.perm_sparse_ex(ccs, mode=mode, zero_skip=zs)
-        print("n40", mode, zs, got, exact, st["kernel_ms"], st["vgprs"], st["waves_per_simd"])
-        # products of 40 half-integers can exceed 2^53, so single terms are
-        # rounded; the FP64 result must still round to the exact count
-        assert abs(got - exact) < 0.5 and round(got) == exact
+        print("n40", mode, zs, got, exact, st["kernel_ms"], st["vgprs"], st["waves_per_simd"], st["exact_passes"],
+              st["err_bound"], flush=True)
+        # products of 40 half-integers can exceed 2^53, so FP64 terms round;
+        # the exact mode returns the count itself, with its certificate
+        assert got == exact and st["exact"] == 1
+        assert abs(st["estimate"] - exact) <= st["err_bound"]
 
 
 def test_n40_bench_configuration_block_partials(P, oracle_mod):
@@ -319,7 +321,7 @@ def test_n40_bench_configuration_block_partials(P, oracle_mod):
     for w in (0, -1):
         got, st, parts = P.perm_sparse_ex(ccs, unroll_log2=7, waves_per_simd=w, block_partials=True)
         print("n40 bench config", w, got, st["kernel_ms"], st["vgprs"], st["waves_per_simd"], flush=True)
-        assert abs(got - exact) < 0.5 and round(got) == exact
+        assert got == exact and st["exact"] == 1
         assert (st["block"] << st["chunk_log2"]) == W_ and st["nblocks"] == nb
         for b, ((h, l), (ah, al)) in refs.items():
             part = parts[b, 0] + parts[b, 1]
@@ -401,3 +403,37 @@ def test_autotune_single(P, oracle_mod):
     assert st["sample_fraction"] == 1.0
     got, _ = P.perm_sparse_ex(small, **opts)
     assert abs(got - ref) <= _tol(20, ref, abs_sum)
+
+
+def test_n36_01_full_exact(P):
+    """An n = 36, p = 0.15 0/1 matrix (permanent about 1.3e13, terms near
+    1e18): FP64 alone misses the count by units; the exact mode returns it,
+    with a first pass and with all three primes forced."""
+    g = _golden()
+    key = "n36_p0.15_01:1"
+    if key not in g:
+        pytest.skip("stored n=36 0/1 oracle value not generated")
+    exact = int(g[key]["perm_exact"])
+    ccs = W.WORKLOADS["n36_p0.15_01"](1)
+    for kw in ({}, {"exact_passes": 3}, {"zero_skip": False}):
+        got, st = P.perm_sparse_ex(ccs, **kw)
+        print("n36 0/1", kw, got, exact, st["estimate"], st["err_bound"], st["exact_passes"], st["kernel_ms"],
+              flush=True)
+        assert got == exact and st["exact"] == 1
+        assert abs(st["estimate"] - exact) <= st["err_bound"]
+    plain, st = P.perm_sparse_ex(ccs, exact=False)
+    assert st["exact"] == -1 and abs(plain - exact) <= 1e-9 * exact
+
+
+def test_exact_passes_and_option_errors(P, oracle_mod):
+    """One, two and three forced passes give the same exact count; exact
+    mode is refused for real values when required."""
+    O = oracle_mod
+    ccs = W.single_01(22, 0.3, 4)
+    exact = O.perm_int(ccs)
+    for k in (1, 2, 3):
+        got, st = P.perm_sparse_ex(ccs, exact_passes=k)
+        assert got == exact and st["exact_passes"] == k and st["exact"] == 1
+    with pytest.raises(P.PermError) as e:
+        P.perm_sparse_ex(W.single_real(12, 0.3, 1), exact=True)
+    assert e.value.status == P.PERM_EINVAL
