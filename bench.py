@@ -83,12 +83,10 @@ def cpu_baseline(ccs, seconds_target=20.0, one_core_seconds=6.0, int_seconds=8.0
 
 def batch_bench(seed=1, count=2000, reps=3, sequential=True, opts=None):
     """The batch workload (2000 matrices, n ~ U{16..30}, density ~ U[0.15, 0.40],
-    U(-1,1) values), host preparation included, in the launch forms of
-    perm_batch: one wave per work item on the class streams, and the
-    persistent instances captured in one graph (captured on the warm-up call,
-    relaunched after), against one matrix per launch, synchronised after
-    each, with the same kernels.  `opts` (perm_batch keywords, e.g. from
-    perm_batch_autotune) apply to both batched forms."""
+    U(-1,1) values), host preparation included: perm_batch with one wave per
+    work item, each kernel instance on its class stream, against one matrix
+    per launch, synchronised after each, with the same kernels.  `opts`
+    (perm_batch keywords, e.g. from perm_batch_autotune) apply to both."""
     import paper_2501_15126_amd.perm as P
     from paper_2501_15126_amd import workloads as W
     mats = W.batch(seed, count)
@@ -96,7 +94,7 @@ def batch_bench(seed=1, count=2000, reps=3, sequential=True, opts=None):
     opts.pop("batch_mode", None)
 
     def best_of(mode):
-        P.perm_batch(mats, batch_mode=mode, **opts)  # warm-up: device buffers, graph capture
+        P.perm_batch(mats, batch_mode=mode, **opts)  # warm-up: device buffers
         best = None
         for _ in range(reps):
             t0 = time.perf_counter()
@@ -105,12 +103,7 @@ def batch_bench(seed=1, count=2000, reps=3, sequential=True, opts=None):
             best = (dt, st, out) if best is None or dt < best[0] else best
         return best
 
-    forms = {}
-    for mode in ("streams", "graph"):
-        dt, st, out = best_of(mode)
-        forms[mode] = (dt, st, out)
-    dt, st, out = min(forms.values(), key=lambda t: t[0])
-    best_mode = min(forms, key=lambda m: forms[m][0])
+    dt, st, out = best_of("streams")
 
     def roof(st):
         ks = st["kernel_ms"] / 1e3
@@ -120,16 +113,14 @@ def batch_bench(seed=1, count=2000, reps=3, sequential=True, opts=None):
 
     res = {"workload": "%d sparse real matrices, n ~ U{16..30}, density ~ U[0.15,0.40], U(-1,1), seed %d"
                        % (count, seed),
-           "permanents_per_s": count / dt, "wall_ms": dt * 1e3, "kernel_ms": st["kernel_ms"], "form": best_mode,
+           "permanents_per_s": count / dt, "wall_ms": dt * 1e3, "kernel_ms": st["kernel_ms"],
+           "form": "one launch per kernel instance, instances on class streams",
            "options": opts,
            "prep_ms": st["prep_ms"], "gray_steps": st["steps"], "gray_steps_per_s": st["steps"] / dt,
            "structurally_singular": st["singular"],
            # the batch kernels' own FP64 work (counted exactly per chunk from
            # their code) over the device time of the launches
-           "roofline": roof(st),
-           "forms": {m: {"permanents_per_s": count / f[0], "wall_ms": f[0] * 1e3, "kernel_ms": f[1]["kernel_ms"],
-                         "graph_captures": f[1]["graph_captures"]} for m, f in forms.items()},
-           "forms_bitwise_equal": bool(np.array_equal(forms["streams"][2], forms["graph"][2]))}
+           "roofline": roof(st)}
     if sequential:
         t0 = time.perf_counter()
         out_seq, st_seq = P.perm_batch_ex(mats, batch_mode="sequential", **opts)
@@ -200,6 +191,7 @@ def serving_bench(duration_s=60.0, rate_hz=200.0, seed=1, compare_fifo=True, rou
         return lat, done[-1] - t0
 
     lat, span, st = run_server()
+    print("bench: server run done (%d requests), sequential baseline next" % len(reqs), file=sys.stderr, flush=True)
     out = {"workload": "Poisson %.0f req/s for %.0f s, n ~ U{12..36}, density ~ U[0.10,0.35], 70%% 0/1 else U(0,1), "
                        "seed %d" % (rate_hz, duration_s, seed),
            "requests": len(reqs), "offered_gray_steps_per_s": steps / duration_s,
@@ -266,6 +258,18 @@ def er_grid_bench(ns, variants, seed=1, ps=None):
             print("grid cell n=%d p=%.1f %s: %.3f s kernel" % (n, p, var, ks), file=sys.stderr, flush=True)
             rows.append(row)
     return rows
+
+
+def oracle_value(workload, seed):
+    """The oracle's exact count for this workload and seed, stored by
+    tests/golden/make_golden.py (which calls only the oracle); None if absent."""
+    path = os.path.join(ROOT, "tests", "golden", "full_size.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get("%s:%d" % (workload, seed))
+    except OSError:
+        return None
+    return rec.get("perm_exact") if rec else None
 
 
 def measured_traffic(src):
@@ -401,8 +405,10 @@ def main():
                 "exact": st["exact"], "exact_passes": st["exact_passes"], "err_bound": st["err_bound"],
                 "estimate": st["estimate"], "skipped_fraction": 1.0 - eval_steps / steps_per_perm}
 
-    # ---- headline: every Gray-code term evaluated (no pruning) ----
-    opts, tune = tuned(mode=args.mode, zero_skip=False)
+    # ---- headline: every Gray-code term evaluated (no pruning), accumulated
+    # in FP64 as the paper does (the exact mode's residue certificate is a
+    # separate leg below) ----
+    opts, tune = tuned(mode=args.mode, zero_skip=False, exact=False)
     chosen = {k: opts.get(k) for k in ("mode", "chunk_log2", "unroll_log2", "block", "waves_per_simd",
                                           "block_queue", "cold_tier") if k in opts}
     elapsed, kernel_ms, evaluated, values, st, first = timed_calls(opts, args.steps, args.warmup)
@@ -428,7 +434,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "single sparse 0/1 matrix n=%d, permutation pattern OR Bernoulli(0.10), seed %d, "
-                               "all 2^%d Gray-code terms evaluated, exact integer count" % (n, args.seed, n - 1),
+                               "all 2^%d Gray-code terms evaluated, FP64 accumulation" % (n, args.seed, n - 1),
                    "n": n, "nnz": len(ccs[2]), "mode": args.mode,
                    "options": "given" if args.opts else ("library defaults" if args.no_tune else
                                                          "perm_autotune, searched before the timed region"),
@@ -441,6 +447,19 @@ def main():
     }
     if tune is not None:
         out["autotune"] = tune
+    ref = oracle_value(args.workload, args.seed)
+    if ref is not None:
+        out["oracle_integer"] = ref
+        out["matches_oracle_integer"] = values[-1] == float(int(ref))
+    # ---- the same, with the exact mode's certificate (residue modulo a
+    # prime and a rigorous FP64 error bound), same launch options ----
+    xopts = dict(opts, exact="auto")
+    xel, xk, xev, xvals, xst, xfirst = timed_calls(xopts, max(2, args.steps // 4), 1)
+    xkern = kernel_record(xst, xk, xev, xfirst)
+    out["exact_all_terms"] = {
+        "ms_per_permanent": xel / len(xk) * 1e3, "gray_steps_per_s": steps_per_perm * len(xk) / xel,
+        "kernel": xkern, "permanent": xvals[-1], "certified": xst["exact"] == 1,
+        "note": "every term evaluated, plus the residue and error-bound operations that certify the integer"}
     # ---- the same permanent with exact zero-aware pruning (beyond the paper) ----
     if args.zero_skip != "off" and not args.no_pruned:
         popts, ptune = tuned(mode=args.mode, zero_skip={"auto": "auto", "on": True}[args.zero_skip])
@@ -468,9 +487,15 @@ def main():
             bopts, btune = P.perm_batch_autotune(W2.batch(1, 2000))
             print("bench: batch autotuned: %s" % bopts, file=sys.stderr, flush=True)
         out["batch"] = batch_bench(opts={k: bopts[k] for k in ("block", "batch_kappa_shift")} if bopts else None)
+        print("bench: batch done, %.1f permanents/s" % out["batch"]["permanents_per_s"], file=sys.stderr, flush=True)
     if args.serving_seconds > 0:
+        print("bench: serving run, %.0f s (then the sequential baseline on the same trace)" % args.serving_seconds,
+              file=sys.stderr, flush=True)
         out["serving"] = serving_bench(args.serving_seconds, rate_hz=args.serving_rate)
+        print("bench: serving done, p50 %.2f ms p99 %.2f ms" % (out["serving"]["p50_ms"], out["serving"]["p99_ms"]),
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
+        print("bench: CPU oracle samples", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(ccs)
     print(json.dumps(out), flush=True)
 

@@ -92,10 +92,9 @@ typedef struct {
     int32_t batch_mode;    /* perm_batch: 0 = one launch per kernel instance, one wave per
                               work item (64 chunks of one matrix), each instance on its own
                               class stream so instances overlap (default); 1 = persistent
-                              instances (a grid of resident waves taking work items from an
-                              atomic counter) on those streams, captured in one graph that is
-                              launched again, without a new capture, for later batches with
-                              the same launch layout; 2 = one matrix per launch, synchronised
+                              instances captured in one graph: switched off, PERM_EINVAL
+                              (a GPU test of it stopped making progress, cause not found);
+                              2 = one matrix per launch, synchronised
                               after each (the sequential baseline); 3 = the launches of 0 on
                               one stream.  perm_batch also reads `block` (64, 128 or 256
                               threads per workgroup; 0 = 256) */
@@ -227,8 +226,8 @@ typedef struct {
                                   structurally singular) */
     int32_t exact_uncertified; /* exact-mode matrices left at the FP64 estimate */
     int32_t passes;        /* kernel passes run (exact mode: one per prime needed) */
-    int32_t graph_captures; /* graph captures of the process so far (batch_mode 1 captures
-                              once per launch layout and relaunches the graph after) */
+    int32_t graph_captures; /* graph captures of the process so far (0 while batch_mode 1
+                              is switched off) */
 } perm_batch_stats;
 
 /* perm_batch with statistics (st may be NULL). */
@@ -267,9 +266,8 @@ typedef struct {
  * benchmarks; here the launch shape and the split are chosen by timing. */
 perm_status perm_autotune(const perm_csc *a, const perm_opts *opts, perm_opts *best, perm_tune_stats *st);
 
-/* Picks perm_batch options for a batch by running it whole: the launch form
- * (batch_mode 0, one wave per item on the class streams, or 1, persistent
- * instances in one captured graph), the threads per workgroup (64, 128, 256)
+/* Picks perm_batch options for a batch by running it whole (batch_mode 0, or
+ * 3 if given): the threads per workgroup (64, 128, 256)
  * and then batch_kappa_shift (+-1, +-2), each kept if at least 2 % faster
  * in device time (best of 3 runs).  Results are bitwise independent of
  * batch_mode and block; batch_kappa_shift changes the chunking, so results
