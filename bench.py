@@ -306,6 +306,10 @@ def main():
                          "profiling the kernel an earlier run chose")
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the run of the same permanent with exact zero-aware pruning")
+    ap.add_argument("--no-exact-leg", action="store_true",
+                    help="skip the all-terms run with the exact mode's certificate")
+    ap.add_argument("--pruned-only", action="store_true",
+                    help="run only the pruned permanent (for profiling its kernel)")
     ap.add_argument("--serving-seconds", type=float, default=60.0,
                     help="length of the Poisson serving run (0 skips it)")
     ap.add_argument("--serving-rate", type=float, default=200.0,
@@ -405,6 +409,32 @@ def main():
                 "exact": st["exact"], "exact_passes": st["exact_passes"], "err_bound": st["err_bound"],
                 "estimate": st["estimate"], "skipped_fraction": 1.0 - eval_steps / steps_per_perm}
 
+    def pruned_leg():
+        """The same permanent with exact zero-aware pruning (beyond the paper):
+        permanents/s, with the product's default exact certificate."""
+        popts, ptune = tuned(mode=args.mode, zero_skip={"auto": "auto", "on": True}[args.zero_skip])
+        pel, pk, pev, pvals, pst, pfirst = timed_calls(popts, max(args.steps, 20), args.warmup)
+        pkern = kernel_record(pst, pk, pev, pfirst)
+        pflops = pst["flops_per_step"] * pkern["evaluated_steps_per_launch_set"]
+        return {
+            "permanents_per_s": len(pk) / pel, "ms_per_permanent": pel / len(pk) * 1e3,
+            "evaluated_steps_per_s": pkern["evaluated_steps_per_s"],
+            "note": "most of the 2^(n-1) terms are exactly zero and skipped; evaluated_steps_per_s counts the "
+                    "lane-steps the kernel evaluated",
+            "kernel": pkern, "permanent": pvals[-1], "certified": pst["exact"] == 1,
+            "roofline": {"bound": "alu", "achieved": pflops / (pkern["avg_ms"] / 1e3) / 1e12,
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": pflops / (pkern["avg_ms"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+                         "traffic": measured_traffic(P.perm_codegen(
+                             ccs, **dict(popts, waves_per_simd=pst["waves_hint"] or -1)))},
+            "options": {k: popts.get(k) for k in ("mode", "chunk_log2", "unroll_log2", "block", "waves_per_simd",
+                                                   "block_queue")},
+            "autotune": ptune}
+
+    if args.pruned_only:
+        print(json.dumps({"pruned": pruned_leg()}), flush=True)
+        return
+
     # ---- headline: every Gray-code term evaluated (no pruning), accumulated
     # in FP64 as the paper does (the exact mode's residue certificate is a
     # separate leg below) ----
@@ -453,33 +483,16 @@ def main():
         out["matches_oracle_integer"] = values[-1] == float(int(ref))
     # ---- the same, with the exact mode's certificate (residue modulo a
     # prime and a rigorous FP64 error bound), same launch options ----
-    xopts = dict(opts, exact="auto")
-    xel, xk, xev, xvals, xst, xfirst = timed_calls(xopts, max(2, args.steps // 4), 1)
-    xkern = kernel_record(xst, xk, xev, xfirst)
-    out["exact_all_terms"] = {
-        "ms_per_permanent": xel / len(xk) * 1e3, "gray_steps_per_s": steps_per_perm * len(xk) / xel,
-        "kernel": xkern, "permanent": xvals[-1], "certified": xst["exact"] == 1,
-        "note": "every term evaluated, plus the residue and error-bound operations that certify the integer"}
-    # ---- the same permanent with exact zero-aware pruning (beyond the paper) ----
+    if not args.no_exact_leg:
+        xopts = dict(opts, exact="auto")
+        xel, xk, xev, xvals, xst, xfirst = timed_calls(xopts, max(2, args.steps // 4), 1)
+        xkern = kernel_record(xst, xk, xev, xfirst)
+        out["exact_all_terms"] = {
+            "ms_per_permanent": xel / len(xk) * 1e3, "gray_steps_per_s": steps_per_perm * len(xk) / xel,
+            "kernel": xkern, "permanent": xvals[-1], "certified": xst["exact"] == 1,
+            "note": "every term evaluated, plus the residue and error-bound operations that certify the integer"}
     if args.zero_skip != "off" and not args.no_pruned:
-        popts, ptune = tuned(mode=args.mode, zero_skip={"auto": "auto", "on": True}[args.zero_skip])
-        pel, pk, pev, pvals, pst, pfirst = timed_calls(popts, max(args.steps, 20), args.warmup)
-        pkern = kernel_record(pst, pk, pev, pfirst)
-        pflops = pst["flops_per_step"] * pkern["evaluated_steps_per_launch_set"]
-        out["pruned"] = {
-            "permanents_per_s": len(pk) / pel, "ms_per_permanent": pel / len(pk) * 1e3,
-            "step_equivalent_per_s": steps_per_perm * len(pk) / pel,
-            "note": "step_equivalent_per_s counts all 2^(n-1) terms, most of them skipped as exactly zero; "
-                    "evaluated_steps_per_s counts the terms the kernel evaluated",
-            "kernel": pkern, "permanent": pvals[-1], "same_as_headline": pvals[-1] == values[-1],
-            "roofline": {"bound": "alu", "achieved": pflops / (pkern["avg_ms"] / 1e3) / 1e12,
-                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": pflops / (pkern["avg_ms"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
-                         "traffic": measured_traffic(P.perm_codegen(
-                             ccs, **dict(popts, waves_per_simd=pst["waves_hint"] or -1)))},
-            "options": {k: popts.get(k) for k in ("chunk_log2", "unroll_log2", "block", "waves_per_simd",
-                                                   "block_queue")},
-            "autotune": ptune}
+        out["pruned"] = pruned_leg()
     if not args.no_batch:
         bopts = None
         if not args.no_tune:

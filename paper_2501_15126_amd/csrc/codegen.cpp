@@ -74,6 +74,14 @@ struct Gen {
     // (exact mode: then R_{qtop+1}, the residue of S_{qtop+1})
     int qfields() const { return (int)qrows.size() + 2 + (p.exact ? 1 : 0); }
 
+    // Exact mode with pruned blocks: the walk between evaluated blocks keeps
+    // only the FP64 products S_l (its zero tests need nothing else); the
+    // residues R_l are formed again from x where a term is evaluated (at an
+    // evaluated or queued block, and under a wave-uniform branch for a
+    // nonzero walk term).  walk_s_only marks code emitted for the walk.
+    bool lazy_r = false;
+    bool walk_s_only = false;
+
     std::string fresh() { return "t" + std::to_string(tmp++); }
     std::string xname(int r) const { return "x" + std::to_string(r); }
     std::string cold_addr(int r) const {
@@ -192,6 +200,7 @@ struct Gen {
             os << I << "S" << l << " = " << pl;
             if (!top) os << " * S" << l + 1;
             os << ";\n";
+            if (walk_s_only) return;  // residues are formed again where a term is evaluated
             const std::string r = residue_chain(qs, 0, top ? "" : "R" + std::to_string(l + 1), I);
             os << I << "R" << l << " = " << r << ";\n";
             return;
@@ -200,6 +209,15 @@ struct Gen {
         if (l + 1 < p.nlevels) v.push_back("S" + std::to_string(l + 1));
         std::string prod = product(v, I);
         os << I << "S" << l << " = " << prod << ";\n";
+    }
+
+    // R_l for l = L-1 down to lo, from the current x (exact mode).
+    void recompute_residues(int lo, std::map<int, std::string> &cur, const char *I) {
+        for (int l = p.nlevels - 1; l >= lo; --l) {
+            const std::vector<std::string> qs = part_products(l, cur, I);
+            const std::string r = residue_chain(qs, 0, l + 1 < p.nlevels ? "R" + std::to_string(l + 1) : "", I);
+            os << I << "R" << l << " = " << r << ";\n";
+        }
     }
 
     // One Gray step: flip column j with the given direction, refresh the
@@ -221,6 +239,33 @@ struct Gen {
     // acc += term_sign * (product of level 0) * S_1   (one FMA)
     void accumulate(int term_sign, int acc, std::map<int, std::string> &cur, const char *I,
                     const char *weight = nullptr) {
+        if (p.pair0) {
+            // the pair (-1)^i S_1 (P(x) - P(x + a)) over column 0's rows: one
+            // row r gives -a_r; two rows r, s give -(a_r x_s + a_s x_r + a_r a_s)
+            const Ccs &B = p.B;
+            const int q0 = B.colptr[0];
+            std::string d;
+            if (B.colptr[1] - q0 == 1) {
+                d = "(" + lit(B.val[q0]) + ")";
+            } else {
+                // r in the inner FMA, t in the outer (the plan puts there the
+                // row that more often changes)
+                const int r = p.pair_r, t = p.pair_s;
+                const double ar = B.val[B.rowidx[q0] == r ? q0 : q0 + 1];
+                const double at = B.val[B.rowidx[q0] == t ? q0 : q0 + 1];
+                d = fresh();
+                os << I << "const double " << d << " = fma(" << lit(ar) << ", " << xname(t) << ", fma(" << lit(at)
+                   << ", " << xname(r) << ", " << lit(ar * at) << "));\n";
+            }
+            if (weight) {
+                const std::string dw = fresh();
+                os << I << "const double " << dw << " = " << d << " * " << weight << ";\n";
+                d = dw;
+            }
+            // term_sign * (-d) * S_1
+            os << I << "acc" << acc << " = fma(" << (term_sign < 0 ? "" : "-") << d << ", S1, acc" << acc << ");\n";
+            return;
+        }
         if (p.exact) {
             // the term is pr * last (exact inside the FMA); its residue is the
             // first sub-product times the residue of the rest; A (the error
@@ -228,6 +273,22 @@ struct Gen {
             const std::vector<std::string> qs = part_products(0, cur, I, weight);
             const char *sg = term_sign < 0 ? "-" : "";
             std::string pr, last, rest;
+            if (p.nlevels > 1 && walk_s_only) {
+                // a walk term: its residue only where some lane's term is
+                // nonzero, from residues formed again from x (reduced at once,
+                // so any number of walk terms keeps racc exact)
+                pr = product(qs, I);
+                os << I << "acc" << acc << " = fma(" << sg << pr << ", S1, acc" << acc << ");\n";
+                os << I << "accA = fma(fabs(" << pr << "), fabs(S1), accA);\n";
+                os << I << "if (__any(" << pr << " != 0.0 && S1 != 0.0)) {\n";
+                const std::string in2 = std::string(I) + "  ";
+                recompute_residues(1, cur, in2.c_str());
+                rest = residue_chain(qs, 1, "R1", in2.c_str());
+                os << in2 << "racc = fma(" << sg << qs[0] << ", " << rest << ", racc);\n";
+                os << in2 << "racc = fma(-rint(racc * pinv), pmod, racc);\n";
+                os << I << "}\n";
+                return;
+            }
             if (p.nlevels > 1) {
                 pr = product(qs, I);
                 last = "S1";
@@ -318,8 +379,11 @@ struct Gen {
     // Static block of steps i = 1 .. 2^u - 1 inside a 2^(u+1)-aligned pair of
     // blocks; `second` selects the second block (where the step i = 2^(u-1)
     // excludes instead of includes).
+    // (Column-0 pairing: i counts paired steps and step i flips column
+    // ctz(i) + 1, with Theorem 1's direction taken from i.)
     void static_block(bool second, const char *ind) {
         const int U = 1 << p.u;
+        const int c0 = p.pair0 ? 1 : 0;
         for (int i = 1; i < U; ++i) {
             const int j = __builtin_ctz(i);
             bool neg;
@@ -327,7 +391,7 @@ struct Gen {
                 neg = (i >> (j + 1)) & 1;  // Theorem 1 with the chunk-local index
             else
                 neg = second;              // bit u of the local index
-            step(j, neg ? Sign::Minus : Sign::Plus, (i & 1) ? -1 : 1, (i >> 1) & 1, ind);
+            step(j + c0, neg ? Sign::Minus : Sign::Plus, (i & 1) ? -1 : 1, (i >> 1) & 1, ind);
         }
         if (U > 1) reduce_racc(ind);
     }
@@ -337,8 +401,15 @@ struct Gen {
         const int n = p.n, k = p.k, L = p.nlevels;
         const int kappa = p.kappa, u = p.u, U = 1 << u;
         const uint64_t DELTA = 1ull << kappa;
+        // the walk: local steps of a chunk, its length and the column offset
+        // (column-0 pairing: paired steps flipping columns 1 ..)
+        const int c0 = p.pair0 ? 1 : 0;
+        const int kw = kappa - c0;
+        const uint64_t DW = DELTA >> c0;
+        const unsigned evm = 1u << c0;  // Gray terms per walked step
         os << "// generated by libperm_mi355x: n=" << n << " nnz=" << p.nnz << " k=" << k << " c=" << p.c
-           << " levels=" << L << " kappa=" << kappa << " u=" << u << " block=" << p.block << "\n";
+           << " levels=" << L << " kappa=" << kappa << " u=" << u << " block=" << p.block
+           << (p.pair0 ? " pair0" : "") << "\n";
         os << "typedef unsigned long long u64;\n"
               "typedef unsigned int u32;\n"
               "struct dd { double h, l; };\n"
@@ -352,7 +423,7 @@ struct Gen {
         // of this lane live at xg[(r - k) * xs + lid].
         // `ev` counts the terms whose product this lane actually evaluates
         // (skipped ones excluded), for the device-work statistics.
-        if (kappa >= 1 && u + 1 <= kappa - 1) build_dyn_table(u + 1, kappa - 1);
+        if (kw >= 1 && u + 1 <= kw - 1) build_dyn_table(u + 1 + c0, kappa - 1);
         // LDS tier: the cold rows of a workgroup's lanes, [row][lane], so a
         // wave's accesses to one row are 64 consecutive doubles
         if (p.cold_lds) os << "__shared__ double xl[" << (n - k) * p.block << "];\n";
@@ -430,7 +501,7 @@ struct Gen {
               "                                        const double pmod, const double pinv) {\n";
         if (!p.exact) os << "  (void)xo; (void)pmod; (void)pinv;\n";
         if (!use_queue) os << "  (void)act; (void)qw; (void)qc;\n";
-        os << "  ev = 1u;\n";
+        os << "  ev = " << evm << "u;\n";
         os << "  const u64 g0 = m << "
            << kappa
            << ";\n"
@@ -509,6 +580,7 @@ struct Gen {
             int block_top = 0;
             for (int j = 0; j <= u; ++j) block_top = std::max(block_top, p.col_top[j]);
             const bool skip_block = p.zero_skip && u >= 1 && block_top + 1 <= L - 1;
+            lazy_r = p.exact && skip_block;
             // Larger intervals (zero-aware, exact): after position pos (a
             // multiple of 2^v, v >= u + 2) the next 2^v - 1 steps flip only
             // columns < v, so the rows on levels above those columns' levels
@@ -553,6 +625,14 @@ struct Gen {
                         os << ind << "const u64 bal = __ballot(need);\n";
                         os << ind << "const u32 nk = (u32)__popcll(bal);\n";
                         os << ind << "if (nk == 0u || qc + nk <= " << QS << "u) {\n";
+                        if (lazy_r) {
+                            // the queued start state carries the residue of the
+                            // rows above the block's levels
+                            std::map<int, std::string> rc;
+                            os << in2 << "if (nk != 0u) {\n";
+                            recompute_residues(block_top + 1, rc, (in2 + "  ").c_str());
+                            os << in2 << "}\n";
+                        }
                         os << in2 << "if (need) {\n";
                         os << in3 << "const u32 sl = qc + __builtin_amdgcn_mbcnt_hi((u32)(bal >> 32), "
                                      "__builtin_amdgcn_mbcnt_lo((u32)bal, 0u));\n";
@@ -572,6 +652,7 @@ struct Gen {
                         os << ind << "if (__all(S" << block_top + 1 << " == 0.0)) {\n";
                     }
                     std::map<int, std::string> cur;
+                    walk_s_only = lazy_r;
                     if (u + 1 == kappa) {
                         update(u, Sign::Lane, cur, in2.c_str());
                     } else {
@@ -579,16 +660,22 @@ struct Gen {
                         update(u, Sign::Uniform, cur, in2.c_str());
                     }
                     for (int l = block_top; l >= 1; --l) refresh_level(l, cur, in2.c_str());
+                    walk_s_only = false;
                     os << ind << "} else {\n";
                 }
                 const char *bi = skip_block ? in2.c_str() : ind;
-                os << bi << "ev += " << (2 * U - 1) << "u;\n";
+                if (lazy_r) {
+                    // evaluated in place: the residues of every level from x
+                    std::map<int, std::string> rc;
+                    recompute_residues(1, rc, bi);
+                }
+                os << bi << "ev += " << evm * (2 * U - 1) << "u;\n";
                 static_block(false, bi);
-                if (u + 1 == kappa) {
-                    step(u, Sign::Lane, term_u, 0, bi);
+                if (u + 1 == kw) {
+                    step(u + c0, Sign::Lane, term_u, 0, bi);
                 } else {
                     os << bi << "{\n" << bi << "  const bool neg = (" << posv << " >> " << (u + 1) << ") & 1u;\n";
-                    step(u, Sign::Uniform, term_u, 0, (std::string(bi) + "  ").c_str());
+                    step(u + c0, Sign::Uniform, term_u, 0, (std::string(bi) + "  ").c_str());
                     os << bi << "}\n";
                 }
                 static_block(true, bi);
@@ -605,26 +692,29 @@ struct Gen {
                 std::string in2 = std::string(ind) + "  ";
                 const char *I2 = in2.c_str();
                 os << ind << "{\n";
-                os << I2 << "const double w = (" << ellv << " < " << DELTA << "u) ? 1.0 : 0.0;\n";
-                os << I2 << "const int jj = __builtin_ctz(" << ellv << ");\n";
-                os << I2 << "const double sgu = ((" << ellv << " >> (jj + 1)) & 1u) ? -1.0 : 1.0;\n";
+                os << I2 << "const double w = (" << ellv << " < " << DW << "u) ? 1.0 : 0.0;\n";
+                os << I2 << "const int jr = __builtin_ctz(" << ellv << ");\n";
+                os << I2 << "const int jj = jr + " << c0 << ";\n";
+                os << I2 << "const double sgu = ((" << ellv << " >> (jr + 1)) & 1u) ? -1.0 : 1.0;\n";
                 os << I2 << "const double sg = (jj == " << kappa - 1 << ") ? lsgn : sgu;\n";
                 std::map<int, std::string> cur;
+                walk_s_only = lazy_r;
                 const int top_max = dyn_flip("jj", "sg", cur, I2);
                 for (int l = top_max; l >= 1; --l) refresh_level(l, cur, I2);
                 accumulate(1, 1, cur, I2, "w");
+                walk_s_only = false;
                 os << ind << "}\n";
             };
             if (!tree) {
                 os << "#pragma clang loop unroll(disable)\n";
-                os << "  for (u32 base = 0; base < " << DELTA << "u; base += " << 2 * U << "u) {\n";
+                os << "  for (u32 base = 0; base < " << DW << "u; base += " << 2 * U << "u) {\n";
                 block_pair("base", "    ");
-                if (u + 1 <= kappa - 1) {
+                if (u + 1 <= kw - 1) {
                     os << "    const u32 ell = base + " << 2 * U << "u;\n";
                     dynamic_step("ell", "    ");
                 }
                 os << "  }\n";
-                os << "  ev += " << (DELTA / (2 * U) - 1) << "u;  // the dynamic steps\n";
+                os << "  ev += " << evm * (DW / (2 * U) - 1) << "u;  // the dynamic steps\n";
             } else {
                 // pos: the local index whose term was added last (a multiple of 2^(u+1))
                 os << "  u32 pos = 0u;\n";

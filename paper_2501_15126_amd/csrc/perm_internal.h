@@ -76,6 +76,16 @@ struct Plan {
     int queue_slots = 0;                // per-wave queue of partly needed blocks: slots,
                                         // 0 = the most that fit, -1 = none
     bool zero_skip = true;              // skip chunks / blocks whose terms are exactly 0
+    // Column-0 pairing: the two terms of Gray indices 2i and 2i+1 (which
+    // differ only in column 0) are summed by one expression, (-1)^i S_1
+    // (P(x) - P(x + a)), P the product of column 0's rows (level 0) and x
+    // kept without column 0; the walk then flips columns 1..n-2 only, over
+    // half as many steps.  Set for AUTO all-terms FP64 kernels whose column 0
+    // has one or two entries; kappa and u then count these paired steps:
+    // a chunk still covers 2^kappa Gray indices, walked in 2^(kappa-1) steps,
+    // and a static block is 2^u paired steps.
+    bool pair0 = false;
+    int pair_r = -1, pair_s = -1;       // column 0's rows: bracket fma(a_r, x_s, fma(a_s, x_r, a_r a_s))
     // Exact mode (integer-valued matrices): B holds 2a, so x is y = 2x, an
     // integer; the kernel also keeps the term sum modulo a prime and the two
     // sums of its error bound (exact.h).  Each level's product is formed from
@@ -83,12 +93,16 @@ struct Plan {
     bool exact = false;
     std::vector<std::vector<std::vector<int>>> level_parts;
     double base_x_hi[PERM_MAX_N];       // x_r at Gray index 0 (Alg. 1's initialisation)
+    int tau_base = 0;                   // VGPRs besides x in Alg. 5's thread-count model
     double ops_per_step = 0, flops_per_step = 0;
     double exact_ops_per_step = 0;      // of ops_per_step: residue and error-bound operations
     std::vector<double> ops_of_col;     // FP64 VALU ops of one step flipping column j
 };
 
-perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *err);
+// tau_base: VGPRs a lane needs besides its register rows of x in the thread
+// count model of Alg. 5 (0 = the built-in estimate; the runtime passes the
+// count measured from a compiled HYBRID kernel).
+perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *err, int tau_base = 0);
 
 // ---- runtime.cpp -----------------------------------------------------------
 // Sets the calling thread's perm_last_error() text.

@@ -118,8 +118,11 @@ namespace {
 
 // VGPRs a lane needs besides x and the cached products: two accumulators,
 // the lane sign, chunk index, temporaries of the product trees and the
-// reduction.  Used only by the plan's budget (the real count comes from the
-// compiled code object).
+// reduction.  The AUTO level budget uses it as is; Alg. 5's thread-count
+// model starts from it and is then given the count measured from the
+// compiled HYBRID kernel (its VGPRs minus two per register row: 74..132 on
+// n = 24..44 matrices, far above this estimate, because the cold rows'
+// loaded values and the product tree's temporaries stay in registers).
 constexpr int kBaseVgprs = 28;
 // Exact mode's further registers in the plan's budget: the residue and |term|
 // accumulators and the prime with its reciprocal.  (The compiler's count did
@@ -156,7 +159,7 @@ bool integer_valued(const Ccs &a) {
 
 }  // namespace
 
-perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *err) {
+perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *err, int tau_base) {
     char buf[256];
     const int n = a.n;
     p->n = n;
@@ -205,7 +208,8 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
 
     const double gr = o.gr_ratio > 0 ? o.gr_ratio : 16.0;
     const int budget = o.vgpr_budget > 0 ? o.vgpr_budget : 128;
-    std::vector<double> tau = tau_model(n, kBaseVgprs);
+    p->tau_base = tau_base > 0 ? tau_base : kBaseVgprs;
+    std::vector<double> tau = tau_model(n, p->tau_base);
     int k5 = n, c5 = n;
     partitioning(B, tau.data(), gr, &k5, &c5);
 
@@ -374,6 +378,34 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         *err = "block must be a multiple of 64 and at most 1024";
         return PERM_EINVAL;
     }
+    // column-0 pairing (AUTO, every term evaluated, FP64): level 0 is then
+    // exactly column 0's rows (the rows first touched by column 0)
+    p->pair0 = false;
+    {
+        const int d0 = n >= 2 ? B.colptr[1] - B.colptr[0] : 0;
+        bool ok = o.mode == PERM_MODE_AUTO && !zs && !ex && !p->cold && p->nlevels >= 2 && p->kappa >= 3 &&
+                  (d0 == 1 || d0 == 2);
+        for (int r = 0; r < n && ok; ++r)
+            if ((p->row_level[r] == 0) != (first[r] == 0)) ok = false;
+        if (ok) {
+            p->pair0 = true;
+            p->u = std::min(p->u, p->kappa - 2);  // a static block of paired steps fits the chunk's half
+            // two entries: the row that lower (more often flipped) columns
+            // touch goes in the outer FMA of the bracket, so that a flip of
+            // it alone costs one operation
+            p->pair_r = B.rowidx[B.colptr[0]];
+            p->pair_s = d0 == 2 ? B.rowidx[B.colptr[0] + 1] : -1;
+            if (d0 == 2) {
+                int fr = n, fs = n;
+                for (int j = n - 2; j >= 1; --j)
+                    for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) {
+                        if (B.rowidx[q] == p->pair_r) fr = j;
+                        if (B.rowidx[q] == p->pair_s) fs = j;
+                    }
+                if (fr < fs) std::swap(p->pair_r, p->pair_s);
+            }
+        }
+    }
 
     // ---- FP64 operations per step (matches what generate_source emits) ----
     std::vector<int> level_size(p->nlevels, 0);
@@ -415,6 +447,46 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
     p->exact_ops_per_step = exact_ops / steps;
     // the accumulate FMA replaces a multiply and an add of Alg. 1 (counts 2)
     p->flops_per_step = (ops + (steps - 1.0)) / steps;
+    if (p->pair0) {
+        // Paired walk: column 0 never flips; a step flipping column j >= 1
+        // updates its rows, refreshes the levels above 0 as before, forms
+        // P(x) - P(x + a) of level 0 only when the column touches level 0
+        // (else the compiler reuses it: two FMAs for two rows, a literal for
+        // one) and adds the pair with one FMA.  Each FMA of the two-row
+        // difference and the accumulate does a multiply and an add the sum
+        // needs (2 flops each).
+        const int d0 = B.colptr[1] - B.colptr[0];
+        double pops = 0.0, pfl = 0.0;
+        for (int j = 1; j < n - 1; ++j) {
+            const int t = p->col_top[j];
+            std::fill(touched.begin(), touched.end(), 0);
+            for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) touched[p->row_level[B.rowidx[q]]] = 1;
+            double oj = B.colptr[j + 1] - B.colptr[j];
+            for (int l = 1; l <= t; ++l)
+                if (touched[l]) oj += std::max(0, level_size[l] - 1);
+            for (int l = 1; l <= t; ++l)
+                if (l < L - 1) oj += 1;
+            // the bracket fma(a_r, x_s, fma(a_s, x_r, a_r a_s)): the inner
+            // FMA only when x_r changed, the outer when either did
+            double bops = 0.0;
+            if (d0 == 2) {
+                bool tr = false, ts = false;
+                for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) {
+                    tr = tr || B.rowidx[q] == p->pair_r;
+                    ts = ts || B.rowidx[q] == p->pair_s;
+                }
+                bops = tr ? 2.0 : ts ? 1.0 : 0.0;
+            }
+            oj += bops + 1.0;
+            p->ops_of_col[j] = oj;
+            const double cnt = std::ldexp(1.0, n - j - 2);
+            pops += cnt * oj;
+            pfl += cnt * (oj + 1.0 + bops);
+        }
+        p->ops_of_col[0] = 0.0;
+        p->ops_per_step = pops / steps;
+        p->flops_per_step = pfl / steps;
+    }
     return PERM_OK;
 }
 

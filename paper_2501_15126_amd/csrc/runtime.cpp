@@ -143,7 +143,7 @@ struct Prepared {
     double host_ms = 0;
 };
 
-perm_status prepare(const perm_csc *m, const perm_opts &o, Prepared *p, bool want_source) {
+perm_status prepare(const perm_csc *m, const perm_opts &o, Prepared *p, bool want_source, int tau_base = 0) {
     auto t0 = std::chrono::steady_clock::now();
     std::string err;
     perm_status s = normalize_ccs(m, &p->a, &err);
@@ -151,7 +151,7 @@ perm_status prepare(const perm_csc *m, const perm_opts &o, Prepared *p, bool wan
     p->rank = structural_rank(p->a);
     p->singular = p->rank < p->a.n;
     if (!p->singular || !want_source) {
-        s = make_plan(p->a, o, &p->plan, &err);
+        s = make_plan(p->a, o, &p->plan, &err, tau_base);
         if (s != PERM_OK) return fail(s, err);
         if (want_source && !p->singular) p->src = generate_source(p->plan);
     }
@@ -187,6 +187,37 @@ perm_status compile_prepared(Prepared *p, const perm_opts &o, CodeObject *co, st
     p->plan.waves_per_simd = q.waves_per_simd;
     p->src = std::move(src5);
     *co = std::move(c5);
+    return PERM_OK;
+}
+
+// compile_prepared, then for a HYBRID plan whose partition is not forced:
+// Alg. 5 once more with the thread-count model of the compiled kernel (its
+// VGPRs besides the register rows of x replace the estimate); a different
+// (k, c) is compiled and replaces the first.
+perm_status compile_plan(const perm_csc *m, const perm_opts &o, Prepared *p, CodeObject *co, std::string *err) {
+    perm_status s = compile_prepared(p, o, co, err);
+    if (s != PERM_OK) return s;
+    const Plan &pl = p->plan;
+    if (pl.mode != PERM_MODE_HYBRID || o.force_k > 0 || co->vgprs <= 0) return PERM_OK;
+    const int base = co->vgprs - 2 * pl.k;
+    if (base <= 0 || std::abs(base - pl.tau_base) < 8) return PERM_OK;
+    Prepared q;
+    s = prepare(m, o, &q, true, base);
+    if (s != PERM_OK) {
+        *err = "re-planning with the measured register model failed";
+        return s;
+    }
+    if (q.plan.k == pl.k && q.plan.c == pl.c) {
+        p->plan.tau_base = base;
+        return PERM_OK;
+    }
+    CodeObject c2;
+    s = compile_prepared(&q, o, &c2, err);
+    if (s != PERM_OK) return s;
+    c2.compile_ms += co->compile_ms;
+    q.host_ms += p->host_ms;
+    *p = std::move(q);
+    *co = std::move(c2);
     return PERM_OK;
 }
 
@@ -266,7 +297,7 @@ perm_status acquire_plan(const perm_csc *m, const perm_opts &o, std::shared_ptr<
         if (s != PERM_OK) return s;
         if (!cp->p.singular) {
             std::string err;
-            s = compile_prepared(&cp->p, o, &cp->co, &err);
+            s = compile_plan(m, o, &cp->p, &cp->co, &err);
             if (s != PERM_OK) return fail(s, err);
         }
         if (keyed) {
@@ -1041,12 +1072,15 @@ perm_status perm_compile_info(const perm_csc *a, const perm_opts *opts, perm_sta
     if (s != PERM_OK) return s;
     if (!st) return fail(PERM_EINVAL, "null stats");
     memset(st, 0, sizeof *st);
-    fill_plan_stats(p, st);
-    if (p.singular) return PERM_OK;
+    if (p.singular) {
+        fill_plan_stats(p, st);
+        return PERM_OK;
+    }
     CodeObject co;
     std::string err;
-    s = compile_prepared(&p, o, &co, &err);
+    s = compile_plan(a, o, &p, &co, &err);
     if (s != PERM_OK) return fail(s, err);
+    fill_plan_stats(p, st);
     st->waves_hint = p.plan.waves_per_simd;
     st->vgpr_spills = co.vgpr_spills;
     st->compile_ms = co.compile_ms;

@@ -23,6 +23,7 @@ static inline unsigned __builtin_amdgcn_mbcnt_lo(unsigned, unsigned acc) { retur
 static inline unsigned __builtin_amdgcn_mbcnt_hi(unsigned, unsigned acc) { return acc; }
 // one emulated lane is the whole "wave"
 static inline int __all(int p) { return p; }
+static inline int __any(int p) { return p; }
 using std::fma;
 using std::rint;
 using std::fabs;

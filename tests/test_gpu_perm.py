@@ -335,6 +335,40 @@ def test_n40_bench_configuration_block_partials(P, oracle_mod):
             assert abs(part - (h + l)) <= 1e-12 * (ah + al) + 1e-9, (w, b, part, h + l)
 
 
+def test_n40_all_terms_fp64_paired(P, oracle_mod):
+    """The benchmark's headline configuration: n = 40, every Gray term
+    evaluated, FP64 accumulation, terms paired over column 0.  The result
+    rounds to the stored exact count, and sampled workgroup partials (each the
+    sum over its Gray-index range) agree with the oracle on the same ranges of
+    the plan's ordered matrix."""
+    O = oracle_mod
+    g = _golden()
+    key = "n40_p0.10_01:1"
+    if key not in g:
+        pytest.skip("stored n=40 oracle value not generated")
+    exact = int(g[key]["perm_exact"])
+    ccs = W.single_01(40, 0.10, 1)
+    opts = dict(zero_skip=False, exact=False)
+    assert "pair0" in P.perm_codegen(ccs, **opts).splitlines()[0]
+    plan = P.perm_plan(ccs)
+    A = O.ccs_to_dense(ccs)
+    B = O.dense_to_ccs(A[np.ix_(plan["row_perm"], plan["col_perm"])])
+    info = P.compile_info(ccs, **opts)
+    W_ = info["block"] << info["chunk_log2"]
+    nb = info["nblocks"]
+    rng = np.random.default_rng(7)
+    blocks = sorted({0, nb - 1} | {int(b) for b in rng.integers(1, nb - 1, 3)})
+    refs = {b: O.nw_range(B, b * W_, (b + 1) * W_) for b in blocks}
+    print("n40 paired: sampled workgroups", blocks, flush=True)
+    got, st, parts = P.perm_sparse_ex(ccs, block_partials=True, **opts)
+    print("n40 paired", got, st["kernel_ms"], st["vgprs"], st["evaluated_steps"], flush=True)
+    assert st["exact"] == -1 and st["evaluated_steps"] == 2.0 ** 39
+    assert abs(got - exact) < 0.5, (got, exact)
+    for b, ((h, l), (ah, al)) in refs.items():
+        part = parts[b, 0] + parts[b, 1]
+        assert abs(part - (h + l)) <= 1e-12 * (ah + al) + 1e-9, (b, part, h + l)
+
+
 def test_zero_skip_is_exact(P, oracle_mod):
     """Skipping chunks/blocks whose terms are exactly 0 leaves every result
     unchanged (0/1 and integer matrices, several chunk and unroll sizes)."""

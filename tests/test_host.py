@@ -215,10 +215,10 @@ def test_codegen_resources(P):
         own = P.compile_info(ccs, waves_per_simd=-1)
         assert own["vgprs"] <= (168 if own["exact"] >= 0 else 128)
         # the LDS tier: cold rows in LDS ([row][lane]), at most 40 KiB per workgroup
+        # (k as compiled: Alg. 5 runs again with the compiled kernel's register model)
         lds = P.compile_info(ccs, mode="hybrid", cold_tier="lds")
-        plan = P.perm_plan(ccs, mode="hybrid")
         assert lds["scratch_bytes"] == 0
-        assert lds["lds_bytes"] >= 8 * (ccs[0] - plan["k"]) * lds["block"]
+        assert lds["lds_bytes"] >= 8 * (ccs[0] - lds["k"]) * lds["block"]
         assert lds["lds_bytes"] <= 40960 + 1024
 
 
@@ -577,3 +577,28 @@ def test_autotune_singular_needs_no_device(P):
     sing = (n, cp2, ri[keep].astype(np.int32), v[keep])
     opts, st = P.perm_autotune(sing, unroll_log2=3)
     assert st["candidates"] == 0 and opts["unroll_log2"] == 3 and opts["mode"] == "auto"
+
+
+def test_column0_pairing_on_cpu(P, oracle_mod):
+    """All-terms FP64 kernels whose first ordered column has one or two entries
+    sum each pair of Gray terms that differ in column 0 by one expression
+    (the walk flips columns 1..n-2 only, over half the steps); emulated on the
+    CPU over every chunk, against the oracle, with every term accounted for."""
+    O = oracle_mod
+    cases = [(W.random_sparse(10, 0.3, 0, kind="real"), 3, 1), (W.random_sparse(13, 0.25, 1, kind="signed"), 5, 2),
+             (W.random_sparse(14, 0.3, 7, kind="real"), 6, 0), (W.single_01(16, 0.2, 2), 7, 3),
+             (W.single_01(20, 0.1, 6), 12, 4), (W.random_sparse(12, 0.2, 9, kind="signed"), 8, 5)]
+    # a batch-workload matrix whose column 0 holds one negative entry (the
+    # pair's bracket is then that literal, negated)
+    cases += [(W.batch_matrix(7, 16), 8, 6)]
+    for ccs, kappa, u in cases:
+        ref, abs_sum = O.perm_nw(ccs)
+        opts = dict(chunk_log2=kappa, unroll_log2=u, zero_skip=False, exact=False)
+        assert "pair0" in P.perm_codegen(ccs, **opts).splitlines()[0], (ccs[0], kappa, u)
+        got, info = _emulate(P, ccs, **opts)
+        assert info["evaluated"] == 1 << (ccs[0] - 1)
+        assert abs(got - ref) <= 1e-13 * abs_sum + 1e-15, (ccs[0], kappa, u, got, ref)
+    # not paired: zero-aware kernels, the exact mode, HYBRID
+    ccs = W.single_01(16, 0.2, 2)
+    for opts in (dict(zero_skip=True, exact=False), dict(zero_skip=False), dict(zero_skip=False, mode="hybrid")):
+        assert "pair0" not in P.perm_codegen(ccs, chunk_log2=7, **opts).splitlines()[0], opts
