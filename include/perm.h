@@ -234,6 +234,28 @@ typedef struct {
 perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out,
                           perm_batch_stats *st);
 
+/* perm_batch_ex for callers that cannot allocate device memory (code that a
+ * caller captures into a HIP graph, tight serving loops, hosts that forbid
+ * allocation after start-up).  It allocates no device or pinned host memory
+ * and frees none: the staged matrices, the wave partials and the per-matrix
+ * sums live in a fixed region of PERM_NOALLOC_SCRATCH_BYTES bytes per device,
+ * a device array of the library whose address is looked up once, when the
+ * library first sets up the device.  Inputs are copied from ordinary host
+ * memory; host-side preparation uses the ordinary heap, on the calling thread.
+ * Same kernels, same work order and so bitwise the same results as
+ * perm_batch_ex with the same opts, except that every launch goes on one
+ * stream (opts->hip_stream, else the library's): batch_mode is ignored.
+ * A batch whose buffers do not fit the region fails with PERM_ETOOBIG (its
+ * message gives the bytes needed); split it, or use perm_batch_ex.
+ * The region keeps the last call's contents; every buffer a call reads is
+ * written by that call first, so nothing needs clearing.  Synchronous, and
+ * serialised with every other call of the library in this process by its
+ * lock, so calls from several threads never share the region at once; each
+ * process holds its own copy of the region. */
+#define PERM_NOALLOC_SCRATCH_BYTES (64u << 20)
+perm_status perm_batch_noalloc(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out,
+                               perm_batch_stats *st);
+
 /* ---- Autotuning ---------------------------------------------------------- */
 
 typedef struct {

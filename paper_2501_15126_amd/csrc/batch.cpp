@@ -11,6 +11,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <type_traits>
 
 #include "batch.h"
 #include "batch_host.h"
@@ -228,7 +229,19 @@ hipError_t batch_class_streams(hipStream_t out[kBatchStreams]) {
     return hipSuccess;
 }
 
+hipError_t BatchJob::init_events() {
+    if (ev0) return hipSuccess;
+    hipError_t e;
+    if ((e = hipEventCreate(&ev0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&ev1)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming)) != hipSuccess) return e;
+    for (int i = 0; i < kBatchStreams; ++i)
+        if ((e = hipEventCreateWithFlags(&ev_join[i], hipEventDisableTiming)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
 BatchJob::~BatchJob() {
+    if (arena) return;  // the buffers are views of the allocation-free region
     if (d_mats) (void)hipFree(d_mats);
     if (d_ranges) (void)hipFree(d_ranges);
     if (d_blk) (void)hipFree(d_blk);
@@ -368,21 +381,57 @@ perm_status BatchJob::run_pass(const std::vector<const PreparedMatrix *> &mats, 
         nblk += w.blk_first.size();
     }
     perm_status s;
-    if ((s = grow(&d_mats, &cap_mats, (size_t)nm, err)) != PERM_OK) return s;
-    if ((s = grow(&d_ranges, &cap_ranges, nranges, err)) != PERM_OK) return s;
-    if ((s = grow(&d_blk, &cap_blk, nblk, err)) != PERM_OK) return s;
-    if ((s = grow(&d_vals, &cap_vals, nvals, err)) != PERM_OK) return s;
-    if ((s = grow(&d_tops, &cap_tops, ntops, err)) != PERM_OK) return s;
-    if ((s = grow(&d_fin, &cap_fin, (size_t)nm, err)) != PERM_OK) return s;
-    if ((s = grow(&d_partials, &cap_partials, (size_t)kPartStride * nparts, err)) != PERM_OK) return s;
-    if ((s = grow(&d_out, &cap_out, (size_t)kPartStride * nm, err)) != PERM_OK) return s;
-    // one pinned staging buffer for all inputs
+    // all inputs staged in one host buffer (pinned, or ordinary host memory
+    // in the allocation-free form)
     const size_t bytes = nm * sizeof(BatchMat) + nranges * sizeof(BatchRange) + nblk * sizeof(int32_t) +
                          nvals * sizeof(double) + ntops * sizeof(int32_t) + nm * sizeof(FinishDesc) + 64;
-    if ((s = grow_host(&h_stage, &cap_stage, bytes, err)) != PERM_OK) return s;
-    if ((s = grow_host(&h_out, &cap_hout, (size_t)kPartStride * nm, err)) != PERM_OK) return s;
-    char *p = h_stage;
-    auto align8 = [&]() { p = h_stage + ((size_t)(p - h_stage) + 7) / 8 * 8; };
+    char *stage = nullptr;
+    double *hout = nullptr;
+    if (arena) {
+        if (how != BatchLaunch::Single) {
+            *err = "the allocation-free form launches on one stream only";
+            return PERM_EINVAL;
+        }
+        // views of the fixed region, 256-byte aligned; nothing is allocated
+        size_t off = 0;
+        auto carve = [&](auto **pp, size_t n) {
+            off = (off + 255) / 256 * 256;
+            *pp = reinterpret_cast<std::remove_reference_t<decltype(**pp)> *>(arena + off);
+            off += n * sizeof(**pp);
+        };
+        carve(&d_mats, (size_t)nm);
+        carve(&d_ranges, nranges);
+        carve(&d_blk, nblk);
+        carve(&d_vals, nvals);
+        carve(&d_tops, ntops);
+        carve(&d_fin, (size_t)nm);
+        carve(&d_partials, (size_t)kPartStride * nparts);
+        carve(&d_out, (size_t)kPartStride * nm);
+        if (off > arena_bytes) {
+            *err = "the batch needs " + std::to_string(off) + " bytes of device scratch; the allocation-free form "
+                   "holds " + std::to_string(arena_bytes) + " (split the batch, or use perm_batch)";
+            return PERM_ETOOBIG;
+        }
+        if (arena_stage.size() < bytes) arena_stage.resize(bytes);
+        if (arena_hout.size() < (size_t)kPartStride * nm) arena_hout.resize((size_t)kPartStride * nm);
+        stage = arena_stage.data();
+        hout = arena_hout.data();
+    } else {
+        if ((s = grow(&d_mats, &cap_mats, (size_t)nm, err)) != PERM_OK) return s;
+        if ((s = grow(&d_ranges, &cap_ranges, nranges, err)) != PERM_OK) return s;
+        if ((s = grow(&d_blk, &cap_blk, nblk, err)) != PERM_OK) return s;
+        if ((s = grow(&d_vals, &cap_vals, nvals, err)) != PERM_OK) return s;
+        if ((s = grow(&d_tops, &cap_tops, ntops, err)) != PERM_OK) return s;
+        if ((s = grow(&d_fin, &cap_fin, (size_t)nm, err)) != PERM_OK) return s;
+        if ((s = grow(&d_partials, &cap_partials, (size_t)kPartStride * nparts, err)) != PERM_OK) return s;
+        if ((s = grow(&d_out, &cap_out, (size_t)kPartStride * nm, err)) != PERM_OK) return s;
+        if ((s = grow_host(&h_stage, &cap_stage, bytes, err)) != PERM_OK) return s;
+        if ((s = grow_host(&h_out, &cap_hout, (size_t)kPartStride * nm, err)) != PERM_OK) return s;
+        stage = h_stage;
+        hout = h_out;
+    }
+    char *p = stage;
+    auto align8 = [&]() { p = stage + ((size_t)(p - stage) + 7) / 8 * 8; };
     char *s_mats = p;
     memcpy(p, hm.data(), nm * sizeof(BatchMat));
     p += nm * sizeof(BatchMat);
@@ -421,12 +470,7 @@ perm_status BatchJob::run_pass(const std::vector<const PreparedMatrix *> &mats, 
     HIP_OK(hipMemcpyAsync(d_tops, s_tops, ntops * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemcpyAsync(d_fin, s_fin, nm * sizeof(FinishDesc), hipMemcpyHostToDevice, stream));
 
-    if (!ev0) {
-        HIP_OK(hipEventCreate(&ev0));
-        HIP_OK(hipEventCreate(&ev1));
-        HIP_OK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-        for (int i = 0; i < kBatchStreams; ++i) HIP_OK(hipEventCreateWithFlags(&ev_join[i], hipEventDisableTiming));
-    }
+    HIP_OK(init_events());
     const bool persistent = how == BatchLaunch::Graph;
     const bool branches = how == BatchLaunch::Streams || how == BatchLaunch::Graph;
     // persistent form: one item counter and a resident-size grid per instance
@@ -533,7 +577,7 @@ perm_status BatchJob::run_pass(const std::vector<const PreparedMatrix *> &mats, 
         if (es != PERM_OK) return es;
     }
     HIP_OK(hipEventRecord(ev1, stream));
-    HIP_OK(hipMemcpyAsync(h_out, d_out, (size_t)kPartStride * nm * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemcpyAsync(hout, d_out, (size_t)kPartStride * nm * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     if (kernel_ms) {
         float ms = 0;
@@ -541,7 +585,7 @@ perm_status BatchJob::run_pass(const std::vector<const PreparedMatrix *> &mats, 
         *kernel_ms = ms;
     }
     for (int k = 0; k < nm; ++k)
-        for (int c = 0; c < kPartStride; ++c) raw[(size_t)kPartStride * order[k] + c] = h_out[kPartStride * k + c];
+        for (int c = 0; c < kPartStride; ++c) raw[(size_t)kPartStride * order[k] + c] = hout[kPartStride * k + c];
     return PERM_OK;
 }
 

@@ -51,6 +51,16 @@ hipError_t launch_counters_reset(unsigned long long *c, int n, hipStream_t strea
 hipError_t launch_batch_finish(const FinishDesc *d, int count, const double *partials, double *out,
                                hipStream_t stream);
 
+// The allocation-free entry point's device region: kNoallocScratchBytes
+// bytes per device, a file-scope device array of batch.hip.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+constexpr int kNoallocMaxDevices = 64;
+
+// *ptr = the current device's address of that region (looked up once per
+// device with hipGetSymbolAddress, then kept).  Not thread-safe on the first
+// call for a device: callers hold the library lock.
+hipError_t batch_scratch_address(void **ptr);
+
 // Resources of the compiled batch kernel instance (VGPRs, scratch).
 int batch_kernel_attributes(int ng, bool zero_skip, bool exact, int *vgprs, int *scratch);
 

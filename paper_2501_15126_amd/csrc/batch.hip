@@ -287,6 +287,31 @@ hipError_t launch_batch_finish(const FinishDesc *d, int count, const double *par
     return hipGetLastError();
 }
 
+// Device memory of the allocation-free batch entry point: the staged
+// matrices, the wave partials and the per-matrix sums live here instead of
+// in buffers the library allocates.  Each device the library runs on holds
+// its own copy, at its own address, until the process ends.  Host code never
+// names the array itself (its host-side symbol is not a device address); it
+// uses the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+hipError_t batch_scratch_address(void **ptr) {
+    static void *addr[kNoallocMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoallocMaxDevices) return hipErrorInvalidDevice;
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
 int batch_kernel_attributes(int ng, bool zero_skip, bool exact, int *vgprs, int *scratch) {
     *vgprs = -1;
     *scratch = -1;

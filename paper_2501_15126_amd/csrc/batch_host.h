@@ -97,6 +97,16 @@ struct BatchJob {
     std::string graph_sig;   // launch layout the graph was captured for
     int graph_captures = 0;  // captures so far (a relaunch does not count)
     int block = 256;         // threads per workgroup of the batch kernels: 64, 128 or 256
+    // Allocation-free form: when `arena` is set, every device buffer of a pass
+    // is carved from [arena, arena + arena_bytes) (nothing is allocated or
+    // freed; a pass that does not fit fails with PERM_ETOOBIG), inputs are
+    // staged in ordinary host memory, and only BatchLaunch::Single is allowed.
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    std::vector<char> arena_stage;   // host staging of the allocation-free form
+    std::vector<double> arena_hout;
+    // Creates the timing events (done once, at set-up).
+    hipError_t init_events();
 
     ~BatchJob();
     // Runs all matrices (singular ones are answered 0 without work) and writes

@@ -77,6 +77,9 @@ DeviceState g_dev;
 // device buffers and graph of perm_batch (used under g_mu); never destroyed,
 // so that no HIP call runs during static destruction at process exit
 BatchJob &g_batch_job = *new BatchJob;
+// perm_batch_noalloc's job: its buffers are views of the batch kernels'
+// fixed device region, set at device set-up
+BatchJob &g_noalloc_job = *new BatchJob;
 
 perm_status ensure_device() {
     if (g_dev.ready) return PERM_OK;
@@ -93,6 +96,13 @@ perm_status ensure_device() {
     for (auto &ev : g_dev.ev) HIP_TRY(hipEventCreate(&ev));
     HIP_TRY(hipMalloc(&g_dev.out, 8 * sizeof(double)));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&g_dev.host_out), 8 * sizeof(double), hipHostMallocDefault));
+    // the allocation-free batch form: the device address of the fixed region
+    // (this device's copy) and its timing events, once, here
+    void *scr = nullptr;
+    HIP_TRY(batch_scratch_address(&scr));
+    g_noalloc_job.arena = static_cast<char *>(scr);
+    g_noalloc_job.arena_bytes = kNoallocScratchBytes;
+    HIP_TRY(g_noalloc_job.init_events());
     g_dev.ready = true;
     return PERM_OK;
 }
@@ -908,8 +918,15 @@ perm_status perm_batch_autotune(int32_t count, const perm_csc *mats, const perm_
     return autotune_batch(count, mats, opts, best, st);
 }
 
-perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out,
-                          perm_batch_stats *st) {
+}  // extern "C"
+
+namespace {
+
+// perm_batch_ex and its allocation-free form (noalloc: every device buffer is
+// a view of the library's fixed scratch region, all launches on one stream,
+// the matrices prepared on the calling thread).
+perm_status batch_impl(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out,
+                       perm_batch_stats *st, bool noalloc) {
     auto t0 = std::chrono::steady_clock::now();
     if (count < 0 || (count > 0 && (!mats || !out))) return fail(PERM_EINVAL, "bad batch arguments");
     const perm_opts o = defaults(opts);
@@ -934,7 +951,8 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
         // (each writes only its own slots), then report the first failure
         std::vector<perm_status> st_of(count, PERM_OK);
         std::vector<std::string> err_of(count);
-        const int nthreads = std::max(1, std::min<int>({(int)std::thread::hardware_concurrency(), 8, count / 64}));
+        const int nthreads =
+            noalloc ? 1 : std::max(1, std::min<int>({(int)std::thread::hardware_concurrency(), 8, count / 64}));
         auto work = [&](int t) {
             for (int32_t i = t; i < count; i += nthreads) st_of[i] = prepare_batch_matrix(&mats[i], bo, &prep[i], &err_of[i]);
         };
@@ -960,17 +978,24 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
     std::lock_guard<std::mutex> g(g_mu);
     perm_status s = ensure_device();
     if (s != PERM_OK) return s;
-    g_batch_job.block = o.block > 0 ? o.block : 256;
+    BatchJob &job = noalloc ? g_noalloc_job : g_batch_job;
+    job.block = o.block > 0 ? o.block : 256;
     hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : g_dev.stream;
     double kms = 0.0;
     int launches = 0, passes = 0;
     std::vector<int> xs((size_t)std::max(count, 1), -1);
-    if (o.batch_mode == 2) {
+    if (noalloc) {
+        std::vector<const PreparedMatrix *> all;
+        for (auto &pm : prep) all.push_back(&pm);
+        s = job.run(all, out, stream, BatchLaunch::Single, &kms, &err, xs.data(), &passes, o.exact_passes);
+        if (s != PERM_OK) return fail(s, err);
+        launches = -1;
+    } else if (o.batch_mode == 2) {
         for (int32_t i = 0; i < count; ++i) {
             std::vector<const PreparedMatrix *> one{&prep[i]};
             double k1 = 0.0;
             int np = 0;
-            s = g_batch_job.run(one, &out[i], stream, BatchLaunch::Single, &k1, &err, &xs[i], &np, o.exact_passes);
+            s = job.run(one, &out[i], stream, BatchLaunch::Single, &k1, &err, &xs[i], &np, o.exact_passes);
             if (s != PERM_OK) return fail(s, err);
             kms += k1;
             launches += prep[i].singular ? 0 : 2 * np;
@@ -982,7 +1007,7 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
         const BatchLaunch how = o.batch_mode == 0   ? BatchLaunch::Streams
                                 : o.batch_mode == 1 ? BatchLaunch::Graph
                                                     : BatchLaunch::Single;
-        s = g_batch_job.run(all, out, stream, how, &kms, &err, xs.data(), &passes, o.exact_passes);
+        s = job.run(all, out, stream, how, &kms, &err, xs.data(), &passes, o.exact_passes);
         if (s != PERM_OK) return fail(s, err);
         launches = -1;
     }
@@ -998,7 +1023,7 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
         st->fp64_ops = ops;
         st->flops = ops + fmas;
         st->passes = passes;
-        st->graph_captures = g_batch_job.graph_captures;
+        st->graph_captures = job.graph_captures;
         for (int32_t i = 0; i < count; ++i) {
             if (xs[i] == 1 && !prep[i].singular) st->exact_certified++;
             if (xs[i] == 0) st->exact_uncertified++;
@@ -1009,6 +1034,20 @@ perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *
         st->exact_ops = xo;
     }
     return PERM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+perm_status perm_batch_ex(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out,
+                          perm_batch_stats *st) {
+    return batch_impl(count, mats, opts, out, st, false);
+}
+
+perm_status perm_batch_noalloc(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out,
+                               perm_batch_stats *st) {
+    return batch_impl(count, mats, opts, out, st, true);
 }
 
 perm_status perm_batch(int32_t count, const perm_csc *mats, const perm_opts *opts, double *out) {

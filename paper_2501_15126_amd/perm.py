@@ -97,6 +97,9 @@ _lib.perm_batch.restype = ctypes.c_int
 _lib.perm_batch.argtypes = [ctypes.c_int32, _P(PermCsc), _P(PermOpts), _P(ctypes.c_double)]
 _lib.perm_batch_ex.restype = ctypes.c_int
 _lib.perm_batch_ex.argtypes = [ctypes.c_int32, _P(PermCsc), _P(PermOpts), _P(ctypes.c_double), _P(PermBatchStats)]
+_lib.perm_batch_noalloc.restype = ctypes.c_int
+_lib.perm_batch_noalloc.argtypes = [ctypes.c_int32, _P(PermCsc), _P(PermOpts), _P(ctypes.c_double),
+                                    _P(PermBatchStats)]
 _lib.perm_plan.restype = ctypes.c_int
 _lib.perm_plan.argtypes = [_P(PermCsc), _P(PermOpts), _P(ctypes.c_int32), _P(ctypes.c_int32),
                            _P(ctypes.c_double), _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32),
@@ -155,7 +158,8 @@ _lib.perm_server_destroy.restype = None
 _lib.perm_server_destroy.argtypes = [ctypes.c_void_p]
 
 # every symbol include/perm.h declares
-EXPORTED = ["perm_sparse", "perm_sparse_ex", "perm_batch", "perm_batch_ex", "perm_server_create", "perm_submit",
+EXPORTED = ["perm_sparse", "perm_sparse_ex", "perm_batch", "perm_batch_ex", "perm_batch_noalloc",
+            "perm_server_create", "perm_submit",
             "perm_poll", "perm_wait", "perm_server_get_stats", "perm_server_destroy", "perm_batch_describe",
             "perm_plan", "perm_partition", "perm_codegen",
             "perm_compile_info", "perm_autotune", "perm_batch_autotune", "perm_exact_recover", "perm_exact_primes",
@@ -284,6 +288,19 @@ def perm_batch_ex(mats, **opts):
     st = PermBatchStats()
     _check(_lib.perm_batch_ex(len(held), arr, ctypes.byref(o), out.ctypes.data_as(_P(ctypes.c_double)),
                               ctypes.byref(st)))
+    return out[:len(held)], st.as_dict()
+
+
+def perm_batch_noalloc(mats, **opts):
+    """perm_batch_ex without device allocation (the library's fixed scratch
+    region); returns (results array, batch stats dict)."""
+    held = [_Csc(c) for c in mats]
+    arr = (PermCsc * max(1, len(held)))(*[h.c for h in held])
+    out = np.zeros(max(1, len(held)), np.float64)
+    o = make_opts(**opts)
+    st = PermBatchStats()
+    _check(_lib.perm_batch_noalloc(len(held), arr, ctypes.byref(o), out.ctypes.data_as(_P(ctypes.c_double)),
+                                   ctypes.byref(st)))
     return out[:len(held)], st.as_dict()
 
 
