@@ -262,8 +262,14 @@ struct Gen {
                 os << I << "const double " << dw << " = " << d << " * " << weight << ";\n";
                 d = dw;
             }
-            // term_sign * (-d) * S_1
-            os << I << "acc" << acc << " = fma(" << (term_sign < 0 ? "" : "-") << d << ", S1, acc" << acc << ");\n";
+            // term_sign * (-d) * S_1; exact mode: d is an integer (y units,
+            // within the sub-product bound), so its residue is d R_1
+            const char *sg = term_sign < 0 ? "" : "-";
+            os << I << "acc" << acc << " = fma(" << sg << d << ", S1, acc" << acc << ");\n";
+            if (p.exact) {
+                os << I << "racc = fma(" << sg << d << ", R1, racc);\n";
+                os << I << "accA = fma(fabs(" << d << "), fabs(S1), accA);\n";
+            }
             return;
         }
         if (p.exact) {

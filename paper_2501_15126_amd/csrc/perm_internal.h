@@ -80,8 +80,9 @@ struct Plan {
     // differ only in column 0) are summed by one expression, (-1)^i S_1
     // (P(x) - P(x + a)), P the product of column 0's rows (level 0) and x
     // kept without column 0; the walk then flips columns 1..n-2 only, over
-    // half as many steps.  Set for AUTO all-terms FP64 kernels whose column 0
-    // has one or two entries; kappa and u then count these paired steps:
+    // half as many steps.  Set for AUTO all-terms kernels (FP64, or the
+    // exact mode when the bracket stays within the sub-product bound) whose
+    // column 0 has one or two entries; kappa and u then count these paired steps:
     // a chunk still covers 2^kappa Gray indices, walked in 2^(kappa-1) steps,
     // and a static block is 2^u paired steps.
     bool pair0 = false;

@@ -383,10 +383,23 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
     p->pair0 = false;
     {
         const int d0 = n >= 2 ? B.colptr[1] - B.colptr[0] : 0;
-        bool ok = o.mode == PERM_MODE_AUTO && !zs && !ex && !p->cold && p->nlevels >= 2 && p->kappa >= 3 &&
+        bool ok = o.mode == PERM_MODE_AUTO && !zs && !p->cold && p->nlevels >= 2 && p->kappa >= 3 &&
                   (d0 == 1 || d0 == 2);
         for (int r = 0; r < n && ok; ++r)
             if ((p->row_level[r] == 0) != (first[r] == 0)) ok = false;
+        if (ok && ex) {
+            // exact mode: the bracket (an integer in y units) must stay within
+            // kExactPartMax, like any sub-product whose residue is formed
+            std::vector<double> yb(n, 0.0);  // |y_r| <= half the row's sum of |2a|
+            for (int q = 0; q < B.nnz(); ++q) yb[B.rowidx[q]] += std::fabs(B.val[q]) / 2;
+            const int q0 = B.colptr[0];
+            double bd = std::fabs(B.val[q0]);
+            if (d0 == 2) {
+                const double ar = std::fabs(B.val[q0]), as = std::fabs(B.val[q0 + 1]);
+                bd = ar * yb[B.rowidx[q0 + 1]] + as * yb[B.rowidx[q0]] + ar * as;
+            }
+            if (bd > kExactPartMax) ok = false;
+        }
         if (ok) {
             p->pair0 = true;
             p->u = std::min(p->u, p->kappa - 2);  // a static block of paired steps fits the chunk's half
@@ -456,7 +469,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         // difference and the accumulate does a multiply and an add the sum
         // needs (2 flops each).
         const int d0 = B.colptr[1] - B.colptr[0];
-        double pops = 0.0, pfl = 0.0;
+        double pops = 0.0, pfl = 0.0, pxo = 0.0;
         for (int j = 1; j < n - 1; ++j) {
             const int t = p->col_top[j];
             std::fill(touched.begin(), touched.end(), 0);
@@ -478,14 +491,26 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
                 bops = tr ? 2.0 : ts ? 1.0 : 0.0;
             }
             oj += bops + 1.0;
-            p->ops_of_col[j] = oj;
             const double cnt = std::ldexp(1.0, n - j - 2);
+            double xo = 0.0;
+            if (ex) {
+                // residue chain of the refreshed levels (four operations per
+                // sub-product, the top level's first needs none), then the
+                // pair's residue FMA and the error bound's FMA
+                for (int l = 1; l <= t; ++l)
+                    xo += 4.0 * ((double)p->level_parts[l].size() - (l + 1 < L ? 0.0 : 1.0));
+                xo += 2.0;
+                oj += xo;
+                pxo += cnt * xo;
+            }
+            p->ops_of_col[j] = oj;
             pops += cnt * oj;
             pfl += cnt * (oj + 1.0 + bops);
         }
         p->ops_of_col[0] = 0.0;
         p->ops_per_step = pops / steps;
         p->flops_per_step = pfl / steps;
+        p->exact_ops_per_step = pxo / steps;
     }
     return PERM_OK;
 }

@@ -598,7 +598,23 @@ def test_column0_pairing_on_cpu(P, oracle_mod):
         got, info = _emulate(P, ccs, **opts)
         assert info["evaluated"] == 1 << (ccs[0] - 1)
         assert abs(got - ref) <= 1e-13 * abs_sum + 1e-15, (ccs[0], kappa, u, got, ref)
-    # not paired: zero-aware kernels, the exact mode, HYBRID
+    # the exact mode pairs too: the pair's bracket is an integer (y units),
+    # its residue d R_1; residues and the recovered count against the oracle
+    for ccs, kappa, u in ((W.single_01(16, 0.2, 2), 7, 3), (W.single_01(20, 0.1, 6), 12, 4)):
+        opts = dict(chunk_log2=kappa, unroll_log2=u, zero_skip=False)
+        assert "pair0" in P.perm_codegen(ccs, **opts).splitlines()[0]
+        res = []
+        for pm in P.exact_primes():
+            got, info = _emulate(P, ccs, prime=pm, **opts)
+            assert info["exact"] == 0 and info["evaluated"] == 1 << (ccs[0] - 1)
+            res.append(info["resid"])
+        perm = O.perm_int(ccs)
+        v, est, bound, cert, more = P.exact_recover(ccs[0], info["hi"], info["lo"], info["abs_sum"],
+                                                    info["chunk_log2"], res[:1])
+        assert cert and v == perm, (ccs[0], v, perm)
+        v3 = P.exact_recover(ccs[0], info["hi"], info["lo"], info["abs_sum"], info["chunk_log2"], res)[0]
+        assert v3 == perm
+    # not paired: zero-aware kernels, HYBRID
     ccs = W.single_01(16, 0.2, 2)
-    for opts in (dict(zero_skip=True, exact=False), dict(zero_skip=False), dict(zero_skip=False, mode="hybrid")):
+    for opts in (dict(zero_skip=True, exact=False), dict(zero_skip=True), dict(zero_skip=False, mode="hybrid")):
         assert "pair0" not in P.perm_codegen(ccs, chunk_log2=7, **opts).splitlines()[0], opts
