@@ -211,9 +211,12 @@ struct Gen {
         os << I << "S" << l << " = " << prod << ";\n";
     }
 
-    // R_l for l = L-1 down to lo, from the current x (exact mode).
+    // R_l for l = rtop down to lo, from the current x (exact mode).  Levels
+    // above rtop hold rows that no column of the chunk flips: their residues,
+    // formed at the chunk start, stay valid for the whole chunk.
+    int rtop = 0;
     void recompute_residues(int lo, std::map<int, std::string> &cur, const char *I) {
-        for (int l = p.nlevels - 1; l >= lo; --l) {
+        for (int l = std::min(rtop, p.nlevels - 1); l >= lo; --l) {
             const std::vector<std::string> qs = part_products(l, cur, I);
             const std::string r = residue_chain(qs, 0, l + 1 < p.nlevels ? "R" + std::to_string(l + 1) : "", I);
             os << I << "R" << l << " = " << r << ";\n";
@@ -574,6 +577,7 @@ struct Gen {
             // their cached product is 0 in all 64 lanes the wave skips the chunk.
             int chunk_top = 0;
             for (int j = 0; j < kappa; ++j) chunk_top = std::max(chunk_top, p.col_top[j]);
+            rtop = chunk_top;
             const bool skip_chunk = p.zero_skip && chunk_top + 1 <= L - 1;
             if (skip_chunk) os << "  if (!__all(S" << chunk_top + 1 << " == 0.0)) {\n";
             // local step base + 2^u flips column u; its direction is bit u+1

@@ -262,9 +262,12 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         for (int r = 0; r < k; ++r)
             if (first[r] < kap) ++live_rows;
         // exact mode: a residue beside each cached product, and the residue
-        // and error-bound accumulators
+        // and error-bound accumulators.  With zero-aware skipping the walk
+        // keeps no residues (they are formed again where terms are evaluated,
+        // so their registers are live only there): 2 per level, as in FP64.
+        const int per_level = (ex && !zs) ? 4 : 2;
         auto vgprs = [&](int nlev) {
-            return 2 * live_rows + (ex ? 4 : 2) * (nlev + cold_levels - 1) + kBaseVgprs + (ex ? kExactBaseVgprs : 0);
+            return 2 * live_rows + per_level * (nlev + cold_levels - 1) + kBaseVgprs + (ex ? kExactBaseVgprs : 0);
         };
         int cap = o.max_levels > 0 ? o.max_levels : INT_MAX;
         while ((int)lev_begin.size() > 1 && ((int)lev_begin.size() > cap || vgprs((int)lev_begin.size()) > budget))
