@@ -107,6 +107,12 @@ def test_ordering_matches_oracle_alg4(P, oracle_mod):
         plan = P.perm_plan(ccs, mode="auto")
         rp, cp = O.permanent_ordering(ccs)
         assert plan["row_perm"] == rp and plan["col_perm"] == cp, seed
+    # the hand-worked instance of the oracle's tests (Sec. V, Alg. 4)
+    A = np.zeros((5, 5))
+    for j, rows in enumerate(([0, 1, 2, 3], [2], [1, 4], [0, 3, 4], [0, 1, 2, 3, 4])):
+        A[rows, j] = 1.0
+    plan = P.perm_plan(O.dense_to_ccs(A))
+    assert plan["col_perm"] == [1, 2, 0, 3, 4] and plan["row_perm"] == [2, 1, 4, 0, 3]
 
 
 def test_partition_matches_oracle_alg5(P, oracle_mod):

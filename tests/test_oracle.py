@@ -402,6 +402,25 @@ def test_ordering_is_greedy_min_unordered_degree(oracle_mod):
         assert rowPerm == ordered_rows
 
 
+def test_ordering_hand_worked_instance(oracle_mod):
+    """Alg. 4 on a 5x5 pattern worked by hand (Sec. V): columns hold rows
+    c0 = {0,1,2,3}, c1 = {2}, c2 = {1,4}, c3 = {0,3,4}, c4 = {0,...,4}.
+    Step 1: counts over unordered rows 4,1,2,3,5 -> column 1; rows [2].
+    Step 2: rows other than 2: c0 3, c2 2, c3 3, c4 4 -> column 2; rows [1, 4].
+    Step 3: unordered rows {0, 3}: c0 2, c3 2, c4 2 -> the lowest, column 0;
+    rows [0, 3].  (By total degree, 4, 3, 5, column 3 would win here.)
+    Steps 4-5: no rows left; columns 3, then 4.  A rule taking the largest
+    count (column 4 first), the highest index on ties, or rows in descending
+    order gives another result."""
+    O = oracle_mod
+    A = np.zeros((5, 5))
+    for j, rows in enumerate(([0, 1, 2, 3], [2], [1, 4], [0, 3, 4], [0, 1, 2, 3, 4])):
+        A[rows, j] = 1.0
+    rowPerm, colPerm = O.permanent_ordering(O.dense_to_ccs(A))
+    assert list(colPerm) == [1, 2, 0, 3, 4]
+    assert list(rowPerm) == [2, 1, 4, 0, 3]
+
+
 def test_ordering_gives_staircase_pattern(oracle_mod):
     """After ordering, the rows touched by the first c columns are the first
     |I_c| rows, for every c (the pattern of Fig. 4a)."""
