@@ -66,6 +66,8 @@ struct DeviceState {
     unsigned long long *counts = nullptr;  // evaluated terms per workgroup
     size_t counts_cap = 0;
     double *xparts = nullptr;  // exact mode: (residue, sum |term|) per workgroup
+    double *stage = nullptr;   // the final reduction's per-slice results (6 doubles each)
+    size_t stage_cap = 0;
     size_t xparts_cap = 0;
     double *out = nullptr;    // 2 doubles, the evaluated-term total (u64), then the 3 exact-mode sums
     double *host_out = nullptr;  // pinned host copy of out
@@ -390,9 +392,10 @@ perm_status run_pass(CachedPlan &cp, double prime, const perm_opts &o, hipStream
         }
     }
     HIP_TRY(hipEventRecord(g_dev.ev[1], stream));
-    unsigned long long *count_out = reinterpret_cast<unsigned long long *>(g_dev.out + 2);
-    HIP_TRY(launch_final_reduce(g_dev.partials, g_dev.counts, (long long)nblocks, g_dev.out, count_out, stream));
-    if (pl.exact) HIP_TRY(launch_final_reduce_x(g_dev.xparts, (long long)nblocks, g_dev.out + 3, stream));
+    s = ensure_buffer(&g_dev.stage, &g_dev.stage_cap, 6 * (size_t)final_reduce_slices((long long)nblocks));
+    if (s != PERM_OK) return s;
+    HIP_TRY(launch_final_reduce(g_dev.partials, g_dev.counts, pl.exact ? g_dev.xparts : nullptr, (long long)nblocks,
+                                g_dev.stage, g_dev.out, stream));
     HIP_TRY(hipEventRecord(g_dev.ev[2], stream));
     double *hl = g_dev.host_out;  // pinned: the result copy is a plain DMA
     HIP_TRY(hipMemcpyAsync(hl, g_dev.out, (pl.exact ? 5 : 3) * sizeof(double), hipMemcpyDeviceToHost, stream));
@@ -595,8 +598,10 @@ perm_status time_sample(CachedPlan &cp, const TuneSample &ts, hipStream_t stream
         }
     }
     HIP_TRY(hipEventRecord(g_dev.ev[1], stream));
-    unsigned long long *count_out = reinterpret_cast<unsigned long long *>(g_dev.out + 2);
-    HIP_TRY(launch_final_reduce(g_dev.partials, g_dev.counts, (long long)nblocks, g_dev.out, count_out, stream));
+    perm_status rs = ensure_buffer(&g_dev.stage, &g_dev.stage_cap, 6 * (size_t)final_reduce_slices((long long)nblocks));
+    if (rs != PERM_OK) return rs;
+    HIP_TRY(launch_final_reduce(g_dev.partials, g_dev.counts, nullptr, (long long)nblocks, g_dev.stage, g_dev.out,
+                                stream));
     HIP_TRY(hipMemcpyAsync(g_dev.host_out, g_dev.out, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     HIP_TRY(hipEventElapsedTime(ms, g_dev.ev[0], g_dev.ev[1]));
