@@ -33,6 +33,7 @@
 //    accesses are contiguous (Sec. V), or in LDS with the same layout per
 //    workgroup (the shared-memory tier the paper leaves to future work), and
 //    their product is recomputed only when a column that touches them flips.
+#include <cmath>
 #include <cstdio>
 #include <map>
 #include <sstream>
@@ -81,6 +82,70 @@ struct Gen {
     // nonzero walk term).  walk_s_only marks code emitted for the walk.
     bool lazy_r = false;
     bool walk_s_only = false;
+    // Nested accumulation (FP64 kernels with column-0 pairing): instead of
+    // the cached products S_l = P_l S_{l+1} the kernel keeps each level's
+    // own product P_l and one accumulator c_l per level, holding the sum of
+    // the terms since level l+1 last changed as a coefficient of
+    // P_{l+1} ... P_{L-1} (c_0: the pairs' brackets).  A step whose highest
+    // level is t first moves c_0 .. c_{t-1} up through the products they
+    // multiply (c_l += c_{l-1} P_l, old P_l), then changes x and the touched
+    // P_l, then starts c_0 with its term: t operations where the cached
+    // products need t multiplies and an accumulate.  cz[l] marks an
+    // accumulator whose sum has moved up (its register is stale and its next
+    // fill is a multiply, not an FMA).  The loop's last (dynamic) step moves
+    // everything up to T, the highest level any step of the loop reaches, so
+    // c_1 .. c_{T-1} are empty at the loop's end and are taken as empty at
+    // its top (their registers hold 0 on entry).
+    bool horner = false;
+    std::vector<char> cz;
+    int loop_top = 0;  // T
+
+    // Bracket tracking (nested accumulation): with two entries in column 0
+    // the pair's bracket a_r x_s + a_s x_r + a_r a_s is affine in x, so it is
+    // kept in `dp` and moved by every step that touches row r or s (one add
+    // of the column's constant change); the level-0 rows' own x are never
+    // needed (with one entry the bracket is a constant).
+    bool dtrack = false;
+    int dyn_dslot = -1;  // slot of the bracket's change in the dynamic table
+
+    // Coefficients of x_r and x_s in the bracket and the bracket at x.
+    void bracket_coeffs(double &cr, double &cs) const {
+        const Ccs &B = p.B;
+        const int q0 = B.colptr[0];
+        const double ar = B.val[B.rowidx[q0] == p.pair_r ? q0 : q0 + 1];
+        const double as = B.val[B.rowidx[q0] == p.pair_s ? q0 : q0 + 1];
+        cr = as;  // d/dx_r
+        cs = ar;  // d/dx_s
+    }
+    // Change of the bracket when column j's entries are added to x.
+    double bracket_delta(int j) const {
+        const Ccs &B = p.B;
+        double cr, cs, dr = 0.0, ds = 0.0;
+        bracket_coeffs(cr, cs);
+        for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) {
+            if (B.rowidx[q] == p.pair_r) dr = B.val[q];
+            if (B.rowidx[q] == p.pair_s) ds = B.val[q];
+        }
+        return std::fma(cr, dr, cs * ds);
+    }
+    bool touches_level0(int j) const {
+        const Ccs &B = p.B;
+        for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q)
+            if (p.row_level[B.rowidx[q]] == 0) return true;
+        return false;
+    }
+
+    // c_0 .. c_{t-1} into c_t through the current products.
+    void flush_to(int t, const char *I) {
+        for (int l = 1; l <= t; ++l) {
+            if (cz[l])
+                os << I << "c" << l << " = c" << l - 1 << " * P" << l << ";\n";
+            else
+                os << I << "c" << l << " = fma(c" << l - 1 << ", P" << l << ", c" << l << ");\n";
+            cz[l] = 0;
+            if (l >= 2) cz[l - 1] = 1;
+        }
+    }
 
     std::string fresh() { return "t" + std::to_string(tmp++); }
     std::string xname(int r) const { return "x" + std::to_string(r); }
@@ -167,8 +232,10 @@ struct Gen {
     // cold rows are recorded in `cur`.
     void update(int j, Sign sg, std::map<int, std::string> &cur, const char *I) {
         const Ccs &B = p.B;
+        if (dtrack && touches_level0(j)) emit_add("dp", lit(bracket_delta(j)), sg, I);
         for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) {
             const int r = B.rowidx[q];
+            if (horner && p.row_level[r] == 0) continue;  // level 0 lives in the bracket
             const std::string a = lit(B.val[q]);
             std::string target;
             if (r < p.k) {
@@ -178,16 +245,21 @@ struct Gen {
                 os << I << "double " << target << " = " << cold_addr(r) << ";\n";
                 cur[r] = target;
             }
-            if (sg == Sign::Plus)
-                os << I << target << " += " << a << ";\n";
-            else if (sg == Sign::Minus)
-                os << I << target << " -= " << a << ";\n";
-            else if (sg == Sign::Uniform)
-                os << I << target << " += (neg ? -(" << a << ") : (" << a << "));\n";
-            else
-                os << I << target << " = fma(lsgn, " << a << ", " << target << ");\n";
+            emit_add(target, a, sg, I);
             if (r >= p.k) os << I << cold_addr(r) << " = " << target << ";\n";
         }
+    }
+
+    // target += a in direction sg
+    void emit_add(const std::string &target, const std::string &a, Sign sg, const char *I) {
+        if (sg == Sign::Plus)
+            os << I << target << " += " << a << ";\n";
+        else if (sg == Sign::Minus)
+            os << I << target << " -= " << a << ";\n";
+        else if (sg == Sign::Uniform)
+            os << I << target << " += (neg ? -(" << a << ") : (" << a << "));\n";
+        else
+            os << I << target << " = fma(lsgn, " << a << ", " << target << ");\n";
     }
 
     // Recompute the cached product of level l: S_l = prod(level l) * S_{l+1}.
@@ -206,6 +278,11 @@ struct Gen {
             return;
         }
         std::vector<std::string> v = level_values(l, cur, I);
+        if (horner) {
+            const std::string pr = product(v, I);
+            os << I << "P" << l << " = " << pr << ";\n";
+            return;
+        }
         if (l + 1 < p.nlevels) v.push_back("S" + std::to_string(l + 1));
         std::string prod = product(v, I);
         os << I << "S" << l << " = " << prod << ";\n";
@@ -233,15 +310,16 @@ struct Gen {
            << "\n";
         std::string in = std::string(ind) + "  ";
         const char *I = in.c_str();
+        if (horner) flush_to(p.col_top[j], I);
         update(j, sg, cur, I);
         for (int l = p.col_top[j]; l >= 1; --l) refresh_level(l, cur, I);
-        accumulate(term_sign, acc, cur, I);
+        accumulate(term_sign, acc, cur, I, nullptr, horner && p.col_top[j] >= 1);
         os << ind << "}\n";
     }
 
     // acc += term_sign * (product of level 0) * S_1   (one FMA)
     void accumulate(int term_sign, int acc, std::map<int, std::string> &cur, const char *I,
-                    const char *weight = nullptr) {
+                    const char *weight = nullptr, bool fresh_run = false) {
         if (p.pair0) {
             // the pair (-1)^i S_1 (P(x) - P(x + a)) over column 0's rows: one
             // row r gives -a_r; two rows r, s give -(a_r x_s + a_s x_r + a_r a_s)
@@ -250,6 +328,8 @@ struct Gen {
             std::string d;
             if (B.colptr[1] - q0 == 1) {
                 d = "(" + lit(B.val[q0]) + ")";
+            } else if (dtrack) {
+                d = "dp";
             } else {
                 // r in the inner FMA, t in the outer (the plan puts there the
                 // row that more often changes)
@@ -268,6 +348,14 @@ struct Gen {
             // term_sign * (-d) * S_1; exact mode: d is an integer (y units,
             // within the sub-product bound), so its residue is d R_1
             const char *sg = term_sign < 0 ? "" : "-";
+            if (horner) {
+                // the pair's bracket starts c_0 (after a flush) or adds to it
+                if (fresh_run)
+                    os << I << "c0 = " << sg << d << ";\n";
+                else
+                    os << I << "c0 = c0 + " << sg << d << ";\n";
+                return;
+            }
             os << I << "acc" << acc << " = fma(" << sg << d << ", S1, acc" << acc << ");\n";
             if (p.exact) {
                 os << I << "racc = fma(" << sg << d << ", R1, racc);\n";
@@ -340,19 +428,27 @@ struct Gen {
         dyn_lo = lo;
         dyn_hi = hi;
         std::vector<char> used(p.n, 0);
-        for (int j = lo; j <= hi; ++j)
+        dyn_dslot = -1;
+        bool dtouch = false;
+        for (int j = lo; j <= hi; ++j) {
             for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) used[B.rowidx[q]] = 1;
+            dtouch = dtouch || touches_level0(j);
+        }
         dyn_rows.clear();
         for (int r = 0; r < p.n; ++r)
-            if (used[r]) dyn_rows.push_back(r);
-        if (dyn_rows.empty()) return;
-        const size_t R = dyn_rows.size();
+            if (used[r] && !(horner && p.row_level[r] == 0)) dyn_rows.push_back(r);
+        // with bracket tracking, one more slot per column: the bracket's change
+        if (dtrack && dtouch) dyn_dslot = (int)dyn_rows.size();
+        const size_t R = dyn_rows.size() + (dyn_dslot >= 0 ? 1 : 0);
+        if (R == 0) return;
         std::vector<double> tab((size_t)(hi - lo + 2) * R, 0.0);
         std::vector<int> slot(p.n, -1);
-        for (size_t i = 0; i < R; ++i) slot[dyn_rows[i]] = (int)i;
-        for (int j = lo; j <= hi; ++j)
+        for (size_t i = 0; i < dyn_rows.size(); ++i) slot[dyn_rows[i]] = (int)i;
+        for (int j = lo; j <= hi; ++j) {
             for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q)
-                tab[(size_t)(j - lo) * R + slot[B.rowidx[q]]] = B.val[q];
+                if (slot[B.rowidx[q]] >= 0) tab[(size_t)(j - lo) * R + slot[B.rowidx[q]]] = B.val[q];
+            if (dyn_dslot >= 0) tab[(size_t)(j - lo) * R + dyn_dslot] = bracket_delta(j);
+        }
         os << "__constant__ double dyn_tab[" << tab.size() << "] = {";
         for (size_t i = 0; i < tab.size(); ++i) os << (i ? "," : "") << (i % 8 ? " " : "\n  ") << lit(tab[i]);
         os << "};\n";
@@ -365,11 +461,12 @@ struct Gen {
     int dyn_flip(const char *jvar, const char *svar, std::map<int, std::string> &cur, const char *I) {
         int top_max = 0;
         for (int j = dyn_lo; j <= dyn_hi; ++j) top_max = std::max(top_max, p.col_top[j]);
-        if (dyn_rows.empty()) return top_max;
-        const size_t R = dyn_rows.size();
+        const size_t R = dyn_rows.size() + (dyn_dslot >= 0 ? 1 : 0);
+        if (R == 0) return top_max;
         const std::string tp = fresh();
         os << I << "const double* " << tp << " = dyn_tab + (u32)(" << jvar << " - " << dyn_lo << ") * " << R << "u;\n";
-        for (size_t i = 0; i < R; ++i) {
+        if (dyn_dslot >= 0) os << I << "dp = fma(" << svar << ", " << tp << "[" << dyn_dslot << "], dp);\n";
+        for (size_t i = 0; i < dyn_rows.size(); ++i) {
             const int r = dyn_rows[i];
             std::string target;
             if (r < p.k) {
@@ -414,6 +511,9 @@ struct Gen {
         // (column-0 pairing: paired steps flipping columns 1 ..)
         const int c0 = p.pair0 ? 1 : 0;
         const int kw = kappa - c0;
+        horner = p.pair0 && !p.exact && !p.cold && L >= 2;
+        dtrack = horner && p.B.colptr[1] - p.B.colptr[0] == 2;
+        cz.assign(L, 0);
         const uint64_t DW = DELTA >> c0;
         const unsigned evm = 1u << c0;  // Gray terms per walked step
         os << "// generated by libperm_mi355x: n=" << n << " nnz=" << p.nnz << " k=" << k << " c=" << p.c
@@ -561,13 +661,31 @@ struct Gen {
                 continue;
             }
             std::vector<std::string> v = level_values(l, cur, "  ");
+            if (horner) {
+                const std::string pr = product(v, "  ");
+                os << "  double P" << l << " = " << pr << ";\n";
+                continue;
+            }
             if (l + 1 < L) v.push_back("S" + std::to_string(l + 1));
             std::string prod = product(v, "  ");
             os << "  double S" << l << " = " << prod << ";\n";
         }
         os << "  double acc0 = 0.0, acc1 = 0.0;\n";
         if (p.exact) os << "  double racc = 0.0, accA = 0.0;\n";
-        accumulate(+1, 0, cur, "  ");  // term g = m 2^kappa (even index: sign +)
+        if (dtrack) {
+            double cr, cs;
+            bracket_coeffs(cr, cs);
+            os << "  double dp = fma(" << lit(cs) << ", " << value_of(p.pair_s, cur, "  ") << ", fma(" << lit(cr) << ", "
+               << value_of(p.pair_r, cur, "  ") << ", " << lit(cr * cs) << "));\n";
+        }
+        if (horner) {
+            // every accumulator live and zero at the top of the loop
+            os << "  double c0 = 0.0";
+            for (int l = 1; l < L; ++l) os << ", c" << l << " = 0.0";
+            os << ";\n";
+            std::fill(cz.begin(), cz.end(), 0);
+        }
+        accumulate(+1, 0, cur, "  ", nullptr, true);  // term g = m 2^kappa (even index: sign +)
         // ---- Gray loop over local steps 1 .. 2^kappa - 1 ----
         if (kappa >= 1) {
             os << "  const double lsgn = (m & 1ull) ? -1.0 : 1.0;  // direction at local step 2^(kappa-1)\n";
@@ -709,13 +827,21 @@ struct Gen {
                 os << I2 << "const double sg = (jj == " << kappa - 1 << ") ? lsgn : sgu;\n";
                 std::map<int, std::string> cur;
                 walk_s_only = lazy_r;
+                if (horner) flush_to(loop_top, I2);
                 const int top_max = dyn_flip("jj", "sg", cur, I2);
                 for (int l = top_max; l >= 1; --l) refresh_level(l, cur, I2);
-                accumulate(1, 1, cur, I2, "w");
+                accumulate(1, 1, cur, I2, "w", horner && loop_top >= 1);
                 walk_s_only = false;
                 os << ind << "}\n";
             };
             if (!tree) {
+                if (horner && u + 1 <= kw - 1) {
+                    // the accumulators empty at the loop's top (and at its end)
+                    loop_top = 0;
+                    for (int j = dyn_lo; j <= dyn_hi; ++j) loop_top = std::max(loop_top, p.col_top[j]);
+                    for (int j = c0; j <= u + c0; ++j) loop_top = std::max(loop_top, p.col_top[j]);
+                    for (int l = 1; l < loop_top; ++l) cz[l] = 1;
+                }
                 os << "#pragma clang loop unroll(disable)\n";
                 os << "  for (u32 base = 0; base < " << DW << "u; base += " << 2 * U << "u) {\n";
                 block_pair("base", "    ");
@@ -769,6 +895,11 @@ struct Gen {
         if (p.exact) {
             reduce_racc("  ");
             os << "  xo[0] = racc; xo[1] = accA;\n";
+        }
+        if (horner) {
+            // everything up to the top level: c_{L-1} is the chunk's sum
+            flush_to(L - 1, "  ");
+            os << "  acc0 = c" << L - 1 << ";\n";
         }
         os << "  return two_sum(acc0, acc1);\n}\n";
         // ---- the kernel: one chunk per lane, then a deterministic reduction

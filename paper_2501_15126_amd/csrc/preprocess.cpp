@@ -468,24 +468,40 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         // updates its rows, refreshes the levels above 0 as before, forms
         // P(x) - P(x + a) of level 0 only when the column touches level 0
         // (else the compiler reuses it: two FMAs for two rows, a literal for
-        // one) and adds the pair with one FMA.  Each FMA of the two-row
-        // difference and the accumulate does a multiply and an add the sum
-        // needs (2 flops each).
+        // one) and adds the pair with one FMA (exact mode) or through the
+        // nested accumulators (FP64).  Each FMA of the two-row difference,
+        // the accumulate and the accumulators' moves does a multiply and an
+        // add the sum needs (2 flops each).
         const int d0 = B.colptr[1] - B.colptr[0];
+        const bool nest = !ex && L >= 2;
         double pops = 0.0, pfl = 0.0, pxo = 0.0;
         for (int j = 1; j < n - 1; ++j) {
             const int t = p->col_top[j];
             std::fill(touched.begin(), touched.end(), 0);
             for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) touched[p->row_level[B.rowidx[q]]] = 1;
-            double oj = B.colptr[j + 1] - B.colptr[j];
+            // x updates (nested accumulation: level 0 lives in the bracket)
+            double oj = 0.0;
+            for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q)
+                if (!nest || p->row_level[B.rowidx[q]] != 0) oj += 1.0;
             for (int l = 1; l <= t; ++l)
                 if (touched[l]) oj += std::max(0, level_size[l] - 1);
-            for (int l = 1; l <= t; ++l)
-                if (l < L - 1) oj += 1;
+            if (nest) {
+                // nested accumulation: c_0 .. c_{t-1} move up through the
+                // level products (t operations) and the bracket starts c_0;
+                // with no level above 0 touched, the bracket adds to c_0
+                oj += t > 0 ? t : 1;
+            } else {
+                for (int l = 1; l <= t; ++l)
+                    if (l < L - 1) oj += 1;  // chain multiply by S_{l+1}
+                oj += 1;                     // accumulate: fma(bracket, S_1, acc)
+            }
             // the bracket fma(a_r, x_s, fma(a_s, x_r, a_r a_s)): the inner
-            // FMA only when x_r changed, the outer when either did
+            // FMA only when x_r changed, the outer when either did; nested
+            // accumulation keeps the bracket itself (one add of a constant)
             double bops = 0.0;
-            if (d0 == 2) {
+            if (nest) {
+                if (d0 == 2 && touched[0]) oj += 1.0;
+            } else if (d0 == 2) {
                 bool tr = false, ts = false;
                 for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) {
                     tr = tr || B.rowidx[q] == p->pair_r;
@@ -493,7 +509,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
                 }
                 bops = tr ? 2.0 : ts ? 1.0 : 0.0;
             }
-            oj += bops + 1.0;
+            oj += bops;
             const double cnt = std::ldexp(1.0, n - j - 2);
             double xo = 0.0;
             if (ex) {
@@ -508,7 +524,34 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
             }
             p->ops_of_col[j] = oj;
             pops += cnt * oj;
-            pfl += cnt * (oj + 1.0 + bops);
+            pfl += cnt * (oj + bops + (nest ? 0.0 : 1.0));
+        }
+        if (nest) {
+            // the moves that are FMAs (2 flops; a move into an empty c_l is a
+            // multiply): a step reaching level l >= 1 finds c_l live when the
+            // last earlier step reaching level l stopped there.  Counted over
+            // the paired walk's column sequence (step i flips column
+            // ctz(i) + 1), built as R_m = R_{m-1}, m, R_{m-1}: per segment
+            // its first and last step reaching level l and the live finds.
+            struct Seg {
+                int first, last;
+                double live;
+            };
+            for (int l = 1; l < L; ++l) {
+                auto cat = [&](const Seg &a, const Seg &b) {
+                    Seg r;
+                    r.live = a.live + b.live + ((a.last > 0 && b.first > 0 && p->col_top[a.last] == l) ? 1.0 : 0.0);
+                    r.first = a.first > 0 ? a.first : b.first;
+                    r.last = b.last > 0 ? b.last : a.last;
+                    return r;
+                };
+                Seg r{0, 0, 0.0};
+                for (int m = 1; m < n - 1; ++m) {
+                    const int e = p->col_top[m] >= l ? m : 0;
+                    r = cat(cat(r, Seg{e, e, 0.0}), r);
+                }
+                pfl += r.live;
+            }
         }
         p->ops_of_col[0] = 0.0;
         p->ops_per_step = pops / steps;

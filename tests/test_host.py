@@ -597,10 +597,21 @@ def test_column0_pairing_on_cpu(P, oracle_mod):
     # a batch-workload matrix whose column 0 holds one negative entry (the
     # pair's bracket is then that literal, negated)
     cases += [(W.batch_matrix(7, 16), 8, 6)]
+    # real and signed entries where column 0 has two: the bracket is kept
+    # and moved by constants, in the static steps and through the table
+    cases += [(W.random_sparse(13, 0.25, 0, kind="real"), 9, 2), (W.random_sparse(15, 0.2, 0, kind="signed"), 11, 2)]
     for ccs, kappa, u in cases:
         ref, abs_sum = O.perm_nw(ccs)
         opts = dict(chunk_log2=kappa, unroll_log2=u, zero_skip=False, exact=False)
-        assert "pair0" in P.perm_codegen(ccs, **opts).splitlines()[0], (ccs[0], kappa, u)
+        src = P.perm_codegen(ccs, **opts)
+        assert "pair0" in src.splitlines()[0], (ccs[0], kappa, u)
+        # with two levels or more the terms go through per-level accumulators
+        # (c_{L-1}, the top one, holds the chunk's sum)
+        L = P.compile_info(ccs, **opts)["levels"]
+        if L >= 2:
+            assert "double c0 = 0.0" in src and f"acc0 = c{L - 1};" in src
+        if (kappa, u) in ((9, 2), (11, 2)):
+            assert "double dp = " in src and "dp = fma(sg, " in src and re.search(r"dp [+-]= ", src)
         got, info = _emulate(P, ccs, **opts)
         assert info["evaluated"] == 1 << (ccs[0] - 1)
         assert abs(got - ref) <= 1e-13 * abs_sum + 1e-15, (ccs[0], kappa, u, got, ref)
