@@ -77,7 +77,9 @@ typedef enum { PERM_MODE_AUTO = 0, PERM_MODE_PURE = 1, PERM_MODE_HYBRID = 2 } pe
 typedef struct {
     int32_t mode;          /* perm_mode */
     int32_t chunk_log2;    /* log2 of Gray steps per lane chunk; 0 = automatic */
-    int32_t unroll_log2;   /* log2 of the static unrolled block; 0 = automatic */
+    int32_t unroll_log2;   /* log2 of the static unrolled block; 0 = automatic (7, zero-aware
+                              kernels 6, FP64 kernels with column-0 pairing 9; always at most
+                              chunk_log2 - 1, paired kernels chunk_log2 - 2) */
     int32_t block;         /* threads per workgroup, multiple of 64, <= 1024; 0 = 256 */
     int32_t vgpr_budget;   /* target VGPRs per lane for the level plan; 0 = 128 */
     int32_t force_k;       /* > 0: override Alg. 5's k (HYBRID only), with force_c */
@@ -142,7 +144,14 @@ typedef struct {
                               1 = required (PERM_EINVAL otherwise), -1 = off (FP64 only) */
     int32_t exact_passes;  /* exact mode: run at least this many passes (primes), 1..3;
                               0 = as many as the certificate needs */
-    int32_t pad2;
+    int32_t copy_cols;     /* FP64 all-terms kernels with column-0 pairing: the rows of the
+                              walk's m most frequent columns are kept in 2^(columns touching
+                              them) copies (each with those columns' entries in or out), so
+                              that flipping one of them only selects other copies, and the
+                              other flips move every copy.  0 = the m (up to unroll_log2)
+                              with the fewest FP64 operations in the generator's count whose
+                              copies stay within 112 doubles per lane, 1..9 = that m (at
+                              most unroll_log2), -1 = none */
 } perm_opts;
 
 /* Statistics of one call (all optional to read). */

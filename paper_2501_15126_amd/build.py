@@ -57,7 +57,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed")
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
-                    "-L/opt/rocm/lib", "-lhiprtc", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"], check=True)
+                    "-L/opt/rocm/lib", "-lhiprtc", "-lamd_comgr", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"], check=True)
     os.replace(tmp, LIB)
     return LIB
 

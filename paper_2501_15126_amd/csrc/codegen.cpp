@@ -36,6 +36,7 @@
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <set>
 #include <sstream>
 
 #include "perm_internal.h"
@@ -108,6 +109,121 @@ struct Gen {
     bool dtrack = false;
     int dyn_dslot = -1;  // slot of the bracket's change in the dynamic table
 
+    // Copies over columns 1..m (the walk's most frequent flips; m =
+    // copy_cols): row r at a level >= 1 is kept once per subset sigma of
+    // Tr[r], the columns <= m touching it (x<r> for none, x<r>_<sigma> with
+    // those columns' entries added), level l once per subset of Tl[l] (P<l>,
+    // P<l>_<sigma>), the bracket once per subset of T0 (dp, dp_<sigma>).  ts
+    // is the set of those columns in x where a step is emitted (none at
+    // every chunk start, loop top and dynamic step); a flip of column c <= m
+    // only toggles bit c-1 of ts, and every other flip moves every copy.
+    int cm = 0;
+    unsigned ts = 0u, T0 = 0u;
+    // Levels whose rows changed since their products were last formed (the
+    // nested-accumulation kernels form only those again).
+    std::vector<char> dirty;
+    void touch_row(int r) {
+        if (horner && r < p.n && p.row_level[r] >= 1) dirty[p.row_level[r]] = 1;
+    }
+    std::vector<unsigned> Tr, Tl;
+    static std::string sub(const std::string &base, unsigned sigma) {
+        return sigma ? base + "_" + std::to_string(sigma) : base;
+    }
+    // every subset of T (the empty one first)
+    static std::vector<unsigned> subsets(unsigned T) {
+        std::vector<unsigned> v;
+        for (unsigned sg = 0;; sg = (sg - T) & T) {  // next subset in increasing order
+            v.push_back(sg);
+            if (sg == T) break;
+        }
+        return v;
+    }
+    std::string xv(int r, unsigned sigma) const { return sub(xname(r), sigma & Tr[r]); }
+    std::string pname(int l) const { return sub("P" + std::to_string(l), ts & Tl[l]); }
+    std::string dname() const { return sub("dp", ts & T0); }
+
+    // ---- FP64 operations of the step loop (nested-accumulation kernels) ----
+    // Each FP64 operation the loop emits is noted with its operands: a value
+    // is named by its operation and its operands' values, and it varies in
+    // the loop when an operand does (every name the loop assigns varies at
+    // its top).  An operation on values that do not vary is hoisted out of
+    // the loop by the compiler and one that this iteration already computed
+    // is reused, so only the others are counted.  Without a loop (one pass
+    // per chunk) every distinct operation is counted.
+    bool track = false, counting = false, all_vary = false;
+    double loop_ops = -1, loop_flops = -1;  // per Gray term, when counted
+    double loop_terms = 0;                  // Gray terms per iteration
+    uint64_t loop_iters = 0;
+    int sign_fmas = 0;                      // table-entry FMAs per iteration
+    std::map<std::string, std::pair<std::string, bool>> vid;  // name -> (value, varies)
+    std::set<std::string> seen, assigned;
+    double cnt_ops = 0, cnt_flops = 0;
+    std::pair<std::string, bool> val(const std::string &name) const {
+        auto it = vid.find(name);
+        return it != vid.end() ? it->second : std::make_pair(name, false);
+    }
+    // +1 or -1 if the value is that constant (a literal, or its sign), else 0
+    std::map<std::string, int> unit;
+    int unit_of(const std::string &name) const {
+        auto it = unit.find(name);
+        if (it != unit.end()) return it->second;
+        std::string t = name;
+        while (t.size() > 2 && t.front() == '(' && t.back() == ')') t = t.substr(1, t.size() - 2);
+        if (t == "0x1p+0") return 1;
+        if (t == "-0x1p+0") return -1;
+        return 0;
+    }
+    void note(const std::string &lhs, const char *op, std::initializer_list<std::string> args, int flops,
+              bool free = false) {
+        if (!track) return;
+        // a product with a factor +-1 is a sign (folded into its use), an
+        // FMA with one a plain add
+        const std::vector<std::string> av(args);
+        const std::string sop(op);
+        if (sop == "mul" && av.size() == 2 && (unit_of(av[0]) || unit_of(av[1]))) {
+            const int u0 = unit_of(av[0]), u1 = unit_of(av[1]);
+            const std::string &other = u0 ? av[1] : av[0];
+            const int sgn = u0 ? u0 : u1;
+            vid[lhs] = {std::string(sgn > 0 ? "id(" : "neg(") + val(other).first + ")", val(other).second};
+            unit[lhs] = unit_of(other) * sgn;
+            assigned.insert(lhs);
+            return;
+        }
+        if (sop == "fma" && (unit_of(av[0]) || unit_of(av[1]))) flops = 1;
+        if (sop == "neg" || sop == "id") unit[lhs] = (sop == "neg" ? -1 : 1) * unit_of(av[0]);
+        else unit.erase(lhs);
+        std::string id = std::string(op) + "(";
+        bool vary = all_vary;
+        for (const std::string &a : args) {
+            const auto v = val(a);
+            id += v.first + ",";
+            vary = vary || v.second;
+        }
+        id += ")";
+        if (counting && vary && seen.insert(id).second && !free) {
+            cnt_ops += 1;
+            cnt_flops += flops;
+        }
+        vid[lhs] = {id, vary};
+        assigned.insert(lhs);
+    }
+    // a value that costs no operation of its own (a sign folded into its use)
+    void derive(const std::string &lhs, const char *op, std::initializer_list<std::string> args) {
+        note(lhs, op, args, 0, true);
+    }
+    void alias(const std::string &lhs, const std::string &rhs) {
+        if (!track) return;
+        vid[lhs] = val(rhs);
+        if (unit_of(rhs)) unit[lhs] = unit_of(rhs); else unit.erase(lhs);
+        assigned.insert(lhs);
+    }
+    void varies(const std::string &name) {
+        if (!track) return;
+        unit.erase(name);
+        vid[name] = {"(" + name + ")", true};
+        assigned.insert(name);
+    }
+
     // Coefficients of x_r and x_s in the bracket and the bracket at x.
     void bracket_coeffs(double &cr, double &cs) const {
         const Ccs &B = p.B;
@@ -138,10 +254,14 @@ struct Gen {
     // c_0 .. c_{t-1} into c_t through the current products.
     void flush_to(int t, const char *I) {
         for (int l = 1; l <= t; ++l) {
-            if (cz[l])
-                os << I << "c" << l << " = c" << l - 1 << " * P" << l << ";\n";
-            else
-                os << I << "c" << l << " = fma(c" << l - 1 << ", P" << l << ", c" << l << ");\n";
+            const std::string cl = "c" + std::to_string(l), cb = "c" + std::to_string(l - 1);
+            if (cz[l]) {
+                os << I << cl << " = " << cb << " * " << pname(l) << ";\n";
+                note(cl, "mul", {cb, pname(l)}, 1);
+            } else {
+                os << I << cl << " = fma(" << cb << ", " << pname(l) << ", " << cl << ");\n";
+                note(cl, "fma", {cb, pname(l), cl}, 2);
+            }
             cz[l] = 0;
             if (l >= 2) cz[l - 1] = 1;
         }
@@ -162,6 +282,7 @@ struct Gen {
             for (size_t i = 0; i + 1 < vals.size(); i += 2) {
                 std::string t = fresh();
                 os << ind << "const double " << t << " = " << vals[i] << " * " << vals[i + 1] << ";\n";
+                note(t, "mul", {vals[i], vals[i + 1]}, 1);
                 next.push_back(t);
             }
             if (vals.size() % 2) next.push_back(vals.back());
@@ -186,6 +307,14 @@ struct Gen {
     std::vector<std::string> level_values(int l, std::map<int, std::string> &cur, const char *ind) {
         std::vector<std::string> v;
         for (int r : level_rows[l]) v.push_back(value_of(r, cur, ind));
+        return v;
+    }
+
+    // The same in copy sigma (columns <= m in sigma added).
+    std::vector<std::string> level_values_in(int l, unsigned sigma, std::map<int, std::string> &cur,
+                                             const char *ind) {
+        std::vector<std::string> v;
+        for (int r : level_rows[l]) v.push_back(Tr[r] & sigma ? xv(r, sigma) : value_of(r, cur, ind));
         return v;
     }
 
@@ -232,11 +361,17 @@ struct Gen {
     // cold rows are recorded in `cur`.
     void update(int j, Sign sg, std::map<int, std::string> &cur, const char *I) {
         const Ccs &B = p.B;
-        if (dtrack && touches_level0(j)) emit_add("dp", lit(bracket_delta(j)), sg, I);
+        if (dtrack && touches_level0(j)) {
+            for (unsigned sgm : subsets(T0)) emit_add(sub("dp", sgm), lit(bracket_delta(j)), sg, I);
+        }
         for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) {
             const int r = B.rowidx[q];
             if (horner && p.row_level[r] == 0) continue;  // level 0 lives in the bracket
+            touch_row(r);
             const std::string a = lit(B.val[q]);
+            if (cm && Tr[r])
+                for (unsigned sgm : subsets(Tr[r]))
+                    if (sgm) emit_add(xv(r, sgm), a, sg, I);
             std::string target;
             if (r < p.k) {
                 target = xname(r);
@@ -260,6 +395,8 @@ struct Gen {
             os << I << target << " += (neg ? -(" << a << ") : (" << a << "));\n";
         else
             os << I << target << " = fma(lsgn, " << a << ", " << target << ");\n";
+        note(target, sg == Sign::Plus ? "add" : sg == Sign::Minus ? "sub" : sg == Sign::Uniform ? "addu" : "addl",
+             {target, a, sg == Sign::Uniform ? "neg" : "lsgn"}, 1);
     }
 
     // Recompute the cached product of level l: S_l = prod(level l) * S_{l+1}.
@@ -277,10 +414,20 @@ struct Gen {
             os << I << "R" << l << " = " << r << ";\n";
             return;
         }
+        if (horner && !dirty[l]) return;  // its products are current
+        if (horner) dirty[l] = 0;
         std::vector<std::string> v = level_values(l, cur, I);
         if (horner) {
             const std::string pr = product(v, I);
             os << I << "P" << l << " = " << pr << ";\n";
+            alias("P" + std::to_string(l), pr);
+            if (cm)
+                for (unsigned sgm : subsets(Tl[l])) {
+                    if (!sgm) continue;
+                    const std::string pi = product(level_values_in(l, sgm, cur, I), I);
+                    os << I << sub("P" + std::to_string(l), sgm) << " = " << pi << ";\n";
+                    alias(sub("P" + std::to_string(l), sgm), pi);
+                }
             return;
         }
         if (l + 1 < p.nlevels) v.push_back("S" + std::to_string(l + 1));
@@ -311,8 +458,16 @@ struct Gen {
         std::string in = std::string(ind) + "  ";
         const char *I = in.c_str();
         if (horner) flush_to(p.col_top[j], I);
-        update(j, sg, cur, I);
-        for (int l = p.col_top[j]; l >= 1; --l) refresh_level(l, cur, I);
+        if (j >= 1 && j <= cm) {
+            // column j in (Plus) or out (Minus): other copies become current
+            const unsigned bit = 1u << (j - 1);
+            if ((sg == Sign::Plus) != !(ts & bit) || (sg != Sign::Plus && sg != Sign::Minus))
+                os << "#error copies of x out of step\n";  // a generator fault: fail to compile
+            ts ^= bit;
+        } else {
+            update(j, sg, cur, I);
+            for (int l = p.col_top[j]; l >= 1; --l) refresh_level(l, cur, I);
+        }
         accumulate(term_sign, acc, cur, I, nullptr, horner && p.col_top[j] >= 1);
         os << ind << "}\n";
     }
@@ -329,7 +484,7 @@ struct Gen {
             if (B.colptr[1] - q0 == 1) {
                 d = "(" + lit(B.val[q0]) + ")";
             } else if (dtrack) {
-                d = "dp";
+                d = dname();
             } else {
                 // r in the inner FMA, t in the outer (the plan puts there the
                 // row that more often changes)
@@ -343,6 +498,7 @@ struct Gen {
             if (weight) {
                 const std::string dw = fresh();
                 os << I << "const double " << dw << " = " << d << " * " << weight << ";\n";
+                note(dw, "mul", {d, weight}, 1);
                 d = dw;
             }
             // term_sign * (-d) * S_1; exact mode: d is an integer (y units,
@@ -350,10 +506,13 @@ struct Gen {
             const char *sg = term_sign < 0 ? "" : "-";
             if (horner) {
                 // the pair's bracket starts c_0 (after a flush) or adds to it
-                if (fresh_run)
+                if (fresh_run) {
                     os << I << "c0 = " << sg << d << ";\n";
-                else
+                    derive("c0", *sg ? "neg" : "id", {d});  // a sign the consumer folds in
+                } else {
                     os << I << "c0 = c0 + " << sg << d << ";\n";
+                    note("c0", *sg ? "subc" : "addc", {"c0", d}, 1);
+                }
                 return;
             }
             os << I << "acc" << acc << " = fma(" << sg << d << ", S1, acc" << acc << ");\n";
@@ -465,9 +624,17 @@ struct Gen {
         if (R == 0) return top_max;
         const std::string tp = fresh();
         os << I << "const double* " << tp << " = dyn_tab + (u32)(" << jvar << " - " << dyn_lo << ") * " << R << "u;\n";
-        if (dyn_dslot >= 0) os << I << "dp = fma(" << svar << ", " << tp << "[" << dyn_dslot << "], dp);\n";
+        varies(tp);
+        if (dyn_dslot >= 0)
+            for (unsigned sgm : subsets(T0)) {
+                const std::string d = sub("dp", sgm);
+                os << I << d << " = fma(" << svar << ", " << tp << "[" << dyn_dslot << "], " << d << ");\n";
+                note(d, "fma", {svar, tp + std::to_string(dyn_dslot), d}, 1);
+                if (counting) ++sign_fmas;
+            }
         for (size_t i = 0; i < dyn_rows.size(); ++i) {
             const int r = dyn_rows[i];
+            touch_row(r);
             std::string target;
             if (r < p.k) {
                 target = xname(r);
@@ -477,6 +644,16 @@ struct Gen {
                 cur[r] = target;
             }
             os << I << target << " = fma(" << svar << ", " << tp << "[" << i << "], " << target << ");\n";
+            note(target, "fma", {svar, tp, std::to_string(i), target}, 1);
+            if (counting) ++sign_fmas;
+            if (cm && r < p.k && Tr[r])
+                for (unsigned sgm : subsets(Tr[r])) {
+                    if (!sgm) continue;
+                    const std::string x = xv(r, sgm);
+                    os << I << x << " = fma(" << svar << ", " << tp << "[" << i << "], " << x << ");\n";
+                    note(x, "fma", {svar, tp, std::to_string(i), x}, 1);
+                    if (counting) ++sign_fmas;
+                }
             if (r >= p.k) os << I << cold_addr(r) << " = " << target << ";\n";
         }
         return top_max;
@@ -513,12 +690,28 @@ struct Gen {
         const int kw = kappa - c0;
         horner = p.pair0 && !p.exact && !p.cold && L >= 2;
         dtrack = horner && p.B.colptr[1] - p.B.colptr[0] == 2;
+        cm = horner ? p.copy_cols : 0;
+        dirty.assign(L, 0);
+        ts = 0u;
+        T0 = 0u;
+        Tr.assign(n, 0u);
+        Tl.assign(L, 0u);
+        for (int c = 1; c <= cm; ++c)
+            for (int q = B.colptr[c]; q < B.colptr[c + 1]; ++q) {
+                const int r = B.rowidx[q];
+                if (p.row_level[r] == 0) {
+                    if (dtrack) T0 |= 1u << (c - 1);
+                } else {
+                    Tr[r] |= 1u << (c - 1);
+                    Tl[p.row_level[r]] |= 1u << (c - 1);
+                }
+            }
         cz.assign(L, 0);
         const uint64_t DW = DELTA >> c0;
         const unsigned evm = 1u << c0;  // Gray terms per walked step
         os << "// generated by libperm_mi355x: n=" << n << " nnz=" << p.nnz << " k=" << k << " c=" << p.c
            << " levels=" << L << " kappa=" << kappa << " u=" << u << " block=" << p.block
-           << (p.pair0 ? " pair0" : "") << "\n";
+           << (p.pair0 ? " pair0" : "") << (cm ? " copies=" + std::to_string(cm) : "") << "\n";
         os << "typedef unsigned long long u64;\n"
               "typedef unsigned int u32;\n"
               "struct dd { double h, l; };\n"
@@ -651,6 +844,19 @@ struct Gen {
             os << "  " << cold_addr(r) << " = cx" << r << ";\n";
             cur[r] = "cx" + std::to_string(r);
         }
+        if (cm) {
+            // columns 1..m are out of x at every chunk start; the other copies
+            for (int r = 0; r < n; ++r)
+                for (unsigned sgm : subsets(Tr[r])) {
+                    if (!sgm) continue;
+                    double add = 0.0;
+                    for (int c = 1; c <= cm; ++c)
+                        if (sgm & (1u << (c - 1)))
+                            for (int q = B.colptr[c]; q < B.colptr[c + 1]; ++q)
+                                if (B.rowidx[q] == r) add += B.val[q];
+                    os << "  double " << xv(r, sgm) << " = " << xname(r) << " + " << lit(add) << ";\n";
+                }
+        }
         for (int l = L - 1; l >= 1; --l) {
             if (p.exact) {
                 const std::vector<std::string> qs = part_products(l, cur, "  ");
@@ -664,6 +870,11 @@ struct Gen {
             if (horner) {
                 const std::string pr = product(v, "  ");
                 os << "  double P" << l << " = " << pr << ";\n";
+                for (unsigned sgm : subsets(Tl[l])) {
+                    if (!sgm) continue;
+                    const std::string pi = product(level_values_in(l, sgm, cur, "  "), "  ");
+                    os << "  double " << sub("P" + std::to_string(l), sgm) << " = " << pi << ";\n";
+                }
                 continue;
             }
             if (l + 1 < L) v.push_back("S" + std::to_string(l + 1));
@@ -677,6 +888,13 @@ struct Gen {
             bracket_coeffs(cr, cs);
             os << "  double dp = fma(" << lit(cs) << ", " << value_of(p.pair_s, cur, "  ") << ", fma(" << lit(cr) << ", "
                << value_of(p.pair_r, cur, "  ") << ", " << lit(cr * cs) << "));\n";
+            for (unsigned sgm : subsets(T0)) {
+                if (!sgm) continue;
+                double add = 0.0;
+                for (int c = 1; c <= cm; ++c)
+                    if (sgm & (1u << (c - 1))) add += bracket_delta(c);
+                os << "  double " << sub("dp", sgm) << " = dp + " << lit(add) << ";\n";
+            }
         }
         if (horner) {
             // every accumulator live and zero at the top of the loop
@@ -803,6 +1021,7 @@ struct Gen {
                     step(u + c0, Sign::Lane, term_u, 0, bi);
                 } else {
                     os << bi << "{\n" << bi << "  const bool neg = (" << posv << " >> " << (u + 1) << ") & 1u;\n";
+                    varies("neg");
                     step(u + c0, Sign::Uniform, term_u, 0, (std::string(bi) + "  ").c_str());
                     os << bi << "}\n";
                 }
@@ -825,6 +1044,8 @@ struct Gen {
                 os << I2 << "const int jj = jr + " << c0 << ";\n";
                 os << I2 << "const double sgu = ((" << ellv << " >> (jr + 1)) & 1u) ? -1.0 : 1.0;\n";
                 os << I2 << "const double sg = (jj == " << kappa - 1 << ") ? lsgn : sgu;\n";
+                varies("w");
+                varies("sg");
                 std::map<int, std::string> cur;
                 walk_s_only = lazy_r;
                 if (horner) flush_to(loop_top, I2);
@@ -844,11 +1065,52 @@ struct Gen {
                 }
                 os << "#pragma clang loop unroll(disable)\n";
                 os << "  for (u32 base = 0; base < " << DW << "u; base += " << 2 * U << "u) {\n";
-                block_pair("base", "    ");
-                if (u + 1 <= kw - 1) {
-                    os << "    const u32 ell = base + " << 2 * U << "u;\n";
-                    dynamic_step("ell", "    ");
+                auto body = [&]() {
+                    block_pair("base", "    ");
+                    if (u + 1 <= kw - 1) {
+                        os << "    const u32 ell = base + " << 2 * U << "u;\n";
+                        dynamic_step("ell", "    ");
+                    }
+                };
+                if (horner) {
+                    // count the body's operations: a first pass finds the
+                    // names it assigns (they vary at the loop's top), the
+                    // second emits it and counts
+                    const std::string before = os.str();
+                    const int tmp0 = tmp;
+                    const std::vector<char> cz0 = cz;
+                    const unsigned ts0 = ts;
+                    const std::vector<char> dirty0 = dirty;
+                    track = true;
+                    vid.clear();
+                    unit.clear();
+                    assigned.clear();
+                    body();
+                    os.str(before);
+                    os.clear();
+                    os.seekp(0, std::ios_base::end);
+                    tmp = tmp0;
+                    cz = cz0;
+                    ts = ts0;
+                    dirty = dirty0;
+                    vid.clear();
+                    unit.clear();
+                    for (const std::string &a : assigned) vid[a] = {"phi:" + a, true};
+                    seen.clear();
+                    cnt_ops = cnt_flops = 0;
+                    counting = true;
+                    all_vary = DW == (uint64_t)(2 * U);  // one pass: nothing to hoist
+                    body();
+                    counting = track = all_vary = false;
+                    const double terms = (double)(2 * U) * evm;
+                    loop_ops = cnt_ops / terms;
+                    loop_flops = cnt_flops / terms;
+                    loop_terms = terms;
+                    loop_iters = DW / (uint64_t)(2 * U);
+                } else {
+                    body();
                 }
+                if (ts != 0u) os << "#error copies of x not restored by the loop\n";
                 os << "  }\n";
                 os << "  ev += " << evm * (DW / (2 * U) - 1) << "u;  // the dynamic steps\n";
             } else {
@@ -981,9 +1243,24 @@ struct Gen {
 
 }  // namespace
 
-std::string generate_source(const Plan &p) {
+std::string generate_source(const Plan &p, LoopCount *lc) {
     Gen g(p);
-    return g.run();
+    std::string src = g.run();
+    if (lc) {
+        lc->counted = g.loop_ops >= 0;
+        lc->ops_per_step = g.loop_ops;
+        lc->flops_per_step = g.loop_flops;
+        lc->loop = g.loop_iters > 1;
+        lc->terms_per_iter = g.loop_terms;
+        lc->sign_fmas = g.sign_fmas;
+        int cv = 0;
+        for (int r = 0; r < p.n && g.cm; ++r) cv += (1 << __builtin_popcount(g.Tr[r])) - 1;
+        for (int l = 1; l < p.nlevels && g.cm; ++l)
+            if (g.level_rows[l].size() > 1) cv += (1 << __builtin_popcount(g.Tl[l])) - 1;
+        if (g.cm) cv += (1 << __builtin_popcount(g.T0)) - 1;
+        lc->copy_values = cv;
+    }
+    return src;
 }
 
 }  // namespace permx

@@ -4,19 +4,72 @@
 // (Sec. VI-E).  Here the generated source is compiled in-process by hipRTC for
 // gfx950, loaded with hipModuleLoadData, and cached by its source text so that
 // repeated calls on the same matrix and options reuse the code object.
+#include <amd_comgr/amd_comgr.h>
+#include <elf.h>
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
 #include <chrono>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "jit.h"
 
 namespace permx {
 
 namespace {
+
+// ---- FP64 instructions of the main loop, from the machine code ----
+struct Disasm {
+    const std::vector<char> *elf = nullptr;
+    uint64_t base = 0, off = 0, size = 0;  // .text: address, file offset, bytes
+    std::string text;                      // the last instruction
+    uint64_t target = 0;                   // its resolved branch target, if any
+    bool has_target = false;
+};
+
+uint64_t dis_read(uint64_t from, char *to, uint64_t size, void *ud) {
+    Disasm *d = static_cast<Disasm *>(ud);
+    if (from < d->base || from >= d->base + d->size) return 0;
+    const uint64_t n = std::min<uint64_t>(size, d->base + d->size - from);
+    memcpy(to, d->elf->data() + d->off + (from - d->base), n);
+    return n;
+}
+void dis_print(const char *ins, void *ud) { static_cast<Disasm *>(ud)->text = ins; }
+void dis_addr(uint64_t a, void *ud) {
+    Disasm *d = static_cast<Disasm *>(ud);
+    d->target = a;
+    d->has_target = true;
+}
+
+// The .text section of an ELF64 code object: address, file offset, size.
+bool find_text(const std::vector<char> &e, uint64_t *addr, uint64_t *off, uint64_t *size) {
+    if (e.size() < sizeof(Elf64_Ehdr) || memcmp(e.data(), ELFMAG, SELFMAG) != 0) return false;
+    Elf64_Ehdr h;
+    memcpy(&h, e.data(), sizeof h);
+    if (h.e_shoff == 0 || h.e_shentsize != sizeof(Elf64_Shdr) || h.e_shstrndx >= h.e_shnum) return false;
+    if (h.e_shoff + (uint64_t)h.e_shnum * sizeof(Elf64_Shdr) > e.size()) return false;
+    auto sec = [&](int i) {
+        Elf64_Shdr s;
+        memcpy(&s, e.data() + h.e_shoff + (uint64_t)i * sizeof(Elf64_Shdr), sizeof s);
+        return s;
+    };
+    const Elf64_Shdr strs = sec(h.e_shstrndx);
+    for (int i = 0; i < h.e_shnum; ++i) {
+        const Elf64_Shdr s = sec(i);
+        if (strs.sh_offset + s.sh_name + 6 > e.size()) continue;
+        if (strcmp(e.data() + strs.sh_offset + s.sh_name, ".text") != 0) continue;
+        if (s.sh_offset + s.sh_size > e.size()) return false;
+        *addr = s.sh_addr;
+        *off = s.sh_offset;
+        *size = s.sh_size;
+        return true;
+    }
+    return false;
+}
 
 const char *const kRtcOptions[] = {
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
@@ -91,6 +144,7 @@ perm_status compile_source(const std::string &src, CodeObject *out, std::string 
     co.scratch_bytes = (int)msgpack_uint_after(co.code, ".private_segment_fixed_size");
     co.lds_bytes = (int)msgpack_uint_after(co.code, ".group_segment_fixed_size");
     co.vgpr_spills = (int)msgpack_uint_after(co.code, ".vgpr_spill_count");
+    count_loop_fp64(&co);
     co.compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     co.cache_hit = false;
     {
@@ -99,6 +153,65 @@ perm_status compile_source(const std::string &src, CodeObject *out, std::string 
     }
     *out = co;
     return PERM_OK;
+}
+
+void count_loop_fp64(CodeObject *co) {
+    co->loop_add = co->loop_mul = co->loop_fma = -1;
+    Disasm d;
+    d.elf = &co->code;
+    if (!find_text(co->code, &d.base, &d.off, &d.size)) return;
+    amd_comgr_disassembly_info_t info;
+    if (amd_comgr_create_disassembly_info("amdgcn-amd-amdhsa--gfx950", dis_read, dis_print, dis_addr, &info) !=
+        AMD_COMGR_STATUS_SUCCESS)
+        return;
+    // kind of each instruction: 0 other, 1 add, 2 mul, 3 fma; backward branches
+    struct Ins {
+        uint64_t addr;
+        int kind;
+    };
+    std::vector<Ins> ins;
+    std::vector<std::pair<uint64_t, uint64_t>> loops;  // (target, branch address)
+    for (uint64_t a = d.base; a < d.base + d.size;) {
+        uint64_t sz = 0;
+        d.text.clear();
+        d.has_target = false;
+        if (amd_comgr_disassemble_instruction(info, a, &d, &sz) != AMD_COMGR_STATUS_SUCCESS || sz == 0) break;
+        std::string t = d.text;
+        const size_t b = t.find_first_not_of(" \t");
+        t = b == std::string::npos ? "" : t.substr(b);
+        const std::string op = t.substr(0, t.find_first_of(" \t"));
+        int kind = 0;
+        if (op.rfind("v_add_f64", 0) == 0) kind = 1;
+        else if (op.rfind("v_mul_f64", 0) == 0) kind = 2;
+        else if (op.rfind("v_fma_f64", 0) == 0 || op.rfind("v_fmac_f64", 0) == 0) kind = 3;
+        ins.push_back({a, kind});
+        if (d.has_target && d.target <= a && (op.rfind("s_cbranch", 0) == 0 || op == "s_branch"))
+            loops.push_back({d.target, a});
+        a += sz;
+    }
+    amd_comgr_destroy_disassembly_info(info);
+    int best = -1;
+    for (const auto &lp : loops) {
+        int c[4] = {0, 0, 0, 0};
+        for (const Ins &i : ins)
+            if (i.addr >= lp.first && i.addr < lp.second) c[i.kind]++;
+        bool inner = true;  // no other loop with FP64 work inside this one
+        for (const auto &l2 : loops) {
+            if (l2 == lp || l2.first < lp.first || l2.second > lp.second) continue;
+            for (const Ins &i : ins)
+                if (i.addr >= l2.first && i.addr < l2.second && i.kind) {
+                    inner = false;
+                    break;
+                }
+            if (!inner) break;
+        }
+        if (inner && c[1] + c[2] + c[3] > best) {
+            best = c[1] + c[2] + c[3];
+            co->loop_add = c[1];
+            co->loop_mul = c[2];
+            co->loop_fma = c[3];
+        }
+    }
 }
 
 }  // namespace permx

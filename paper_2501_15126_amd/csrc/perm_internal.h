@@ -87,6 +87,11 @@ struct Plan {
     // and a static block is 2^u paired steps.
     bool pair0 = false;
     int pair_r = -1, pair_s = -1;       // column 0's rows: bracket fma(a_r, x_s, fma(a_s, x_r, a_r a_s))
+    // FP64 paired kernels: the rows of columns 1..copy_cols (the walk's most
+    // frequent flips) kept with every combination of those columns' entries
+    // in or out, so that flipping one only selects other copies; chosen by
+    // the operation model (0: none).
+    int copy_cols = 0;
     // Exact mode (integer-valued matrices): B holds 2a, so x is y = 2x, an
     // integer; the kernel also keeps the term sum modulo a prime and the two
     // sums of its error bound (exact.h).  Each level's product is formed from
@@ -110,7 +115,17 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
 void set_last_error(const std::string &msg);
 
 // ---- codegen.cpp -----------------------------------------------------------
-std::string generate_source(const Plan &p);
+// FP64 operations per Gray term of a generated step loop, counted as the
+// code is emitted (nested-accumulation kernels only; see codegen.cpp).
+struct LoopCount {
+    bool counted = false;
+    double ops_per_step = 0, flops_per_step = 0;
+    bool loop = false;          // the step loop runs more than once per chunk
+    double terms_per_iter = 0;  // Gray terms of one loop iteration
+    int sign_fmas = 0;          // FMAs per iteration that add a signed table entry (1 flop each)
+    int copy_values = 0;        // extra doubles the copies of columns 1..copy_cols keep
+};
+std::string generate_source(const Plan &p, LoopCount *lc = nullptr);
 // Kernel entry point name inside every generated module.
 extern const char *const kGrayKernelName;
 

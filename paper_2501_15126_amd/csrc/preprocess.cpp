@@ -151,6 +151,12 @@ int auto_kappa(int n, bool zero_skip) {
 
 int auto_unroll(bool zero_skip) { return zero_skip ? 6 : 7; }
 
+// Copies of the most frequent columns' rows (FP64 paired kernels): at most
+// this many extra doubles per lane in the automatic choice (about half the
+// 512 VGPRs of one wave per SIMD; the measured n = 40 kernels keep 2 waves
+// per SIMD up to about 100).
+constexpr int kMaxCopyValues = 112;
+
 bool integer_valued(const Ccs &a) {
     for (double v : a.val)
         if (v != std::floor(v)) return false;
@@ -371,6 +377,10 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         return PERM_EINVAL;
     }
     p->waves_per_simd = std::max(0, o.waves_per_simd);
+    if (o.copy_cols < -1 || o.copy_cols > 9) {
+        *err = "copy_cols must be -1 (none), 0 (automatic) or 1..9";
+        return PERM_EINVAL;
+    }
     if (!(o.block_queue == -1 || o.block_queue == 0 || o.block_queue == 8 || o.block_queue == 16 ||
           o.block_queue == 32 || o.block_queue == 64)) {
         *err = "block_queue must be -1 (off), 0 (automatic) or 8, 16, 32, 64 slots per wave";
@@ -405,6 +415,9 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         }
         if (ok) {
             p->pair0 = true;
+            // FP64: static blocks of 2^9 paired steps by default (the more of
+            // the walk's columns are static, the more can be kept in copies)
+            if (o.unroll_log2 == 0 && !ex) p->u = 9;
             p->u = std::min(p->u, p->kappa - 2);  // a static block of paired steps fits the chunk's half
             // two entries: the row that lower (more often flipped) columns
             // touch goes in the outer FMA of the bracket, so that a flip of
@@ -526,31 +539,39 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
             pops += cnt * oj;
             pfl += cnt * (oj + bops + (nest ? 0.0 : 1.0));
         }
+        // Copies over columns 1..m (nested accumulation, m <= u; see the
+        // generator): the generator counts the FP64 operations of each
+        // candidate's step loop, which here are far from the per-column sums
+        // above (the flips of columns <= m leave the copies unchanged, so
+        // much of what follows them depends only on values the loop never
+        // changes and is hoisted); the fewest operations win (forced by
+        // copy_cols when set).
+        p->copy_cols = 0;
         if (nest) {
-            // the moves that are FMAs (2 flops; a move into an empty c_l is a
-            // multiply): a step reaching level l >= 1 finds c_l live when the
-            // last earlier step reaching level l stopped there.  Counted over
-            // the paired walk's column sequence (step i flips column
-            // ctz(i) + 1), built as R_m = R_{m-1}, m, R_{m-1}: per segment
-            // its first and last step reaching level l and the live finds.
-            struct Seg {
-                int first, last;
-                double live;
-            };
-            for (int l = 1; l < L; ++l) {
-                auto cat = [&](const Seg &a, const Seg &b) {
-                    Seg r;
-                    r.live = a.live + b.live + ((a.last > 0 && b.first > 0 && p->col_top[a.last] == l) ? 1.0 : 0.0);
-                    r.first = a.first > 0 ? a.first : b.first;
-                    r.last = b.last > 0 ? b.last : a.last;
-                    return r;
-                };
-                Seg r{0, 0, 0.0};
-                for (int m = 1; m < n - 1; ++m) {
-                    const int e = p->col_top[m] >= l ? m : 0;
-                    r = cat(cat(r, Seg{e, e, 0.0}), r);
+            const int mmax = p->u >= 1 ? std::min(p->u, n - 2) : 0;
+            const int want = o.copy_cols < 0 ? 0 : o.copy_cols > 0 ? std::min(o.copy_cols, mmax) : -1;
+            int mbest = -1;
+            LoopCount best;
+            for (int m = 0; m <= mmax; ++m) {
+                if (want >= 0 && m != want) continue;
+                Plan q = *p;
+                q.copy_cols = m;
+                LoopCount lc;
+                generate_source(q, &lc);
+                if (!lc.counted) continue;
+                // a copy column must save at least 1 % of the operations, and
+                // (automatic choice) the copies must fit beside the rest of
+                // the registers: at most kMaxCopyValues doubles
+                if (want < 0 && lc.copy_values > kMaxCopyValues) continue;
+                if (mbest < 0 || lc.ops_per_step < 0.99 * best.ops_per_step) {
+                    mbest = m;
+                    best = lc;
                 }
-                pfl += r.live;
+            }
+            if (mbest >= 0) {
+                p->copy_cols = mbest;
+                pops = best.ops_per_step * steps;
+                pfl = best.flops_per_step * steps;
             }
         }
         p->ops_of_col[0] = 0.0;

@@ -152,8 +152,21 @@ struct Prepared {
     bool singular = false;
     Plan plan;
     std::string src;
+    LoopCount lc;  // the generator's count of the step loop's FP64 operations
     double host_ms = 0;
 };
+
+// Nested-accumulation kernels: the FP64 operations per Gray term that
+// ops_per_step and flops_per_step report are those of the compiled step loop
+// (its FP64 instructions per iteration over the iteration's terms; an FMA
+// counts 2 flops except one adding a signed table entry), which the compiler
+// makes fewer than the generator's count by simplifications of its own.
+void use_compiled_count(Prepared *p, const CodeObject &co) {
+    if (!p->lc.counted || !p->lc.loop || co.loop_add < 0 || p->lc.terms_per_iter <= 0) return;
+    const double t = p->lc.terms_per_iter;
+    p->plan.ops_per_step = (co.loop_add + co.loop_mul + co.loop_fma) / t;
+    p->plan.flops_per_step = (co.loop_add + co.loop_mul + 2.0 * co.loop_fma - p->lc.sign_fmas) / t;
+}
 
 perm_status prepare(const perm_csc *m, const perm_opts &o, Prepared *p, bool want_source, int tau_base = 0) {
     auto t0 = std::chrono::steady_clock::now();
@@ -165,7 +178,7 @@ perm_status prepare(const perm_csc *m, const perm_opts &o, Prepared *p, bool wan
     if (!p->singular || !want_source) {
         s = make_plan(p->a, o, &p->plan, &err, tau_base);
         if (s != PERM_OK) return fail(s, err);
-        if (want_source && !p->singular) p->src = generate_source(p->plan);
+        if (want_source && !p->singular) p->src = generate_source(p->plan, &p->lc);
     }
     p->host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return PERM_OK;
@@ -183,7 +196,7 @@ constexpr int kAutoWavesMaxScratch = 128;
 // dependency and branch latency than the few spilled values cost.  Kernels
 // with LDS-resident rows are left alone (their LDS use already bounds the
 // occupancy).
-perm_status compile_prepared(Prepared *p, const perm_opts &o, CodeObject *co, std::string *err) {
+perm_status compile_prepared_build(Prepared *p, const perm_opts &o, CodeObject *co, std::string *err) {
     perm_status s = compile_source(p->src, co, err);
     if (s != PERM_OK || o.waves_per_simd != 0 || p->plan.cold_lds) return s;
     if (co->vgprs <= 96 || co->vgprs > 168) return PERM_OK;
@@ -200,6 +213,12 @@ perm_status compile_prepared(Prepared *p, const perm_opts &o, CodeObject *co, st
     p->src = std::move(src5);
     *co = std::move(c5);
     return PERM_OK;
+}
+
+perm_status compile_prepared(Prepared *p, const perm_opts &o, CodeObject *co, std::string *err) {
+    const perm_status s = compile_prepared_build(p, o, co, err);
+    if (s == PERM_OK) use_compiled_count(p, *co);
+    return s;
 }
 
 // compile_prepared, then for a HYBRID plan whose partition is not forced:
@@ -285,7 +304,7 @@ bool plan_key(const perm_csc *m, const perm_opts &o, std::string *key) {
     }
     const int32_t f[] = {o.mode,     o.chunk_log2, o.unroll_log2, o.block,     o.vgpr_budget,
                          o.force_k,  o.force_c,    o.max_levels,  o.zero_skip, o.cold_tier,
-                         o.waves_per_simd, o.block_queue, o.exact};
+                         o.waves_per_simd, o.block_queue, o.exact, o.copy_cols};
     put(f, sizeof f);
     put(&o.gr_ratio, sizeof o.gr_ratio);
     return true;

@@ -54,7 +54,7 @@ class PermOpts(ctypes.Structure):
                 ("hip_stream", ctypes.c_void_p), ("block_partials", ctypes.POINTER(ctypes.c_double)),
                 ("block_partials_cap", ctypes.c_int64), ("progress", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
                 ("block_queue", ctypes.c_int32), ("exact", ctypes.c_int32), ("exact_passes", ctypes.c_int32),
-                ("pad2", ctypes.c_int32)]
+                ("copy_cols", ctypes.c_int32)]
 
 
 class PermBatchStats(ctypes.Structure):
@@ -226,7 +226,7 @@ def _stream_handle(stream):
 def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, force_k=0, force_c=0,
               max_levels=0, gr_ratio=0.0, stream=None, zero_skip="auto", batch_mode="streams",
               batch_kappa_shift=0, cold_tier="global", progress=False, waves_per_simd=0,
-              block_queue=True, exact="auto", exact_passes=0):
+              block_queue=True, exact="auto", exact_passes=0, copy_cols=0):
     o = PermOpts()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.chunk_log2, o.unroll_log2, o.block = chunk_log2, unroll_log2, block
@@ -241,6 +241,7 @@ def make_opts(mode="auto", chunk_log2=0, unroll_log2=0, block=0, vgpr_budget=0, 
     o.block_queue = (0 if block_queue is True else -1 if block_queue is False else int(block_queue))
     o.exact = {"auto": 0, True: 1, False: -1}[exact]
     o.exact_passes = exact_passes
+    o.copy_cols = copy_cols
     o.hip_stream = _stream_handle(stream)
     return o
 
@@ -315,7 +316,8 @@ def _opts_kwargs(o):
             "batch_kappa_shift": o.batch_kappa_shift, "cold_tier": {0: "global", 1: "lds"}[o.cold_tier],
             "waves_per_simd": o.waves_per_simd,
             "block_queue": {0: True, -1: False}.get(o.block_queue, o.block_queue),
-            "exact": {0: "auto", 1: True, -1: False}[o.exact], "exact_passes": o.exact_passes}
+            "exact": {0: "auto", 1: True, -1: False}[o.exact], "exact_passes": o.exact_passes,
+            "copy_cols": o.copy_cols}
 
 
 def perm_autotune(ccs, **opts):

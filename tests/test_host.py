@@ -572,6 +572,47 @@ def test_block_queue_on_cpu(P, oracle_mod):
     assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12
 
 
+def _loop_fp64_instructions(src):
+    """FP64 VALU instructions of the generated kernel's step loop (the loop
+    with the most of them) in hipcc's gfx950 assembly of the source, built
+    with the flags the library's hipRTC compile uses."""
+    with tempfile.TemporaryDirectory() as d:
+        f = os.path.join(d, "k.hip")
+        with open(f, "w") as fh:
+            fh.write("#include <hip/hip_runtime.h>\n" + src)
+        subprocess.run([os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc"),
+                        "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
+                        "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-S", f,
+                        "-o", f + ".s"], check=True, capture_output=True)
+        with open(f + ".s") as fh:
+            asm = fh.read().splitlines()
+    labels = {m.group(1): i for i, line in enumerate(asm) if (m := re.match(r"^(\.LBB\d+_\d+):", line))}
+    best = 0
+    for i, line in enumerate(asm):
+        m = re.search(r"s_c?branch\w*\s+(\.LBB\d+_\d+)", line)
+        if m and labels.get(m.group(1), i) < i:
+            best = max(best, sum(1 for x in asm[labels[m.group(1)]:i] if re.match(r"\s+v_\w*f64", x)))
+    return best
+
+
+def test_loop_operation_count_matches_isa(P):
+    """FP64 paired kernels: ops_per_step is the compiled step loop's FP64
+    instructions per Gray term, read by the library from the code object's
+    machine code; hipcc's gfx950 assembly of the same source, an independent
+    reading, has exactly as many in its loop, with and without copies of the
+    most frequent columns' rows."""
+    for ccs in (W.single_01(40, 0.10, 1), W.single_01(36, 0.15, 1)):
+        for m in (-1, 1, 3, 0):
+            opts = dict(zero_skip=False, exact=False, copy_cols=m, waves_per_simd=-1)
+            src = P.perm_codegen(ccs, **opts)
+            assert "pair0" in src.splitlines()[0]
+            info = P.compile_info(ccs, **opts)
+            terms = 2 ** (info["unroll_log2"] + 2)  # paired steps of one iteration, two terms each
+            isa = _loop_fp64_instructions(src)
+            assert isa > 0 and isa == round(info["ops_per_step"] * terms), (ccs[0], m, isa, info["ops_per_step"] * terms)
+            assert info["ops_per_step"] <= info["flops_per_step"] <= 2 * info["ops_per_step"]
+
+
 def test_autotune_singular_needs_no_device(P):
     """A structurally singular matrix has nothing to tune: perm_autotune
     answers with the options it was given and times no candidate (no device
@@ -600,6 +641,9 @@ def test_column0_pairing_on_cpu(P, oracle_mod):
     # real and signed entries where column 0 has two: the bracket is kept
     # and moved by constants, in the static steps and through the table
     cases += [(W.random_sparse(13, 0.25, 0, kind="real"), 9, 2), (W.random_sparse(15, 0.2, 0, kind="signed"), 11, 2)]
+    # static blocks of two paired steps, with the step loop
+    cases += [(W.random_sparse(12, 0.3, 4, kind="real"), 6, 1)]
+    twins = 0
     for ccs, kappa, u in cases:
         ref, abs_sum = O.perm_nw(ccs)
         opts = dict(chunk_log2=kappa, unroll_log2=u, zero_skip=False, exact=False)
@@ -611,10 +655,23 @@ def test_column0_pairing_on_cpu(P, oracle_mod):
         if L >= 2:
             assert "double c0 = 0.0" in src and f"acc0 = c{L - 1};" in src
         if (kappa, u) in ((9, 2), (11, 2)):
-            assert "double dp = " in src and "dp = fma(sg, " in src and re.search(r"dp [+-]= ", src)
+            assert "double dp = " in src and "dp = fma(sg, " in src
+        # copies of the rows of the walk's most frequent columns
+        twins += " copies=" in src.splitlines()[0] and re.search(r"double x\d+_\d+ = ", src) is not None
         got, info = _emulate(P, ccs, **opts)
         assert info["evaluated"] == 1 << (ccs[0] - 1)
         assert abs(got - ref) <= 1e-13 * abs_sum + 1e-15, (ccs[0], kappa, u, got, ref)
+    assert twins == len(cases)
+    # every number of copied columns the static block allows
+    for ccs, kappa, u in cases[3:6] + cases[-3:]:
+        ref, abs_sum = O.perm_nw(ccs)
+        for m in (-1, 1, 2, 3):
+            opts = dict(chunk_log2=kappa, unroll_log2=u, zero_skip=False, exact=False, copy_cols=m)
+            head = P.perm_codegen(ccs, **opts).splitlines()[0]
+            assert (" copies=" in head) == (m > 0), (ccs[0], kappa, u, m, head)
+            got, info = _emulate(P, ccs, **opts)
+            assert info["evaluated"] == 1 << (ccs[0] - 1)
+            assert abs(got - ref) <= 1e-13 * abs_sum + 1e-15, (ccs[0], kappa, u, m, got, ref)
     # the exact mode pairs too: the pair's bracket is an integer (y units),
     # its residue d R_1; residues and the recovered count against the oracle
     for ccs, kappa, u in ((W.single_01(16, 0.2, 2), 7, 3), (W.single_01(20, 0.1, 6), 12, 4)):
