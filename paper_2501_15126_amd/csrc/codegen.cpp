@@ -109,21 +109,24 @@ struct Gen {
     bool dtrack = false;
     int dyn_dslot = -1;  // slot of the bracket's change in the dynamic table
 
-    // Copies over columns 1..m (the walk's most frequent flips; m =
-    // copy_cols): row r at a level >= 1 is kept once per subset sigma of
-    // Tr[r], the columns <= m touching it (x<r> for none, x<r>_<sigma> with
+    // Copies over the walk's first m columns (its most frequent flips:
+    // columns 1..m with pairing, else 0..m-1; m = copy_cols): row r (at a
+    // level >= 1 with pairing) is kept once per subset sigma of Tr[r], the
+    // copied columns touching it (x<r> for none, x<r>_<sigma> with
     // those columns' entries added), level l once per subset of Tl[l] (P<l>,
     // P<l>_<sigma>), the bracket once per subset of T0 (dp, dp_<sigma>).  ts
     // is the set of those columns in x where a step is emitted (none at
-    // every chunk start, loop top and dynamic step); a flip of column c <= m
-    // only toggles bit c-1 of ts, and every other flip moves every copy.
+    // every chunk start, loop top and dynamic step); a flip of copied column
+    // c only toggles bit c - cbase of ts, and every other flip moves every copy.
     int cm = 0;
+    int cbase = 1;  // the first copied column (the walk's first: 1 with pairing, else 0)
+    int lv0 = 1;    // the lowest level whose product a step forms (0: nested, no pairing)
     unsigned ts = 0u, T0 = 0u;
     // Levels whose rows changed since their products were last formed (the
     // nested-accumulation kernels form only those again).
     std::vector<char> dirty;
     void touch_row(int r) {
-        if (horner && r < p.n && p.row_level[r] >= 1) dirty[p.row_level[r]] = 1;
+        if (horner && r < p.n && (p.row_level[r] >= 1 || !p.pair0)) dirty[p.row_level[r]] = 1;
     }
     std::vector<unsigned> Tr, Tl;
     static std::string sub(const std::string &base, unsigned sigma) {
@@ -366,7 +369,7 @@ struct Gen {
         }
         for (int q = B.colptr[j]; q < B.colptr[j + 1]; ++q) {
             const int r = B.rowidx[q];
-            if (horner && p.row_level[r] == 0) continue;  // level 0 lives in the bracket
+            if (horner && p.pair0 && p.row_level[r] == 0) continue;  // level 0 lives in the bracket
             touch_row(r);
             const std::string a = lit(B.val[q]);
             if (cm && Tr[r])
@@ -458,15 +461,15 @@ struct Gen {
         std::string in = std::string(ind) + "  ";
         const char *I = in.c_str();
         if (horner) flush_to(p.col_top[j], I);
-        if (j >= 1 && j <= cm) {
+        if (cm && j >= cbase && j < cbase + cm) {
             // column j in (Plus) or out (Minus): other copies become current
-            const unsigned bit = 1u << (j - 1);
+            const unsigned bit = 1u << (j - cbase);
             if ((sg == Sign::Plus) != !(ts & bit) || (sg != Sign::Plus && sg != Sign::Minus))
                 os << "#error copies of x out of step\n";  // a generator fault: fail to compile
             ts ^= bit;
         } else {
             update(j, sg, cur, I);
-            for (int l = p.col_top[j]; l >= 1; --l) refresh_level(l, cur, I);
+            for (int l = p.col_top[j]; l >= lv0; --l) refresh_level(l, cur, I);
         }
         accumulate(term_sign, acc, cur, I, nullptr, horner && p.col_top[j] >= 1);
         os << ind << "}\n";
@@ -560,6 +563,26 @@ struct Gen {
             os << I << "accA = fma(fabs(" << pr << "), fabs(" << last << "), accA);\n";
             return;
         }
+        if (horner) {
+            // nested accumulation without pairing: the term's level-0 factor
+            // is P_0 (its current copy), which starts c_0 or adds to it
+            std::string d = pname(0);
+            if (weight) {
+                const std::string dw = fresh();
+                os << I << "const double " << dw << " = " << d << " * " << weight << ";\n";
+                note(dw, "mul", {d, weight}, 1);
+                d = dw;
+            }
+            const char *sg = term_sign < 0 ? "-" : "";
+            if (fresh_run) {
+                os << I << "c0 = " << sg << d << ";\n";
+                derive("c0", *sg ? "neg" : "id", {d});
+            } else {
+                os << I << "c0 = c0 + " << sg << d << ";\n";
+                note("c0", *sg ? "subc" : "addc", {"c0", d}, 1);
+            }
+            return;
+        }
         std::vector<std::string> v = level_values(0, cur, I);
         if (weight) v.push_back(weight);
         std::string last;
@@ -595,7 +618,7 @@ struct Gen {
         }
         dyn_rows.clear();
         for (int r = 0; r < p.n; ++r)
-            if (used[r] && !(horner && p.row_level[r] == 0)) dyn_rows.push_back(r);
+            if (used[r] && !(horner && p.pair0 && p.row_level[r] == 0)) dyn_rows.push_back(r);
         // with bracket tracking, one more slot per column: the bracket's change
         if (dtrack && dtouch) dyn_dslot = (int)dyn_rows.size();
         const size_t R = dyn_rows.size() + (dyn_dslot >= 0 ? 1 : 0);
@@ -688,22 +711,24 @@ struct Gen {
         // (column-0 pairing: paired steps flipping columns 1 ..)
         const int c0 = p.pair0 ? 1 : 0;
         const int kw = kappa - c0;
-        horner = p.pair0 && !p.exact && !p.cold && L >= 2;
-        dtrack = horner && p.B.colptr[1] - p.B.colptr[0] == 2;
+        horner = p.nested && !p.exact && !p.cold && L >= 2;
+        dtrack = horner && p.pair0 && p.B.colptr[1] - p.B.colptr[0] == 2;
         cm = horner ? p.copy_cols : 0;
+        cbase = c0;
+        lv0 = horner && !p.pair0 ? 0 : 1;
         dirty.assign(L, 0);
         ts = 0u;
         T0 = 0u;
         Tr.assign(n, 0u);
         Tl.assign(L, 0u);
-        for (int c = 1; c <= cm; ++c)
+        for (int c = cbase; c < cbase + cm; ++c)
             for (int q = B.colptr[c]; q < B.colptr[c + 1]; ++q) {
                 const int r = B.rowidx[q];
-                if (p.row_level[r] == 0) {
-                    if (dtrack) T0 |= 1u << (c - 1);
+                if (p.pair0 && p.row_level[r] == 0) {
+                    if (dtrack) T0 |= 1u << (c - cbase);
                 } else {
-                    Tr[r] |= 1u << (c - 1);
-                    Tl[p.row_level[r]] |= 1u << (c - 1);
+                    Tr[r] |= 1u << (c - cbase);
+                    Tl[p.row_level[r]] |= 1u << (c - cbase);
                 }
             }
         cz.assign(L, 0);
@@ -711,7 +736,8 @@ struct Gen {
         const unsigned evm = 1u << c0;  // Gray terms per walked step
         os << "// generated by libperm_mi355x: n=" << n << " nnz=" << p.nnz << " k=" << k << " c=" << p.c
            << " levels=" << L << " kappa=" << kappa << " u=" << u << " block=" << p.block
-           << (p.pair0 ? " pair0" : "") << (cm ? " copies=" + std::to_string(cm) : "") << "\n";
+           << (p.pair0 ? " pair0" : "") << (horner ? " nested" : "") << (cm ? " copies=" + std::to_string(cm) : "")
+           << "\n";
         os << "typedef unsigned long long u64;\n"
               "typedef unsigned int u32;\n"
               "struct dd { double h, l; };\n"
@@ -845,19 +871,19 @@ struct Gen {
             cur[r] = "cx" + std::to_string(r);
         }
         if (cm) {
-            // columns 1..m are out of x at every chunk start; the other copies
+            // the copied columns are out of x at every chunk start; the other copies
             for (int r = 0; r < n; ++r)
                 for (unsigned sgm : subsets(Tr[r])) {
                     if (!sgm) continue;
                     double add = 0.0;
-                    for (int c = 1; c <= cm; ++c)
-                        if (sgm & (1u << (c - 1)))
+                    for (int c = cbase; c < cbase + cm; ++c)
+                        if (sgm & (1u << (c - cbase)))
                             for (int q = B.colptr[c]; q < B.colptr[c + 1]; ++q)
                                 if (B.rowidx[q] == r) add += B.val[q];
                     os << "  double " << xv(r, sgm) << " = " << xname(r) << " + " << lit(add) << ";\n";
                 }
         }
-        for (int l = L - 1; l >= 1; --l) {
+        for (int l = L - 1; l >= lv0; --l) {
             if (p.exact) {
                 const std::vector<std::string> qs = part_products(l, cur, "  ");
                 const std::string pl = product(qs, "  ");
@@ -891,8 +917,8 @@ struct Gen {
             for (unsigned sgm : subsets(T0)) {
                 if (!sgm) continue;
                 double add = 0.0;
-                for (int c = 1; c <= cm; ++c)
-                    if (sgm & (1u << (c - 1))) add += bracket_delta(c);
+                for (int c = cbase; c < cbase + cm; ++c)
+                    if (sgm & (1u << (c - cbase))) add += bracket_delta(c);
                 os << "  double " << sub("dp", sgm) << " = dp + " << lit(add) << ";\n";
             }
         }
@@ -1050,7 +1076,7 @@ struct Gen {
                 walk_s_only = lazy_r;
                 if (horner) flush_to(loop_top, I2);
                 const int top_max = dyn_flip("jj", "sg", cur, I2);
-                for (int l = top_max; l >= 1; --l) refresh_level(l, cur, I2);
+                for (int l = top_max; l >= lv0; --l) refresh_level(l, cur, I2);
                 accumulate(1, 1, cur, I2, "w", horner && loop_top >= 1);
                 walk_s_only = false;
                 os << ind << "}\n";

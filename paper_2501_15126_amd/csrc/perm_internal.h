@@ -87,10 +87,13 @@ struct Plan {
     // and a static block is 2^u paired steps.
     bool pair0 = false;
     int pair_r = -1, pair_s = -1;       // column 0's rows: bracket fma(a_r, x_s, fma(a_s, x_r, a_r a_s))
-    // FP64 paired kernels: the rows of columns 1..copy_cols (the walk's most
-    // frequent flips) kept with every combination of those columns' entries
-    // in or out, so that flipping one only selects other copies; chosen by
-    // the operation model (0: none).
+    // Nested accumulation (FP64 AUTO all-terms kernels, see the generator):
+    // per-level products and accumulators instead of cached products.
+    bool nested = false;
+    // Nested kernels: the rows of the walk's first copy_cols columns (its
+    // most frequent flips) kept with every combination of those columns'
+    // entries in or out, so that flipping one only selects other copies;
+    // chosen by the generator's operation count (0: none).
     int copy_cols = 0;
     // Exact mode (integer-valued matrices): B holds 2a, so x is y = 2x, an
     // integer; the kernel also keeps the term sum modulo a prime and the two

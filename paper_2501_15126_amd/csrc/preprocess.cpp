@@ -151,11 +151,43 @@ int auto_kappa(int n, bool zero_skip) {
 
 int auto_unroll(bool zero_skip) { return zero_skip ? 6 : 7; }
 
-// Copies of the most frequent columns' rows (FP64 paired kernels): at most
+// Copies of the most frequent columns' rows (nested kernels): at most
 // this many extra doubles per lane in the automatic choice (about half the
 // 512 VGPRs of one wave per SIMD; the measured n = 40 kernels keep 2 waves
 // per SIMD up to about 100).
 constexpr int kMaxCopyValues = 112;
+
+// Nested kernels without pairing replace the cached products only at this
+// fraction of their FP64 operations or below (see make_plan).
+constexpr double kNestedGain = 0.6;
+
+// The number m of the walk's first columns whose rows are kept in copies
+// (nested kernels): the generator counts the FP64 operations of each
+// candidate's step loop (the flips of copied columns leave every value
+// unchanged, so much of what follows them depends only on values the loop
+// never changes and leaves the loop); the fewest win, a further column
+// having to save at least 1 % and (automatic choice) the copies staying
+// within kMaxCopyValues doubles.  copy_cols forces m (-1: none).  Returns
+// -1 if no candidate was counted.
+int choose_copies(const Plan *p, const perm_opts &o, int mmax, LoopCount *best) {
+    mmax = p->u >= 1 ? std::max(0, mmax) : 0;
+    const int want = o.copy_cols < 0 ? 0 : o.copy_cols > 0 ? std::min(o.copy_cols, mmax) : -1;
+    int mbest = -1;
+    for (int m = 0; m <= mmax; ++m) {
+        if (want >= 0 && m != want) continue;
+        Plan q = *p;
+        q.copy_cols = m;
+        LoopCount lc;
+        generate_source(q, &lc);
+        if (!lc.counted) continue;
+        if (want < 0 && lc.copy_values > kMaxCopyValues) continue;
+        if (mbest < 0 || lc.ops_per_step < 0.99 * best->ops_per_step) {
+            mbest = m;
+            *best = lc;
+        }
+    }
+    return mbest;
+}
 
 bool integer_valued(const Ccs &a) {
     for (double v : a.val)
@@ -539,37 +571,13 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
             pops += cnt * oj;
             pfl += cnt * (oj + bops + (nest ? 0.0 : 1.0));
         }
-        // Copies over columns 1..m (nested accumulation, m <= u; see the
-        // generator): the generator counts the FP64 operations of each
-        // candidate's step loop, which here are far from the per-column sums
-        // above (the flips of columns <= m leave the copies unchanged, so
-        // much of what follows them depends only on values the loop never
-        // changes and is hoisted); the fewest operations win (forced by
-        // copy_cols when set).
         p->copy_cols = 0;
+        p->nested = nest;
         if (nest) {
-            const int mmax = p->u >= 1 ? std::min(p->u, n - 2) : 0;
-            const int want = o.copy_cols < 0 ? 0 : o.copy_cols > 0 ? std::min(o.copy_cols, mmax) : -1;
-            int mbest = -1;
             LoopCount best;
-            for (int m = 0; m <= mmax; ++m) {
-                if (want >= 0 && m != want) continue;
-                Plan q = *p;
-                q.copy_cols = m;
-                LoopCount lc;
-                generate_source(q, &lc);
-                if (!lc.counted) continue;
-                // a copy column must save at least 1 % of the operations, and
-                // (automatic choice) the copies must fit beside the rest of
-                // the registers: at most kMaxCopyValues doubles
-                if (want < 0 && lc.copy_values > kMaxCopyValues) continue;
-                if (mbest < 0 || lc.ops_per_step < 0.99 * best.ops_per_step) {
-                    mbest = m;
-                    best = lc;
-                }
-            }
-            if (mbest >= 0) {
-                p->copy_cols = mbest;
+            const int m = choose_copies(p, o, std::min(p->u, n - 2), &best);
+            if (m >= 0) {
+                p->copy_cols = m;
                 pops = best.ops_per_step * steps;
                 pfl = best.flops_per_step * steps;
             }
@@ -578,6 +586,30 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         p->ops_per_step = pops / steps;
         p->flops_per_step = pfl / steps;
         p->exact_ops_per_step = pxo / steps;
+    }
+    // Nested accumulation without pairing (AUTO, all terms, FP64): level 0's
+    // own product starts c_0, and the copied columns are 0..m-1.  Taken when
+    // the generator's count of its best form is at most kNestedGain of the
+    // cached products': these kernels' copies of dense rows take most of
+    // the registers (one wave per SIMD at n = 36..40, densities 0.2..0.5,
+    // 51-69 % FP64 issue against about 90 % for the cached products), so
+    // fewer operations pay only when they are clearly fewer (ER n = 40:
+    // 0.39 of the count at p = 0.3 ran 1.4x faster, 0.65 at p = 0.5 14 %
+    // slower).  Copies asked for (copy_cols > 0) take the nested form.
+    if (!p->pair0 && o.mode == PERM_MODE_AUTO && !zs && !ex && !p->cold && L >= 2 && p->kappa >= 2) {
+        Plan q = *p;
+        q.nested = true;
+        // static blocks of 2^6 steps by default: without pairing the steps
+        // are denser, and longer blocks compile slowly for little gain
+        if (o.unroll_log2 == 0) q.u = std::max(0, std::min(6, p->kappa - 1));
+        LoopCount best;
+        const int m = choose_copies(&q, o, std::min(q.u, n - 1), &best);
+        if (m >= 0 && (o.copy_cols > 0 || best.ops_per_step <= kNestedGain * p->ops_per_step)) {
+            *p = q;
+            p->copy_cols = m;
+            p->ops_per_step = best.ops_per_step;
+            p->flops_per_step = best.flops_per_step;
+        }
     }
     return PERM_OK;
 }

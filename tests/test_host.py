@@ -200,14 +200,17 @@ def test_codegen_hex_literals_exact(P):
 
 def test_codegen_resources(P):
     """hipRTC (gfx950) compiles without a GPU.  At the compiler's own occupancy
-    x stays in VGPRs (no scratch); the automatic occupancy choice recompiles a
-    4-wave kernel (97..128 VGPRs) for 5 waves and a 3-wave one (129..168) for
-    4, and keeps that build only if it spills at most 128 bytes per lane."""
+    x stays in VGPRs (no scratch; nested kernels with copies of rows may use
+    up to all 512 VGPRs of one wave per SIMD, the others at most 256); the
+    automatic occupancy choice recompiles a 4-wave kernel (97..128 VGPRs) for
+    5 waves and a 3-wave one (129..168) for 4, and keeps that build only if it
+    spills at most 128 bytes per lane."""
     for ccs in (W.single_01(40, 0.10, 1), W.single_real(36, 0.30, 1), W.single_01(24, 0.15, 1)):
         for mode in ("auto", "pure", "hybrid"):
             plain = P.compile_info(ccs, mode=mode, waves_per_simd=-1)
             assert plain["scratch_bytes"] == 0 and plain["waves_hint"] == 0, (ccs[0], mode)
-            assert plain["vgprs"] <= 256
+            copies = " copies=" in P.perm_codegen(ccs, mode=mode, waves_per_simd=-1).splitlines()[0]
+            assert plain["vgprs"] <= (512 if copies else 256), (ccs[0], mode, plain["vgprs"])
             auto = P.compile_info(ccs, mode=mode)
             want = 5 if 96 < plain["vgprs"] <= 128 else 4 if 128 < plain["vgprs"] <= 168 else 0
             if auto["waves_hint"] == 0:
@@ -217,9 +220,11 @@ def test_codegen_resources(P):
             else:
                 assert auto["waves_hint"] == want, (ccs[0], mode, plain["vgprs"])
                 assert auto["vgprs"] <= 512 // want and auto["scratch_bytes"] <= 128
-        # x in VGPRs at 4 waves (exact mode, with its residue per level: 3)
+        # x in VGPRs at 4 waves (exact mode, with its residue per level: 3;
+        # nested kernels with copies: whatever the copies take)
         own = P.compile_info(ccs, waves_per_simd=-1)
-        assert own["vgprs"] <= (168 if own["exact"] >= 0 else 128)
+        copies = " copies=" in P.perm_codegen(ccs, waves_per_simd=-1).splitlines()[0]
+        assert own["vgprs"] <= (512 if copies else 168 if own["exact"] >= 0 else 128)
         # the LDS tier: cold rows in LDS ([row][lane]), at most 40 KiB per workgroup
         # (k as compiled: Alg. 5 runs again with the compiled kernel's register model)
         lds = P.compile_info(ccs, mode="hybrid", cold_tier="lds")
@@ -572,6 +577,33 @@ def test_block_queue_on_cpu(P, oracle_mod):
     assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12
 
 
+def test_nested_without_pairing_on_cpu(P, oracle_mod):
+    """FP64 AUTO kernels whose first column has three or more entries (no
+    pairing) sum the terms through per-level accumulators, level 0's own
+    product starting the lowest, with copies of the rows of the walk's first
+    m columns (m = none, 1, 2, 3 and the automatic choice); emulated on the
+    CPU over every chunk, against the oracle."""
+    O = oracle_mod
+    cases = [(W.random_sparse(12, 0.4, 0, kind="real"), 8, 4), (W.random_sparse(14, 0.35, 2, kind="signed"), 9, 5),
+             (W.random_sparse(16, 0.4, 7, kind="real"), 10, 4), (W.random_sparse(11, 0.45, 5, kind="real"), 6, 3)]
+    nested = 0
+    for ccs, kappa, u in cases:
+        ref, abs_sum = O.perm_nw(ccs)
+        for m in (-1, 1, 2, 3, 0):
+            opts = dict(chunk_log2=kappa, unroll_log2=u, zero_skip=False, exact=False, copy_cols=m)
+            head = P.perm_codegen(ccs, **opts).splitlines()[0]
+            assert "pair0" not in head, (ccs[0], head)
+            if " nested" not in head:
+                continue  # the cached products were cheaper for this matrix
+            nested += 1
+            if m > 0:
+                assert (" copies=%d" % m) in head, (ccs[0], m, head)
+            got, info = _emulate(P, ccs, **opts)
+            assert info["evaluated"] == 1 << (ccs[0] - 1)
+            assert abs(got - ref) <= 1e-13 * abs_sum + 1e-15, (ccs[0], kappa, u, m, got, ref)
+    assert nested >= 12
+
+
 def _loop_fp64_instructions(src):
     """FP64 VALU instructions of the generated kernel's step loop (the loop
     with the most of them) in hipcc's gfx950 assembly of the source, built
@@ -596,18 +628,20 @@ def _loop_fp64_instructions(src):
 
 
 def test_loop_operation_count_matches_isa(P):
-    """FP64 paired kernels: ops_per_step is the compiled step loop's FP64
+    """FP64 nested kernels: ops_per_step is the compiled step loop's FP64
     instructions per Gray term, read by the library from the code object's
     machine code; hipcc's gfx950 assembly of the same source, an independent
     reading, has exactly as many in its loop, with and without copies of the
     most frequent columns' rows."""
-    for ccs in (W.single_01(40, 0.10, 1), W.single_01(36, 0.15, 1)):
-        for m in (-1, 1, 3, 0):
+    for ccs, ms in ((W.single_01(40, 0.10, 1), (-1, 1, 3, 0)), (W.single_01(36, 0.15, 1), (-1, 1, 3, 0)),
+                    (W.single_real(36, 0.30, 1), (0,))):  # the last without pairing
+        for m in ms:
             opts = dict(zero_skip=False, exact=False, copy_cols=m, waves_per_simd=-1)
             src = P.perm_codegen(ccs, **opts)
-            assert "pair0" in src.splitlines()[0]
+            assert " nested" in src.splitlines()[0]
             info = P.compile_info(ccs, **opts)
-            terms = 2 ** (info["unroll_log2"] + 2)  # paired steps of one iteration, two terms each
+            # 2^(u+1) steps per iteration, two terms each with pairing
+            terms = 2 ** (info["unroll_log2"] + (2 if "pair0" in src.splitlines()[0] else 1))
             isa = _loop_fp64_instructions(src)
             assert isa > 0 and isa == round(info["ops_per_step"] * terms), (ccs[0], m, isa, info["ops_per_step"] * terms)
             assert info["ops_per_step"] <= info["flops_per_step"] <= 2 * info["ops_per_step"]
