@@ -218,6 +218,35 @@ def test_er_grid_cell_block_partials_vs_oracle(P, oracle_mod):
     assert total * 2.0 == pytest.approx(got, rel=1e-12)
 
 
+@pytest.mark.parametrize("copies", [0, 2])
+def test_er_grid_nested_block_partials_vs_oracle(P, oracle_mod, copies):
+    """A full-size grid cell whose kernel takes the nested form without
+    pairing (n = 40, p = 0.3, U[0,1]; copies of the rows of the walk's first
+    columns as the plan chooses, and with two forced): sampled workgroup
+    partials against the oracle on the same Gray-index ranges of the plan's
+    ordered matrix, and their sum against the returned permanent."""
+    import math
+    O = oracle_mod
+    n = 40
+    ccs = W.er_grid_matrix(n, 0.3)
+    opts = dict(copy_cols=copies)
+    head = P.perm_codegen(ccs, **opts).splitlines()[0]
+    assert " nested" in head and "pair0" not in head, head
+    got, st, parts = P.perm_sparse_ex(ccs, block_partials=True, **opts)
+    print("er40 p0.3 nested", head, st["kernel_ms"], st["vgprs"], flush=True)
+    plan = P.perm_plan(ccs, **opts)
+    A = O.ccs_to_dense(ccs)
+    B = O.dense_to_ccs(A[np.ix_(plan["row_perm"], plan["col_perm"])])
+    W_ = st["block"] << st["chunk_log2"]
+    for b in (0, st["nblocks"] // 2 + 3, st["nblocks"] - 1):
+        (h, l), (ah, al) = O.nw_range(B, b * W_, min((b + 1) * W_, 1 << (n - 1)))
+        ref, abs_sum = h + l, ah + al
+        g = parts[b, 0] + parts[b, 1]
+        assert abs(g - ref) <= max(1e-9 * abs(ref), (2 * n + 2) * 2.0 ** -53 * abs_sum), (b, g, ref)
+    total = math.fsum(parts[:, 0]) + math.fsum(parts[:, 1])
+    assert total * 2.0 * (-1) ** (n - 1) == pytest.approx(got, rel=1e-12)  # Alg. 1's final factor
+
+
 def test_full_size_closed_forms(P, oracle_mod):
     """n = 40, the benchmark size, on matrices whose permanent is known in
     closed form (no oracle run): tridiagonal of ones, F(41) = 165580141; a
