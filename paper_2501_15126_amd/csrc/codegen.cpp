@@ -37,6 +37,8 @@
 #include <cstdio>
 #include <map>
 #include <set>
+#include <unordered_map>
+#include <unordered_set>
 #include <sstream>
 
 #include "perm_internal.h"
@@ -158,12 +160,18 @@ struct Gen {
     double loop_terms = 0;                  // Gray terms per iteration
     uint64_t loop_iters = 0;
     int sign_fmas = 0;                      // table-entry FMAs per iteration
-    std::map<std::string, std::pair<std::string, bool>> vid;  // name -> (value, varies)
-    std::set<std::string> seen, assigned;
+    // values are numbered: a value's key is its operation and its operands'
+    // numbers (a name the loop does not assign is a value of its own)
+    std::unordered_map<std::string, int> interned;
+    std::unordered_map<std::string, std::pair<int, bool>> vid;  // name -> (value, varies)
+    std::unordered_set<int> seen;
+    std::unordered_set<std::string> assigned;
     double cnt_ops = 0, cnt_flops = 0;
-    std::pair<std::string, bool> val(const std::string &name) const {
+    double hoist_ops = 0, hoist_flops = 0;  // the loop's invariant operations (once per chunk)
+    int intern(const std::string &key) { return interned.emplace(key, (int)interned.size()).first->second; }
+    std::pair<int, bool> val(const std::string &name) {
         auto it = vid.find(name);
-        return it != vid.end() ? it->second : std::make_pair(name, false);
+        return it != vid.end() ? it->second : std::make_pair(intern("=" + name), false);
     }
     // +1 or -1 if the value is that constant (a literal, or its sign), else 0
     std::map<std::string, int> unit;
@@ -187,7 +195,8 @@ struct Gen {
             const int u0 = unit_of(av[0]), u1 = unit_of(av[1]);
             const std::string &other = u0 ? av[1] : av[0];
             const int sgn = u0 ? u0 : u1;
-            vid[lhs] = {std::string(sgn > 0 ? "id(" : "neg(") + val(other).first + ")", val(other).second};
+            const auto v = val(other);
+            vid[lhs] = {intern(std::string(sgn > 0 ? "id(" : "neg(") + std::to_string(v.first) + ")"), v.second};
             unit[lhs] = unit_of(other) * sgn;
             assigned.insert(lhs);
             return;
@@ -195,17 +204,19 @@ struct Gen {
         if (sop == "fma" && (unit_of(av[0]) || unit_of(av[1]))) flops = 1;
         if (sop == "neg" || sop == "id") unit[lhs] = (sop == "neg" ? -1 : 1) * unit_of(av[0]);
         else unit.erase(lhs);
-        std::string id = std::string(op) + "(";
+        std::string key = std::string(op) + "(";
         bool vary = all_vary;
         for (const std::string &a : args) {
             const auto v = val(a);
-            id += v.first + ",";
+            key += std::to_string(v.first) + ",";
             vary = vary || v.second;
         }
-        id += ")";
-        if (counting && vary && seen.insert(id).second && !free) {
-            cnt_ops += 1;
-            cnt_flops += flops;
+        key += ")";
+        const int id = intern(key);
+        if (counting && seen.insert(id).second && !free) {
+            // varying: every iteration; not varying: once, before the loop
+            (vary ? cnt_ops : hoist_ops) += 1;
+            (vary ? cnt_flops : hoist_flops) += flops;
         }
         vid[lhs] = {id, vary};
         assigned.insert(lhs);
@@ -223,7 +234,7 @@ struct Gen {
     void varies(const std::string &name) {
         if (!track) return;
         unit.erase(name);
-        vid[name] = {"(" + name + ")", true};
+        vid[name] = {intern("(" + name + ")"), true};
         assigned.insert(name);
     }
 
@@ -1109,6 +1120,7 @@ struct Gen {
                     const std::vector<char> dirty0 = dirty;
                     track = true;
                     vid.clear();
+                    interned.clear();
                     unit.clear();
                     assigned.clear();
                     body();
@@ -1121,18 +1133,21 @@ struct Gen {
                     dirty = dirty0;
                     vid.clear();
                     unit.clear();
-                    for (const std::string &a : assigned) vid[a] = {"phi:" + a, true};
+                    for (const std::string &a : assigned) vid[a] = {intern("phi:" + a), true};
                     seen.clear();
-                    cnt_ops = cnt_flops = 0;
+                    cnt_ops = cnt_flops = hoist_ops = hoist_flops = 0;
                     counting = true;
                     all_vary = DW == (uint64_t)(2 * U);  // one pass: nothing to hoist
                     body();
                     counting = track = all_vary = false;
                     const double terms = (double)(2 * U) * evm;
-                    loop_ops = cnt_ops / terms;
-                    loop_flops = cnt_flops / terms;
                     loop_terms = terms;
                     loop_iters = DW / (uint64_t)(2 * U);
+                    // per Gray term of a chunk: the body every iteration, the
+                    // hoisted operations once
+                    const double it = (double)loop_iters;
+                    loop_ops = (cnt_ops * it + hoist_ops) / (terms * it);
+                    loop_flops = (cnt_flops * it + hoist_flops) / (terms * it);
                 } else {
                     body();
                 }
@@ -1277,6 +1292,7 @@ std::string generate_source(const Plan &p, LoopCount *lc) {
         lc->ops_per_step = g.loop_ops;
         lc->flops_per_step = g.loop_flops;
         lc->loop = g.loop_iters > 1;
+        lc->iters = g.loop_iters;
         lc->terms_per_iter = g.loop_terms;
         lc->sign_fmas = g.sign_fmas;
         int cv = 0;

@@ -157,6 +157,7 @@ perm_status compile_source(const std::string &src, CodeObject *out, std::string 
 
 void count_loop_fp64(CodeObject *co) {
     co->loop_add = co->loop_mul = co->loop_fma = -1;
+    co->all_add = co->all_mul = co->all_fma = -1;
     Disasm d;
     d.elf = &co->code;
     if (!find_text(co->code, &d.base, &d.off, &d.size)) return;
@@ -190,6 +191,11 @@ void count_loop_fp64(CodeObject *co) {
         a += sz;
     }
     amd_comgr_destroy_disassembly_info(info);
+    int tot[4] = {0, 0, 0, 0};
+    for (const Ins &i : ins) tot[i.kind]++;
+    co->all_add = tot[1];
+    co->all_mul = tot[2];
+    co->all_fma = tot[3];
     int best = -1;
     for (const auto &lp : loops) {
         int c[4] = {0, 0, 0, 0};

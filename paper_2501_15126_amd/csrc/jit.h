@@ -17,6 +17,8 @@ struct CodeObject {
     // of the kernel's innermost loop with the most of them, read from the
     // code object's own machine code; -1 when it has no such loop
     int loop_add = -1, loop_mul = -1, loop_fma = -1;
+    // the same over the whole kernel (the loop's instructions counted once)
+    int all_add = -1, all_mul = -1, all_fma = -1;
 };
 
 // Fills co->loop_* from co->code (the disassembler of the ROCm code-object

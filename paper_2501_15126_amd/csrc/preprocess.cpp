@@ -151,36 +151,78 @@ int auto_kappa(int n, bool zero_skip) {
 
 int auto_unroll(bool zero_skip) { return zero_skip ? 6 : 7; }
 
-// Copies of the most frequent columns' rows (nested kernels): at most
-// this many extra doubles per lane in the automatic choice (about half the
-// 512 VGPRs of one wave per SIMD; the measured n = 40 kernels keep 2 waves
-// per SIMD up to about 100).
+// Copies of the most frequent columns' rows (nested kernels): at most this
+// many extra doubles per lane in the automatic choice.  With pairing the
+// matrices are sparse and the copies the main use of registers (n = 40:
+// 150 doubles in 344 VGPRs, one wave per SIMD, still the fastest);
+// without pairing the rows are dense and the rest of the kernel takes more
+// (n = 36, d = 0.30: copies of 6 columns spill, of 4 fit 336 VGPRs).
+constexpr int kMaxCopyValuesPaired = 400;
 constexpr int kMaxCopyValues = 112;
 
 // Nested kernels without pairing replace the cached products only at this
 // fraction of their FP64 operations or below (see make_plan).
 constexpr double kNestedGain = 0.6;
 
+// The extra doubles the copies of the walk's first m columns keep (the
+// generator's layout: rows, multi-row levels, the tracked bracket).
+int copy_values(const Plan *p, int m) {
+    const Ccs &B = p->B;
+    const int cbase = p->pair0 ? 1 : 0;
+    const bool dtrack = p->pair0 && B.colptr[1] - B.colptr[0] == 2;
+    std::vector<unsigned> Tr(p->n, 0u), Tl(p->nlevels, 0u);
+    std::vector<int> lsize(p->nlevels, 0);
+    unsigned T0 = 0u;
+    for (int r = 0; r < p->n; ++r) lsize[p->row_level[r]]++;
+    for (int c = cbase; c < cbase + m && c < p->n; ++c)
+        for (int q = B.colptr[c]; q < B.colptr[c + 1]; ++q) {
+            const int r = B.rowidx[q];
+            if (p->pair0 && p->row_level[r] == 0) {
+                if (dtrack) T0 |= 1u << (c - cbase);
+            } else {
+                Tr[r] |= 1u << (c - cbase);
+                Tl[p->row_level[r]] |= 1u << (c - cbase);
+            }
+        }
+    long cv = 0;
+    for (int r = 0; r < p->n; ++r) cv += (1l << __builtin_popcount(Tr[r])) - 1;
+    for (int l = 1; l < p->nlevels; ++l)
+        if (lsize[l] > 1) cv += (1l << __builtin_popcount(Tl[l])) - 1;
+    cv += (1l << __builtin_popcount(T0)) - 1;
+    return (int)std::min<long>(cv, INT_MAX);
+}
+
 // The number m of the walk's first columns whose rows are kept in copies
-// (nested kernels): the generator counts the FP64 operations of each
-// candidate's step loop (the flips of copied columns leave every value
-// unchanged, so much of what follows them depends only on values the loop
-// never changes and leaves the loop); the fewest win, a further column
-// having to save at least 1 % and (automatic choice) the copies staying
-// within kMaxCopyValues doubles.  copy_cols forces m (-1: none).  Returns
-// -1 if no candidate was counted.
-int choose_copies(const Plan *p, const perm_opts &o, int mmax, LoopCount *best) {
+// (nested kernels): the generator counts the FP64 operations of candidate
+// step loops (the flips of copied columns leave every value unchanged, so
+// much of what follows them depends only on values the loop never changes
+// and leaves the loop).  Candidates: the largest m whose copies fit the
+// register allowance (more copied columns almost always mean fewer
+// operations) and the two below it; the fewest operations win, a further
+// column having to save at least 1 %.  copy_cols forces m (-1: none).  *base
+// gets the count without copies.  Returns -1 if nothing was counted.
+int choose_copies(const Plan *p, const perm_opts &o, int mmax, LoopCount *best, LoopCount *base) {
     mmax = p->u >= 1 ? std::max(0, mmax) : 0;
     const int want = o.copy_cols < 0 ? 0 : o.copy_cols > 0 ? std::min(o.copy_cols, mmax) : -1;
+    const int cap = p->pair0 ? kMaxCopyValuesPaired : kMaxCopyValues;
+    std::vector<int> cands;
+    if (want >= 0) {
+        cands.push_back(want);
+    } else {
+        int top = mmax;
+        while (top > 0 && copy_values(p, top) > cap) --top;
+        for (int m = std::max(0, top - 2); m <= top; ++m) cands.push_back(m);
+    }
+    if (cands.front() != 0) cands.insert(cands.begin(), 0);  // the count without copies, for *base
     int mbest = -1;
-    for (int m = 0; m <= mmax; ++m) {
-        if (want >= 0 && m != want) continue;
+    for (int m : cands) {
         Plan q = *p;
         q.copy_cols = m;
         LoopCount lc;
         generate_source(q, &lc);
         if (!lc.counted) continue;
-        if (want < 0 && lc.copy_values > kMaxCopyValues) continue;
+        if (m == 0 && base) *base = lc;
+        if (want >= 0 && m != want) continue;
         if (mbest < 0 || lc.ops_per_step < 0.99 * best->ops_per_step) {
             mbest = m;
             *best = lc;
@@ -378,8 +420,8 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         return PERM_ETOOBIG;
     }
     p->u = o.unroll_log2 > 0 ? o.unroll_log2 : auto_unroll(zs);
-    if (p->u > 9) {
-        *err = "unroll_log2 must be <= 9";
+    if (p->u > 13) {
+        *err = "unroll_log2 must be <= 13";
         return PERM_EINVAL;
     }
     p->u = std::max(0, std::min(p->u, p->kappa - 1));
@@ -409,7 +451,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         return PERM_EINVAL;
     }
     p->waves_per_simd = std::max(0, o.waves_per_simd);
-    if (o.copy_cols < -1 || o.copy_cols > 9) {
+    if (o.copy_cols < -1 || o.copy_cols > 13) {
         *err = "copy_cols must be -1 (none), 0 (automatic) or 1..9";
         return PERM_EINVAL;
     }
@@ -447,9 +489,10 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         }
         if (ok) {
             p->pair0 = true;
-            // FP64: static blocks of 2^9 paired steps by default (the more of
-            // the walk's columns are static, the more can be kept in copies)
-            if (o.unroll_log2 == 0 && !ex) p->u = 9;
+            // FP64: static blocks as long as the chunk allows, up to 2^12
+            // paired steps, by default (the more of the walk's columns are
+            // static, the more can be kept in copies)
+            if (o.unroll_log2 == 0 && !ex) p->u = 12;
             p->u = std::min(p->u, p->kappa - 2);  // a static block of paired steps fits the chunk's half
             // two entries: the row that lower (more often flipped) columns
             // touch goes in the outer FMA of the bracket, so that a flip of
@@ -575,7 +618,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         p->nested = nest;
         if (nest) {
             LoopCount best;
-            const int m = choose_copies(p, o, std::min(p->u, n - 2), &best);
+            const int m = choose_copies(p, o, std::min(p->u, n - 2), &best, nullptr);
             if (m >= 0) {
                 p->copy_cols = m;
                 pops = best.ops_per_step * steps;
@@ -603,7 +646,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         // are denser, and longer blocks compile slowly for little gain
         if (o.unroll_log2 == 0) q.u = std::max(0, std::min(6, p->kappa - 1));
         LoopCount best;
-        const int m = choose_copies(&q, o, std::min(q.u, n - 1), &best);
+        const int m = choose_copies(&q, o, std::min(q.u, n - 1), &best, nullptr);
         if (m >= 0 && (o.copy_cols > 0 || best.ops_per_step <= kNestedGain * p->ops_per_step)) {
             *p = q;
             p->copy_cols = m;

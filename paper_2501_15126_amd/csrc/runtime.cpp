@@ -157,15 +157,30 @@ struct Prepared {
 };
 
 // Nested-accumulation kernels: the FP64 operations per Gray term that
-// ops_per_step and flops_per_step report are those of the compiled step loop
-// (its FP64 instructions per iteration over the iteration's terms; an FMA
-// counts 2 flops except one adding a signed table entry), which the compiler
-// makes fewer than the generator's count by simplifications of its own.
+// ops_per_step and flops_per_step report are those of the compiled kernel,
+// per chunk over the chunk's terms: the step loop's FP64 instructions times
+// its iterations, plus the rest of the kernel's once (the chunk's start,
+// what the compiler moved out of the loop, the lane's reduction).  An FMA
+// counts 2 flops except one adding a signed table entry.  The compiler
+// makes these fewer than the generator's count by simplifications of its
+// own.
 void use_compiled_count(Prepared *p, const CodeObject &co) {
-    if (!p->lc.counted || !p->lc.loop || co.loop_add < 0 || p->lc.terms_per_iter <= 0) return;
-    const double t = p->lc.terms_per_iter;
-    p->plan.ops_per_step = (co.loop_add + co.loop_mul + co.loop_fma) / t;
-    p->plan.flops_per_step = (co.loop_add + co.loop_mul + 2.0 * co.loop_fma - p->lc.sign_fmas) / t;
+    if (!p->lc.counted || co.all_add < 0 || p->lc.terms_per_iter <= 0 || p->lc.iters < 1) return;
+    const double it = (double)p->lc.iters;
+    const double t = p->lc.terms_per_iter * it;  // Gray terms of one chunk
+    const double all = co.all_add + co.all_mul + co.all_fma;
+    const double all_fl = co.all_add + co.all_mul + 2.0 * co.all_fma - p->lc.sign_fmas;
+    if (!p->lc.loop) {
+        // one pass over the chunk: straight-line code, each instruction once
+        p->plan.ops_per_step = all / t;
+        p->plan.flops_per_step = all_fl / t;
+        return;
+    }
+    if (co.loop_add < 0) return;
+    const double loop = co.loop_add + co.loop_mul + co.loop_fma;
+    const double loop_fl = co.loop_add + co.loop_mul + 2.0 * co.loop_fma - p->lc.sign_fmas;
+    p->plan.ops_per_step = (loop * it + (all - loop)) / t;
+    p->plan.flops_per_step = (loop_fl * it + (all_fl - loop_fl)) / t;
 }
 
 perm_status prepare(const perm_csc *m, const perm_opts &o, Prepared *p, bool want_source, int tau_base = 0) {

@@ -604,10 +604,11 @@ def test_nested_without_pairing_on_cpu(P, oracle_mod):
     assert nested >= 12
 
 
-def _loop_fp64_instructions(src):
-    """FP64 VALU instructions of the generated kernel's step loop (the loop
-    with the most of them) in hipcc's gfx950 assembly of the source, built
-    with the flags the library's hipRTC compile uses."""
+def _fp64_instructions(src):
+    """FP64 VALU instructions (add, mul, fma) of the generated kernel in
+    hipcc's gfx950 assembly of the source, built with the flags the library's
+    hipRTC compile uses: (those of its step loop, the innermost loop with the
+    most of them; those of the whole kernel)."""
     with tempfile.TemporaryDirectory() as d:
         f = os.path.join(d, "k.hip")
         with open(f, "w") as fh:
@@ -618,32 +619,47 @@ def _loop_fp64_instructions(src):
                         "-o", f + ".s"], check=True, capture_output=True)
         with open(f + ".s") as fh:
             asm = fh.read().splitlines()
+    fp = [bool(re.match(r"\s+v_(add|mul|fma|fmac)_f64", x)) for x in asm]
     labels = {m.group(1): i for i, line in enumerate(asm) if (m := re.match(r"^(\.LBB\d+_\d+):", line))}
-    best = 0
+    loops = []
     for i, line in enumerate(asm):
         m = re.search(r"s_c?branch\w*\s+(\.LBB\d+_\d+)", line)
         if m and labels.get(m.group(1), i) < i:
-            best = max(best, sum(1 for x in asm[labels[m.group(1)]:i] if re.match(r"\s+v_\w*f64", x)))
-    return best
+            loops.append((labels[m.group(1)], i))
+    best = 0
+    for a, b in loops:
+        inner = not any(a <= a2 and b2 <= b and (a2, b2) != (a, b) and any(fp[a2:b2]) for a2, b2 in loops)
+        if inner:
+            best = max(best, sum(fp[a:b]))
+    return best, sum(fp)
 
 
 def test_loop_operation_count_matches_isa(P):
-    """FP64 nested kernels: ops_per_step is the compiled step loop's FP64
-    instructions per Gray term, read by the library from the code object's
+    """FP64 nested kernels: ops_per_step is the compiled kernel's FP64
+    instructions per Gray term of a chunk (the step loop's times its
+    iterations, the rest once), read by the library from the code object's
     machine code; hipcc's gfx950 assembly of the same source, an independent
-    reading, has exactly as many in its loop, with and without copies of the
-    most frequent columns' rows."""
-    for ccs, ms in ((W.single_01(40, 0.10, 1), (-1, 1, 3, 0)), (W.single_01(36, 0.15, 1), (-1, 1, 3, 0)),
-                    (W.single_real(36, 0.30, 1), (0,))):  # the last without pairing
+    reading, gives exactly the same, with and without copies of the most
+    frequent columns' rows."""
+    for ccs, ms, u in ((W.single_01(40, 0.10, 1), (-1, 1, 3, 8), 9), (W.single_01(40, 0.10, 1), (0,), 0),
+                       (W.single_01(36, 0.15, 1), (-1, 3, 0), 9), (W.single_real(36, 0.30, 1), (0,), 0)):
+        # (the last without pairing; u = 0: the default static block, for n = 40 the whole chunk)
         for m in ms:
-            opts = dict(zero_skip=False, exact=False, copy_cols=m, waves_per_simd=-1)
+            opts = dict(zero_skip=False, exact=False, copy_cols=m, waves_per_simd=-1, unroll_log2=u)
             src = P.perm_codegen(ccs, **opts)
-            assert " nested" in src.splitlines()[0]
+            head = src.splitlines()[0]
+            assert " nested" in head
             info = P.compile_info(ccs, **opts)
-            # 2^(u+1) steps per iteration, two terms each with pairing
-            terms = 2 ** (info["unroll_log2"] + (2 if "pair0" in src.splitlines()[0] else 1))
-            isa = _loop_fp64_instructions(src)
-            assert isa > 0 and isa == round(info["ops_per_step"] * terms), (ccs[0], m, isa, info["ops_per_step"] * terms)
+            pair = 1 if "pair0" in head else 0
+            # static blocks of 2^(u+1) steps; with pairing a step covers two terms
+            iters = 2 ** (info["chunk_log2"] - pair - info["unroll_log2"] - 1)
+            loop, total = _fp64_instructions(src)
+            if iters >= 2:
+                want = (loop * iters + total - loop) / 2.0 ** info["chunk_log2"]
+                assert loop > 0
+            else:  # one pass over the chunk: straight-line code
+                want = total / 2.0 ** info["chunk_log2"]
+            assert info["ops_per_step"] == want, (ccs[0], m, loop, total, info)
             assert info["ops_per_step"] <= info["flops_per_step"] <= 2 * info["ops_per_step"]
 
 
