@@ -153,10 +153,12 @@ int auto_unroll(bool zero_skip) { return zero_skip ? 6 : 7; }
 
 // Copies of the most frequent columns' rows (nested kernels): at most this
 // many extra doubles per lane in the automatic choice.  With pairing the
-// matrices are sparse and the copies the main use of registers (n = 40:
-// 150 doubles in 344 VGPRs, one wave per SIMD, still the fastest);
-// without pairing the rows are dense and the rest of the kernel takes more
-// (n = 36, d = 0.30: copies of 6 columns spill, of 4 fit 336 VGPRs).
+// matrices are sparse, values the loop never changes leave it, and one
+// wave per SIMD with the fewest operations is fastest (n = 40: copies of
+// 12 columns in 354 VGPRs, 2.3 ms, against 3.3 ms with 10 in 304); without
+// pairing the rows are dense and the rest of the kernel takes more
+// registers (n = 36, d = 0.30: copies of 6 columns spill, of 4 fit 336
+// VGPRs).
 constexpr int kMaxCopyValuesPaired = 400;
 constexpr int kMaxCopyValues = 112;
 
