@@ -1293,6 +1293,7 @@ std::string generate_source(const Plan &p, LoopCount *lc) {
         lc->flops_per_step = g.loop_flops;
         lc->loop = g.loop_iters > 1;
         lc->iters = g.loop_iters;
+        lc->body_ops = g.cnt_ops;
         lc->terms_per_iter = g.loop_terms;
         lc->sign_fmas = g.sign_fmas;
         int cv = 0;

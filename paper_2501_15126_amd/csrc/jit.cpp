@@ -10,6 +10,7 @@
 #include <hip/hiprtc.h>
 
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -172,6 +173,12 @@ void count_loop_fp64(CodeObject *co) {
     };
     std::vector<Ins> ins;
     std::vector<std::pair<uint64_t, uint64_t>> loops;  // (target, branch address)
+    // long branches (bodies beyond a branch's reach): s_getpc_b64 s[k:k+1]
+    // (the next instruction's address), s_add_u32 sk, sk, offset, ...,
+    // s_setpc_b64 s[k:k+1]
+    std::string pc_reg;
+    uint64_t pc_base = 0, pc_target = 0;
+    bool pc_known = false;
     for (uint64_t a = d.base; a < d.base + d.size;) {
         uint64_t sz = 0;
         d.text.clear();
@@ -188,6 +195,42 @@ void count_loop_fp64(CodeObject *co) {
         ins.push_back({a, kind});
         if (d.has_target && d.target <= a && (op.rfind("s_cbranch", 0) == 0 || op == "s_branch"))
             loops.push_back({d.target, a});
+        const std::string args = t.size() > op.size() ? t.substr(op.size()) : std::string();
+        auto operands = [&]() {
+            std::vector<std::string> v;
+            std::string cur;
+            for (char ch : args) {
+                if (ch == ',') {
+                    v.push_back(cur);
+                    cur.clear();
+                } else if (ch != ' ' && ch != '\t') {
+                    cur += ch;
+                }
+            }
+            if (!cur.empty()) v.push_back(cur);
+            return v;
+        };
+        if (op == "s_getpc_b64") {
+            const auto v = operands();
+            pc_reg = v.empty() ? "" : v[0];  // s[k:k+1]
+            pc_base = a + sz;
+            pc_known = false;
+        } else if (op == "s_add_u32" && !pc_reg.empty()) {
+            const auto v = operands();
+            const std::string lo = "s" + pc_reg.substr(2, pc_reg.find(':') - 2);
+            if (v.size() == 3 && v[0] == lo && v[1] == lo) {
+                char *end = nullptr;
+                const unsigned long long off = strtoull(v[2].c_str(), &end, 0);
+                if (end && *end == 0) {
+                    pc_target = pc_base + (uint64_t)(int64_t)(int32_t)(uint32_t)off;
+                    pc_known = true;
+                }
+            }
+        } else if (op == "s_setpc_b64" && pc_known) {
+            const auto v = operands();
+            if (!v.empty() && v[0] == pc_reg && pc_target <= a) loops.push_back({pc_target, a});
+            pc_known = false;
+        }
         a += sz;
     }
     amd_comgr_destroy_disassembly_info(info);

@@ -125,6 +125,7 @@ struct LoopCount {
     double ops_per_step = 0, flops_per_step = 0;
     bool loop = false;          // the step loop runs more than once per chunk
     uint64_t iters = 0;         // its iterations per chunk
+    double body_ops = 0;        // the generator's count of one iteration's varying operations
     double terms_per_iter = 0;  // Gray terms of one loop iteration
     int sign_fmas = 0;          // FMAs per iteration that add a signed table entry (1 flop each)
     int copy_values = 0;        // extra doubles the copies of columns 1..copy_cols keep

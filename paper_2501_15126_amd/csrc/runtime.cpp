@@ -178,6 +178,10 @@ void use_compiled_count(Prepared *p, const CodeObject &co) {
     }
     if (co.loop_add < 0) return;
     const double loop = co.loop_add + co.loop_mul + co.loop_fma;
+    // the loop found in the machine code must be the step loop: far fewer
+    // FP64 instructions than the generator counts for one iteration means
+    // it was not found, and the generator's count stays
+    if (loop < 0.25 * p->lc.body_ops) return;
     const double loop_fl = co.loop_add + co.loop_mul + 2.0 * co.loop_fma - p->lc.sign_fmas;
     p->plan.ops_per_step = (loop * it + (all - loop)) / t;
     p->plan.flops_per_step = (loop_fl * it + (all_fl - loop_fl)) / t;

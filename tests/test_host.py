@@ -622,10 +622,18 @@ def _fp64_instructions(src):
     fp = [bool(re.match(r"\s+v_(add|mul|fma|fmac)_f64", x)) for x in asm]
     labels = {m.group(1): i for i, line in enumerate(asm) if (m := re.match(r"^(\.LBB\d+_\d+):", line))}
     loops = []
+    far = None  # a long branch's target: s_getpc_b64, s_add_u32 ... (label - pc), s_setpc_b64
     for i, line in enumerate(asm):
         m = re.search(r"s_c?branch\w*\s+(\.LBB\d+_\d+)", line)
         if m and labels.get(m.group(1), i) < i:
             loops.append((labels[m.group(1)], i))
+        m = re.search(r"s_add_u32\s+s\d+,\s*s\d+,\s*\((\.LBB\d+_\d+)-\.Lpost_getpc", line)
+        if m:
+            far = m.group(1)
+        if "s_setpc_b64" in line and far is not None:
+            if labels.get(far, i) < i:
+                loops.append((labels[far], i))
+            far = None
     best = 0
     for a, b in loops:
         inner = not any(a <= a2 and b2 <= b and (a2, b2) != (a, b) and any(fp[a2:b2]) for a2, b2 in loops)
@@ -642,8 +650,10 @@ def test_loop_operation_count_matches_isa(P):
     reading, gives exactly the same, with and without copies of the most
     frequent columns' rows."""
     for ccs, ms, u in ((W.single_01(40, 0.10, 1), (-1, 1, 3, 8), 9), (W.single_01(40, 0.10, 1), (0,), 0),
-                       (W.single_01(36, 0.15, 1), (-1, 3, 0), 9), (W.single_real(36, 0.30, 1), (0,), 0)):
-        # (the last without pairing; u = 0: the default static block, for n = 40 the whole chunk)
+                       (W.single_01(36, 0.15, 1), (-1, 3, 0), 9), (W.single_real(36, 0.30, 1), (0,), 0),
+                       (W.single_real(36, 0.30, 1), (0,), 10)):
+        # (the last two without pairing, the last with a loop body beyond a
+        # branch's reach; u = 0: the default static block, for n = 40 the whole chunk)
         for m in ms:
             opts = dict(zero_skip=False, exact=False, copy_cols=m, waves_per_simd=-1, unroll_log2=u)
             src = P.perm_codegen(ccs, **opts)
