@@ -441,6 +441,7 @@ def main():
     opts, tune = tuned(mode=args.mode, zero_skip=False, exact=False)
     chosen = {k: opts.get(k) for k in ("mode", "chunk_log2", "unroll_log2", "block", "waves_per_simd",
                                           "block_queue", "cold_tier") if k in opts}
+    print("bench: headline, %d timed permanents" % args.steps, file=sys.stderr, flush=True)
     elapsed, kernel_ms, evaluated, values, st, first = timed_calls(opts, args.steps, args.warmup)
     kern = kernel_record(st, kernel_ms, evaluated, first)
     avg_kernel_s = kern["avg_ms"] / 1e3
@@ -484,7 +485,9 @@ def main():
     # ---- the same, with the exact mode's certificate (residue modulo a
     # prime and a rigorous FP64 error bound), same launch options ----
     if not args.no_exact_leg:
-        xopts = dict(opts, exact="auto")
+        print("bench: exact all-terms leg", file=sys.stderr, flush=True)
+        # the tuned launch shape, but the exact kernels' own static block and copies
+        xopts = dict(opts, exact="auto", unroll_log2=0, copy_cols=0)
         xel, xk, xev, xvals, xst, xfirst = timed_calls(xopts, max(2, args.steps // 4), 1)
         xkern = kernel_record(xst, xk, xev, xfirst)
         out["exact_all_terms"] = {
@@ -492,6 +495,7 @@ def main():
             "kernel": xkern, "permanent": xvals[-1], "certified": xst["exact"] == 1,
             "note": "every term evaluated, plus the residue and error-bound operations that certify the integer"}
     if args.zero_skip != "off" and not args.no_pruned:
+        print("bench: pruned leg", file=sys.stderr, flush=True)
         out["pruned"] = pruned_leg()
     if not args.no_batch:
         bopts = None

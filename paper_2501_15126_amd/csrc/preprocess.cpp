@@ -166,6 +166,9 @@ constexpr int kMaxCopyValues = 112;
 // fraction of their FP64 operations or below (see make_plan).
 constexpr double kNestedGain = 0.6;
 
+// Largest static block (log2) of kernels other than nested ones with pairing.
+constexpr int kMaxUnrollCached = 9;
+
 // The extra doubles the copies of the walk's first m columns keep (the
 // generator's layout: rows, multi-row levels, the tracked bracket).
 int copy_values(const Plan *p, int m) {
@@ -632,6 +635,10 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         p->flops_per_step = pfl / steps;
         p->exact_ops_per_step = pxo / steps;
     }
+    // Static blocks beyond 2^9 steps only for nested kernels with pairing
+    // (other kernels' blocks of that size compile for minutes and gain
+    // nothing): larger values given are reduced.
+    if (!(p->pair0 && p->nested)) p->u = std::min(p->u, kMaxUnrollCached);
     // Nested accumulation without pairing (AUTO, all terms, FP64): level 0's
     // own product starts c_0, and the copied columns are 0..m-1.  Taken when
     // the generator's count of its best form is at most kNestedGain of the
@@ -647,6 +654,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         // static blocks of 2^6 steps by default: without pairing the steps
         // are denser, and longer blocks compile slowly for little gain
         if (o.unroll_log2 == 0) q.u = std::max(0, std::min(6, p->kappa - 1));
+        q.u = std::min(q.u, kMaxUnrollCached);
         LoopCount best;
         const int m = choose_copies(&q, o, std::min(q.u, n - 1), &best, nullptr);
         if (m >= 0 && (o.copy_cols > 0 || best.ops_per_step <= kNestedGain * p->ops_per_step)) {
