@@ -201,6 +201,11 @@ typedef struct {
     double estimate;        /* the FP64 estimate of the permanent */
     double err_bound;       /* exact mode: rigorous bound on |estimate - perm| */
     double exact_ops_per_step; /* of ops_per_step: the exact mode's residue and bound operations */
+    int32_t exact_bound_log2;  /* exact mode: log2 of the operation count per chunk that the
+                                  error bound takes (perm_exact_recover's chunk_log2 for this
+                                  kernel: chunk_log2, or more with nested accumulators); 0 outside
+                                  the exact mode */
+    int32_t pad_stats;
 } perm_stats;
 
 /* Permanent of one matrix (Alg. 1 end to end).  Returns NaN on error

@@ -100,6 +100,13 @@ struct Gen {
     // c_1 .. c_{T-1} are empty at the loop's end and are taken as empty at
     // its top (their registers hold 0 on entry).
     bool horner = false;
+    // Exact mode in nested form: beside c_l, r_l (the sum's residue modulo
+    // the prime, reduced at every move) and a_l (the sum of |term| for the
+    // error bound), moved up through RP_l (P_l's residue) and |P_l|.
+    bool hx = false;
+    long acc_written = 0;  // accumulator operations as written (per chunk; the error bound's length)
+    long body_acc = 0;     // of those, one loop iteration's
+    double acc_chunk = 0;  // all of one chunk
     std::vector<char> cz;
     int loop_top = 0;  // T
 
@@ -276,6 +283,27 @@ struct Gen {
                 os << I << cl << " = fma(" << cb << ", " << pname(l) << ", " << cl << ");\n";
                 note(cl, "fma", {cb, pname(l), cl}, 2);
             }
+            ++acc_written;
+            if (hx) {
+                const std::string al = "a" + std::to_string(l), ab = "a" + std::to_string(l - 1);
+                const std::string rl = "r" + std::to_string(l), rb = "r" + std::to_string(l - 1);
+                const std::string rp = "R" + pname(l), t = fresh();
+                if (cz[l]) {
+                    os << I << al << " = " << ab << " * fabs(" << pname(l) << ");\n";
+                    note(al, "mula", {ab, pname(l)}, 1);
+                    os << I << "const double " << t << " = " << rb << " * " << rp << ";\n";
+                    note(t, "mul", {rb, rp}, 1);
+                } else {
+                    os << I << al << " = fma(" << ab << ", fabs(" << pname(l) << "), " << al << ");\n";
+                    note(al, "fmaa", {ab, pname(l), al}, 2);
+                    os << I << "const double " << t << " = fma(" << rb << ", " << rp << ", " << rl << ");\n";
+                    note(t, "fma", {rb, rp, rl}, 2);
+                }
+                // |r_{l-1}|, |RP_l| < 2^23 + 2: the product and the sum are exact
+                const std::string red = reduce_expr(t, I);
+                os << I << rl << " = " << red << ";\n";
+                note(rl, "red", {t}, 1);
+            }
             cz[l] = 0;
             if (l >= 2) cz[l - 1] = 1;
         }
@@ -354,8 +382,33 @@ struct Gen {
     std::string mulmod(const std::string &q, const std::string &r, const char *I) {
         const std::string t = fresh(), m = fresh();
         os << I << "const double " << t << " = " << q << " * " << r << ";\n";
-        os << I << "const double " << m << " = fma(-rint(" << t << " * pinv), pmod, " << t << ");\n";
+        note(t, "mul", {q, r}, 1);
+        const std::string red = reduce_expr(t, I);  // emits the quotient first
+        os << I << "const double " << m << " = " << red << ";\n";
+        note(m, "red", {t}, 1);
         return m;
+    }
+    // t reduced modulo the prime (an exact remainder for exact t below 2^53;
+    // the quotient's multiply is an FP64 operation of its own)
+    std::string reduce_expr(const std::string &t, const char *I) {
+        const std::string q = fresh();
+        os << I << "const double " << q << " = rint(" << t << " * pinv);\n";
+        note(q, "quot", {t}, 1);
+        return "fma(-" + q + ", pmod, " + t + ")";
+    }
+    // RP_l of copy sigma: the residue of level l's product, from its exact
+    // sub-products (each at most 2^20 in magnitude)
+    void level_residue(int l, unsigned sigma, std::map<int, std::string> &cur, const char *I, bool decl = false) {
+        std::vector<std::string> qs;
+        for (const auto &part : p.level_parts[l]) {
+            std::vector<std::string> v;
+            for (int r : part) v.push_back(cm && (Tr[r] & sigma) ? xv(r, sigma) : value_of(r, cur, I));
+            qs.push_back(product(v, I));
+        }
+        const std::string res = residue_chain(qs, 0, "", I);
+        const std::string name = "R" + sub("P" + std::to_string(l), sigma);
+        os << I << (decl ? "double " : "") << name << " = " << res << ";\n";
+        alias(name, res);
     }
 
     // residue of sub-products qs[from..] times `r` (r empty: no factor)
@@ -368,7 +421,7 @@ struct Gen {
     // 2^20 (2^23 + 2) each it is below 2^53, where rint(racc / p) is exact
     // enough for an exact remainder.
     void reduce_racc(const char *I) {
-        if (p.exact) os << I << "racc = fma(-rint(racc * pinv), pmod, racc);\n";
+        if (p.exact && !hx) os << I << "racc = fma(-rint(racc * pinv), pmod, racc);\n";
     }
 
     // x updates of one Gray step flipping column j in direction sg; updated
@@ -415,7 +468,7 @@ struct Gen {
 
     // Recompute the cached product of level l: S_l = prod(level l) * S_{l+1}.
     void refresh_level(int l, std::map<int, std::string> &cur, const char *I) {
-        if (p.exact) {
+        if (p.exact && !horner) {
             // S_l = P_l * S_{l+1} in FP64; R_l = P_l R_{l+1} modulo the prime
             const std::vector<std::string> qs = part_products(l, cur, I);
             const std::string pl = product(qs, I);
@@ -435,12 +488,14 @@ struct Gen {
             const std::string pr = product(v, I);
             os << I << "P" << l << " = " << pr << ";\n";
             alias("P" + std::to_string(l), pr);
+            if (hx) level_residue(l, 0u, cur, I);
             if (cm)
                 for (unsigned sgm : subsets(Tl[l])) {
                     if (!sgm) continue;
                     const std::string pi = product(level_values_in(l, sgm, cur, I), I);
                     os << I << sub("P" + std::to_string(l), sgm) << " = " << pi << ";\n";
                     alias(sub("P" + std::to_string(l), sgm), pi);
+                    if (hx) level_residue(l, sgm, cur, I);
                 }
             return;
         }
@@ -526,6 +581,26 @@ struct Gen {
                 } else {
                     os << I << "c0 = c0 + " << sg << d << ";\n";
                     note("c0", *sg ? "subc" : "addc", {"c0", d}, 1);
+                    ++acc_written;
+                }
+                if (hx) {
+                    // exact mode: d is an integer of at most 2^20 (y units), its
+                    // own residue; r_0 is brought back to range after each add
+                    if (fresh_run) {
+                        os << I << "a0 = fabs(" << d << ");\n";
+                        derive("a0", "abs", {d});
+                        os << I << "r0 = " << sg << d << ";\n";
+                        derive("r0", *sg ? "neg" : "id", {d});
+                    } else {
+                        os << I << "a0 = a0 + fabs(" << d << ");\n";
+                        note("a0", "adda", {"a0", d}, 1);
+                        const std::string t = fresh();
+                        os << I << "const double " << t << " = r0 + " << sg << d << ";\n";
+                        note(t, *sg ? "subc" : "addc", {"r0", d}, 1);
+                        const std::string red = reduce_expr(t, I);
+                        os << I << "r0 = " << red << ";\n";
+                        note("r0", "red", {t}, 1);
+                    }
                 }
                 return;
             }
@@ -722,7 +797,9 @@ struct Gen {
         // (column-0 pairing: paired steps flipping columns 1 ..)
         const int c0 = p.pair0 ? 1 : 0;
         const int kw = kappa - c0;
-        horner = p.nested && !p.exact && !p.cold && L >= 2;
+        horner = p.nested && !p.cold && L >= 2;
+        hx = horner && p.exact;
+        if (hx && !p.pair0) os << "#error exact nested kernels are paired\n";  // the plan pairs them
         dtrack = horner && p.pair0 && p.B.colptr[1] - p.B.colptr[0] == 2;
         cm = horner ? p.copy_cols : 0;
         cbase = c0;
@@ -895,7 +972,7 @@ struct Gen {
                 }
         }
         for (int l = L - 1; l >= lv0; --l) {
-            if (p.exact) {
+            if (p.exact && !horner) {
                 const std::vector<std::string> qs = part_products(l, cur, "  ");
                 const std::string pl = product(qs, "  ");
                 os << "  double S" << l << " = " << pl << (l + 1 < L ? " * S" + std::to_string(l + 1) : "") << ";\n";
@@ -907,10 +984,12 @@ struct Gen {
             if (horner) {
                 const std::string pr = product(v, "  ");
                 os << "  double P" << l << " = " << pr << ";\n";
+                if (hx) level_residue(l, 0u, cur, "  ", true);
                 for (unsigned sgm : subsets(Tl[l])) {
                     if (!sgm) continue;
                     const std::string pi = product(level_values_in(l, sgm, cur, "  "), "  ");
                     os << "  double " << sub("P" + std::to_string(l), sgm) << " = " << pi << ";\n";
+                    if (hx) level_residue(l, sgm, cur, "  ", true);
                 }
                 continue;
             }
@@ -938,8 +1017,14 @@ struct Gen {
             os << "  double c0 = 0.0";
             for (int l = 1; l < L; ++l) os << ", c" << l << " = 0.0";
             os << ";\n";
+            if (hx) {
+                os << "  double a0 = 0.0, r0 = 0.0";
+                for (int l = 1; l < L; ++l) os << ", a" << l << " = 0.0, r" << l << " = 0.0";
+                os << ";\n";
+            }
             std::fill(cz.begin(), cz.end(), 0);
         }
+        acc_written = 0;
         accumulate(+1, 0, cur, "  ", nullptr, true);  // term g = m 2^kappa (even index: sign +)
         // ---- Gray loop over local steps 1 .. 2^kappa - 1 ----
         if (kappa >= 1) {
@@ -1118,6 +1203,7 @@ struct Gen {
                     const std::vector<char> cz0 = cz;
                     const unsigned ts0 = ts;
                     const std::vector<char> dirty0 = dirty;
+                    const long acc0_written = acc_written;
                     track = true;
                     vid.clear();
                     interned.clear();
@@ -1131,6 +1217,7 @@ struct Gen {
                     cz = cz0;
                     ts = ts0;
                     dirty = dirty0;
+                    acc_written = acc0_written;
                     vid.clear();
                     unit.clear();
                     for (const std::string &a : assigned) vid[a] = {intern("phi:" + a), true};
@@ -1139,6 +1226,7 @@ struct Gen {
                     counting = true;
                     all_vary = DW == (uint64_t)(2 * U);  // one pass: nothing to hoist
                     body();
+                    body_acc = acc_written - acc0_written;
                     counting = track = all_vary = false;
                     const double terms = (double)(2 * U) * evm;
                     loop_terms = terms;
@@ -1195,14 +1283,16 @@ struct Gen {
             }
             if (skip_chunk) os << "  }\n";
         }
-        if (p.exact) {
-            reduce_racc("  ");
-            os << "  xo[0] = racc; xo[1] = accA;\n";
-        }
         if (horner) {
             // everything up to the top level: c_{L-1} is the chunk's sum
             flush_to(L - 1, "  ");
             os << "  acc0 = c" << L - 1 << ";\n";
+            if (hx) os << "  racc = r" << L - 1 << "; accA = a" << L - 1 << ";\n";
+            acc_chunk = (double)acc_written + (double)body_acc * ((double)std::max<uint64_t>(loop_iters, 1) - 1.0);
+        }
+        if (p.exact) {
+            reduce_racc("  ");
+            os << "  xo[0] = racc; xo[1] = accA;\n";
         }
         os << "  return two_sum(acc0, acc1);\n}\n";
         // ---- the kernel: one chunk per lane, then a deterministic reduction
@@ -1302,6 +1392,9 @@ std::string generate_source(const Plan &p, LoopCount *lc) {
             if (g.level_rows[l].size() > 1) cv += (1 << __builtin_popcount(g.Tl[l])) - 1;
         if (g.cm) cv += (1 << __builtin_popcount(g.T0)) - 1;
         lc->copy_values = cv;
+        int al = 0;
+        while (std::ldexp(1.0, al) < g.acc_chunk + p.n + 2) ++al;
+        lc->acc_log2 = al;
     }
     return src;
 }

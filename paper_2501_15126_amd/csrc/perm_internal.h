@@ -95,6 +95,10 @@ struct Plan {
     // entries in or out, so that flipping one only selects other copies;
     // chosen by the generator's operation count (0: none).
     int copy_cols = 0;
+    // Exact mode: log2 of a bound on the accumulator operations any term's
+    // value passes through in one chunk (the error bound's length; the
+    // cached-product kernels use kappa, one accumulate per term).
+    int acc_log2 = 0;
     // Exact mode (integer-valued matrices): B holds 2a, so x is y = 2x, an
     // integer; the kernel also keeps the term sum modulo a prime and the two
     // sums of its error bound (exact.h).  Each level's product is formed from
@@ -129,6 +133,7 @@ struct LoopCount {
     double terms_per_iter = 0;  // Gray terms of one loop iteration
     int sign_fmas = 0;          // FMAs per iteration that add a signed table entry (1 flop each)
     int copy_values = 0;        // extra doubles the copies of columns 1..copy_cols keep
+    int acc_log2 = 0;           // log2 of a bound on the accumulator operations per chunk plus n
 };
 std::string generate_source(const Plan &p, LoopCount *lc = nullptr);
 // Kernel entry point name inside every generated module.

@@ -161,6 +161,9 @@ int auto_unroll(bool zero_skip) { return zero_skip ? 6 : 7; }
 // VGPRs).
 constexpr int kMaxCopyValuesPaired = 400;
 constexpr int kMaxCopyValues = 112;
+// exact mode (paired): the copies' values with the levels' residues; 128
+// keeps the n = 40 workload's kernel within 256 VGPRs (two waves per SIMD)
+constexpr int kMaxCopyValuesExact = 128;
 
 // Nested kernels without pairing replace the cached products only at this
 // fraction of their FP64 operations or below (see make_plan).
@@ -191,8 +194,9 @@ int copy_values(const Plan *p, int m) {
         }
     long cv = 0;
     for (int r = 0; r < p->n; ++r) cv += (1l << __builtin_popcount(Tr[r])) - 1;
+    // a level's copies (exact mode: with their residues)
     for (int l = 1; l < p->nlevels; ++l)
-        if (lsize[l] > 1) cv += (1l << __builtin_popcount(Tl[l])) - 1;
+        if (lsize[l] > 1) cv += ((1l << __builtin_popcount(Tl[l])) - 1) * (p->exact ? 2 : 1);
     cv += (1l << __builtin_popcount(T0)) - 1;
     return (int)std::min<long>(cv, INT_MAX);
 }
@@ -209,7 +213,7 @@ int copy_values(const Plan *p, int m) {
 int choose_copies(const Plan *p, const perm_opts &o, int mmax, LoopCount *best, LoopCount *base) {
     mmax = p->u >= 1 ? std::max(0, mmax) : 0;
     const int want = o.copy_cols < 0 ? 0 : o.copy_cols > 0 ? std::min(o.copy_cols, mmax) : -1;
-    const int cap = p->pair0 ? kMaxCopyValuesPaired : kMaxCopyValues;
+    const int cap = p->exact ? kMaxCopyValuesExact : p->pair0 ? kMaxCopyValuesPaired : kMaxCopyValues;
     std::vector<int> cands;
     if (want >= 0) {
         cands.push_back(want);
@@ -494,10 +498,12 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         }
         if (ok) {
             p->pair0 = true;
-            // FP64: static blocks as long as the chunk allows, up to 2^12
-            // paired steps, by default (the more of the walk's columns are
-            // static, the more can be kept in copies)
-            if (o.unroll_log2 == 0 && !ex) p->u = 12;
+            // nested kernels: static blocks as long as the chunk allows, up
+            // to 2^12 paired steps (FP64) or 2^9 (exact: the residues take
+            // registers of their own, fewer columns are copied), by default
+            // (the more of the walk's columns are static, the more can be
+            // kept in copies)
+            if (o.unroll_log2 == 0) p->u = ex ? 9 : 12;
             p->u = std::min(p->u, p->kappa - 2);  // a static block of paired steps fits the chunk's half
             // two entries: the row that lower (more often flipped) columns
             // touch goes in the outer FMA of the bracket, so that a flip of
@@ -566,7 +572,9 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         // the accumulate and the accumulators' moves does a multiply and an
         // add the sum needs (2 flops each).
         const int d0 = B.colptr[1] - B.colptr[0];
-        const bool nest = !ex && L >= 2;
+        // nested form: FP64, and the exact mode too (residues and |term|
+        // sums move up beside the FP64 accumulators)
+        const bool nest = L >= 2;
         double pops = 0.0, pfl = 0.0, pxo = 0.0;
         for (int j = 1; j < n - 1; ++j) {
             const int t = p->col_top[j];
@@ -628,6 +636,14 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
                 p->copy_cols = m;
                 pops = best.ops_per_step * steps;
                 pfl = best.flops_per_step * steps;
+                if (ex) pxo = 0.0;  // counted with the rest
+                p->acc_log2 = best.acc_log2;
+            }
+            if (ex && p->acc_log2 == 0) {
+                // no count: each of a chunk's paired steps moves at most L
+                // accumulators and adds one bracket
+                const double F = std::ldexp(1.0, p->kappa - 1) * (L + 1) + n + 2;
+                while (std::ldexp(1.0, p->acc_log2) < F) ++p->acc_log2;
             }
         }
         p->ops_of_col[0] = 0.0;

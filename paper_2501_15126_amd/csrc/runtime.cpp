@@ -271,6 +271,11 @@ perm_status compile_plan(const perm_csc *m, const perm_opts &o, Prepared *p, Cod
     return PERM_OK;
 }
 
+// Length of the exact mode's error bound: a chunk's accumulate operations
+// (one per term for the cached-product kernels; nested accumulators: the
+// generator's count of every accumulator operation of a chunk, plus n).
+int exact_bound_log2(const Plan &pl) { return pl.nested ? std::max(pl.acc_log2, pl.kappa) : pl.kappa; }
+
 void fill_plan_stats(const Prepared &p, perm_stats *st) {
     st->n = p.a.n;
     st->nnz = p.a.nnz();
@@ -290,6 +295,7 @@ void fill_plan_stats(const Prepared &p, perm_stats *st) {
     st->flops_per_step = pl.flops_per_step;
     st->exact_ops_per_step = pl.exact_ops_per_step;
     st->exact = pl.exact ? 0 : -1;  // set to 1 once a result is certified
+    st->exact_bound_log2 = pl.exact ? exact_bound_log2(pl) : 0;
     st->nchunks = (int64_t)1 << (pl.n - 1 - pl.kappa);
     st->nblocks = (st->nchunks + pl.block - 1) / pl.block;
 }
@@ -519,7 +525,7 @@ perm_status run_one(const perm_csc *m, const perm_opts *opts, double *out, perm_
         es.hi = po.hi;
         es.lo = po.lo;
         es.abs_sum = po.abs_sum;
-        es.chunk_log2 = pl.kappa;
+        es.chunk_log2 = exact_bound_log2(pl);
         es.resid[pass] = po.resid;
         es.passes = pass + 1;
         eo = exact_recover(pl.n, es);

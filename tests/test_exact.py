@@ -151,7 +151,7 @@ def test_generated_exact_residues_match_oracle(P, oracle_mod, mode, tier):
                 res.append(info["resid"])
             assert abs(info["hi"] + info["lo"] - T) <= 1e-12 * info["abs_sum"] + 0.5
             v, est, bound, cert, more = P.exact_recover(n, info["hi"], info["lo"], info["abs_sum"],
-                                                        info["chunk_log2"], res[:1])
+                                                        info["exact_bound_log2"], res[:1])
             assert cert and v == perm, (n, mode, tier, zs, v, perm)
 
 
@@ -171,7 +171,7 @@ def test_generated_exact_integer_values(P, oracle_mod):
         got, info = _emulated(P, ccs, chunk_log2=min(3, n - 1), unroll_log2=1)
         assert info["exact"] == 0
         p = P.exact_primes()[0]
-        v, est, bound, cert, more = P.exact_recover(n, info["hi"], info["lo"], info["abs_sum"], info["chunk_log2"],
+        v, est, bound, cert, more = P.exact_recover(n, info["hi"], info["lo"], info["abs_sum"], info["exact_bound_log2"],
                                                     [info["resid"]])
         assert cert and v == ref, (t, v, ref)
 

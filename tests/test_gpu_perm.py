@@ -176,6 +176,12 @@ def test_n24_full_exact(P, oracle_mod):
         for mode, tier in (("auto", "global"), ("pure", "global"), ("hybrid", "global"), ("hybrid", "lds")):
             got, st = P.perm_sparse_ex(ccs, mode=mode, cold_tier=tier)
             assert got == float(int(rec["perm_exact"])), (seed, mode, tier, got)
+        # every term (no zero-aware skipping): the paired kernels with nested
+        # accumulators, their residues and |term| sums, with and without copies
+        for m in (-1, 0, 3):
+            got, st = P.perm_sparse_ex(ccs, zero_skip=False, copy_cols=m)
+            assert got == float(int(rec["perm_exact"])) and st["exact"] == 1, (seed, m, got)
+            assert abs(st["estimate"] - got) <= st["err_bound"], (seed, m)
 
 
 def test_n24_block_partials_vs_oracle(P, oracle_mod):

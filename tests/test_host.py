@@ -733,10 +733,19 @@ def test_column0_pairing_on_cpu(P, oracle_mod):
             assert info["evaluated"] == 1 << (ccs[0] - 1)
             assert abs(got - ref) <= 1e-13 * abs_sum + 1e-15, (ccs[0], kappa, u, m, got, ref)
     # the exact mode pairs too: the pair's bracket is an integer (y units),
-    # its residue d R_1; residues and the recovered count against the oracle
-    for ccs, kappa, u in ((W.single_01(16, 0.2, 2), 7, 3), (W.single_01(20, 0.1, 6), 12, 4)):
-        opts = dict(chunk_log2=kappa, unroll_log2=u, zero_skip=False)
-        assert "pair0" in P.perm_codegen(ccs, **opts).splitlines()[0]
+    # its residue d R_1; with two levels or more the residues and |term| sums
+    # move up beside the FP64 accumulators, and the error bound's length is
+    # the chunk's accumulator operations (at least chunk_log2); residues and
+    # the recovered count against the oracle, with and without copies
+    for ccs, kappa, u, m in ((W.single_01(16, 0.2, 2), 7, 3, 0), (W.single_01(20, 0.1, 6), 12, 4, 0),
+                             (W.single_01(20, 0.1, 6), 12, 4, 3), (W.single_01(18, 0.15, 3), 9, 5, -1)):
+        opts = dict(chunk_log2=kappa, unroll_log2=u, zero_skip=False, copy_cols=m)
+        head = P.perm_codegen(ccs, **opts).splitlines()[0]
+        assert "pair0" in head and " nested" in head, head
+        if m:
+            assert (" copies=" in head) == (m > 0), head  # 0: the plan's choice
+        bl = P.compile_info(ccs, **opts)["exact_bound_log2"]
+        assert kappa <= bl <= kappa + 3, (kappa, bl)
         res = []
         for pm in P.exact_primes():
             got, info = _emulate(P, ccs, prime=pm, **opts)
@@ -744,9 +753,9 @@ def test_column0_pairing_on_cpu(P, oracle_mod):
             res.append(info["resid"])
         perm = O.perm_int(ccs)
         v, est, bound, cert, more = P.exact_recover(ccs[0], info["hi"], info["lo"], info["abs_sum"],
-                                                    info["chunk_log2"], res[:1])
+                                                    info["exact_bound_log2"], res[:1])
         assert cert and v == perm, (ccs[0], v, perm)
-        v3 = P.exact_recover(ccs[0], info["hi"], info["lo"], info["abs_sum"], info["chunk_log2"], res)[0]
+        v3 = P.exact_recover(ccs[0], info["hi"], info["lo"], info["abs_sum"], info["exact_bound_log2"], res)[0]
         assert v3 == perm
     # not paired: zero-aware kernels, HYBRID
     ccs = W.single_01(16, 0.2, 2)
