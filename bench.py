@@ -487,7 +487,7 @@ def main():
     if not args.no_exact_leg:
         print("bench: exact all-terms leg", file=sys.stderr, flush=True)
         # the tuned launch shape, but the exact kernels' own static block and copies
-        xopts = dict(opts, exact="auto", unroll_log2=0, copy_cols=0)
+        xopts = dict(opts, exact="auto", chunk_log2=0, unroll_log2=0, copy_cols=0)
         xel, xk, xev, xvals, xst, xfirst = timed_calls(xopts, max(2, args.steps // 4), 1)
         xkern = kernel_record(xst, xk, xev, xfirst)
         out["exact_all_terms"] = {

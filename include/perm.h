@@ -76,10 +76,11 @@ typedef enum { PERM_MODE_AUTO = 0, PERM_MODE_PURE = 1, PERM_MODE_HYBRID = 2 } pe
 /* Options; pass NULL for all defaults, or zero-initialise and set fields. */
 typedef struct {
     int32_t mode;          /* perm_mode */
-    int32_t chunk_log2;    /* log2 of Gray steps per lane chunk; 0 = automatic */
+    int32_t chunk_log2;    /* log2 of Gray steps per lane chunk; 0 = automatic (FP64 kernels
+                              with column-0 pairing at n >= 37: 15) */
     int32_t unroll_log2;   /* log2 of the static unrolled block, at most 13; 0 = automatic (7,
-                              zero-aware kernels 6, nested kernels without pairing 6, FP64
-                              kernels with column-0 pairing 12).  Always at most chunk_log2 - 1,
+                              zero-aware kernels 6, nested kernels without pairing 6, kernels
+                              with column-0 pairing 13, exact 9).  Always at most chunk_log2 - 1,
                               paired kernels chunk_log2 - 2; values above 9 are reduced to 9
                               except for nested kernels with pairing */
     int32_t block;         /* threads per workgroup, multiple of 64, <= 1024; 0 = 256 */
