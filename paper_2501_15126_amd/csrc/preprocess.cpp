@@ -187,6 +187,12 @@ constexpr double kNestedGain = 0.6;
 // Largest static block (log2) of kernels other than nested ones with pairing.
 constexpr int kMaxUnrollCached = 9;
 
+// Paired FP64 kernels take static blocks beyond 2^9 steps by default only
+// when their best count at 2^9 is at most this many FP64 operations per
+// term (n = 40, d = 0.10: 0.35; ER n = 40..45, p = 0.1: 0.11..0.15; a
+// column-0 pair in ER n = 40, p = 0.2..0.3: 1.5..3.2).
+constexpr double kBigBlockMaxOps = 0.6;
+
 // The extra doubles the copies of the walk's first m columns keep (the
 // generator's layout: rows, multi-row levels, the tracked bracket).
 int copy_values(const Plan *p, int m) {
@@ -225,10 +231,10 @@ int copy_values(const Plan *p, int m) {
 // operations) and the two below it; the fewest operations win, a further
 // column having to save at least 1 %.  copy_cols forces m (-1: none).  *base
 // gets the count without copies.  Returns -1 if nothing was counted.
-int choose_copies(const Plan *p, const perm_opts &o, int mmax, LoopCount *best, LoopCount *base) {
+int choose_copies(const Plan *p, const perm_opts &o, int mmax, LoopCount *best, LoopCount *base, int cap = 0) {
     mmax = p->u >= 1 ? std::max(0, mmax) : 0;
     const int want = o.copy_cols < 0 ? 0 : o.copy_cols > 0 ? std::min(o.copy_cols, mmax) : -1;
-    const int cap = p->exact ? kMaxCopyValuesExact : p->pair0 ? kMaxCopyValuesPaired : kMaxCopyValues;
+    if (cap <= 0) cap = p->exact ? kMaxCopyValuesExact : p->pair0 ? kMaxCopyValuesPaired : kMaxCopyValues;
     std::vector<int> cands;
     if (want >= 0) {
         cands.push_back(want);
@@ -646,7 +652,25 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
         p->nested = nest;
         if (nest) {
             LoopCount best;
-            const int m = choose_copies(p, o, std::min(p->u, n - 2), &best, nullptr);
+            int m = -2;
+            if (!ex && o.unroll_log2 == 0 && p->u > kMaxUnrollCached) {
+                // the long default block only where the copies leave few
+                // operations: the count at 2^9-step blocks (copies within the
+                // allowance of dense rows) decides; above kBigBlockMaxOps the
+                // plan keeps those blocks and copies (a chunk-long block of a
+                // denser matrix is code the compiler takes minutes over, and
+                // its copies spill)
+                Plan q = *p;
+                q.u = kMaxUnrollCached;
+                LoopCount small;
+                const int ms = choose_copies(&q, o, std::min(q.u, n - 2), &small, nullptr, kMaxCopyValues);
+                if (ms >= 0 && small.ops_per_step > kBigBlockMaxOps) {
+                    p->u = q.u;
+                    m = ms;
+                    best = small;
+                }
+            }
+            if (m == -2) m = choose_copies(p, o, std::min(p->u, n - 2), &best, nullptr);
             if (m >= 0) {
                 p->copy_cols = m;
                 pops = best.ops_per_step * steps;

@@ -254,6 +254,33 @@ def test_er_grid_nested_block_partials_vs_oracle(P, oracle_mod, copies):
     assert total * 2.0 * (-1) ** (n - 1) == pytest.approx(got, rel=1e-12)  # Alg. 1's final factor
 
 
+def test_dense_pair_block_partials_vs_oracle(P, oracle_mod):
+    """A denser matrix whose first column has two entries (ER n = 40, p = 0.3,
+    U[0,1], column 0 cut to two entries): the paired kernel with 2^9-step
+    blocks and the copies the plan allows for dense rows; sampled workgroup
+    partials against the oracle, and their sum against the permanent."""
+    import math
+    O = oracle_mod
+    n = 40
+    A = O.ccs_to_dense(W.er_grid_matrix(n, 0.3))
+    A[np.nonzero(A[:, 0])[0][2:], 0] = 0.0
+    ccs = O.dense_to_ccs(A)
+    head = P.perm_codegen(ccs, zero_skip=False).splitlines()[0]
+    assert "pair0" in head and " u=9 " in head, head
+    got, st, parts = P.perm_sparse_ex(ccs, zero_skip=False, block_partials=True)
+    print("dense pair", head, st["kernel_ms"], st["vgprs"], st["vgpr_spills"], flush=True)
+    plan = P.perm_plan(ccs, zero_skip=False)
+    B = O.dense_to_ccs(A[np.ix_(plan["row_perm"], plan["col_perm"])])
+    W_ = st["block"] << st["chunk_log2"]
+    for b in (0, st["nblocks"] // 3 + 5, st["nblocks"] - 1):
+        (h, l), (ah, al) = O.nw_range(B, b * W_, min((b + 1) * W_, 1 << (n - 1)))
+        ref, abs_sum = h + l, ah + al
+        g = parts[b, 0] + parts[b, 1]
+        assert abs(g - ref) <= max(1e-9 * abs(ref), (2 * n + 2) * 2.0 ** -53 * abs_sum), (b, g, ref)
+    total = math.fsum(parts[:, 0]) + math.fsum(parts[:, 1])
+    assert total * 2.0 * (-1) ** (n - 1) == pytest.approx(got, rel=1e-12)
+
+
 def test_full_size_closed_forms(P, oracle_mod):
     """n = 40, the benchmark size, on matrices whose permanent is known in
     closed form (no oracle run): tridiagonal of ones, F(41) = 165580141; a

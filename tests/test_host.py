@@ -577,6 +577,25 @@ def test_block_queue_on_cpu(P, oracle_mod):
     assert abs(got - ref) <= 1e-12 * abs_sum + 1e-12
 
 
+def test_paired_block_length_follows_density(P, oracle_mod):
+    """Paired FP64 kernels take a chunk-long static block (2^13 paired steps,
+    chunks of 2^15 at n >= 37) only where copies leave few operations per
+    term; a pair in a denser matrix keeps 2^9-step blocks and fewer copies
+    (its chunk-long block compiles for minutes and spills)."""
+    O = oracle_mod
+    head = lambda ccs: P.perm_codegen(ccs, zero_skip=False, exact=False).splitlines()[0]
+    sparse = head(W.er_grid_matrix(40, 0.1, 1))
+    assert "pair0" in sparse and "kappa=15 u=13" in sparse, sparse
+    A = O.ccs_to_dense(W.er_grid_matrix(40, 0.3, 1))
+    A[np.nonzero(A[:, 0])[0][2:], 0] = 0.0  # a first column of two entries
+    dense = head(O.dense_to_ccs(A))
+    assert "pair0" in dense and " u=9 " in dense, dense
+    assert int(re.search(r"copies=(\d+)", dense).group(1)) <= 6, dense
+    # a block asked for is taken as given
+    assert " u=12 " in P.perm_codegen(O.dense_to_ccs(A), zero_skip=False, exact=False, unroll_log2=12,
+                                      copy_cols=-1).splitlines()[0]
+
+
 def test_nested_without_pairing_on_cpu(P, oracle_mod):
     """FP64 AUTO kernels whose first column has three or more entries (no
     pairing) sum the terms through per-level accumulators, level 0's own
