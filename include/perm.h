@@ -147,17 +147,19 @@ typedef struct {
                               1 = required (PERM_EINVAL otherwise), -1 = off (FP64 only) */
     int32_t exact_passes;  /* exact mode: run at least this many passes (primes), 1..3;
                               0 = as many as the certificate needs */
-    int32_t copy_cols;     /* AUTO all-terms FP64 kernels in nested form (per-level products
-                              and accumulators; always with column-0 pairing, otherwise when
-                              the generator's count of FP64 operations is at most 0.6 of the
-                              cached products'): the rows of the walk's m most frequent
-                              columns are kept in 2^(columns touching them) copies (each with
-                              those columns' entries in or out), so that flipping one of them
-                              only selects other copies, and the other flips move every copy.
-                              0 = the m (up to unroll_log2) with the fewest FP64 operations in
-                              the generator's count whose copies stay within 112 doubles per
-                              lane, 1..9 = that m (at most unroll_log2; takes the nested form),
-                              -1 = none */
+    int32_t copy_cols;     /* AUTO all-terms kernels in nested form (per-level products and
+                              accumulators; always with column-0 pairing, FP64 or exact,
+                              otherwise in FP64 when the generator's count of FP64 operations
+                              is at most 0.6 of the cached products'): the rows of the walk's
+                              m most frequent columns are kept in 2^(columns touching them)
+                              copies (each with those columns' entries in or out), so that
+                              flipping one of them only selects other copies, and the other
+                              flips move every copy.  0 = the m (up to unroll_log2) with the
+                              fewest FP64 operations in the generator's count whose copies
+                              stay within an allowance of extra doubles per lane (paired FP64
+                              400, exact 128 with each level copy's residue counted, dense
+                              rows 112), 1..13 = that m (at most unroll_log2; takes the nested
+                              form), -1 = none */
 } perm_opts;
 
 /* Statistics of one call (all optional to read). */

@@ -482,7 +482,7 @@ perm_status make_plan(const Ccs &a, const perm_opts &o, Plan *p, std::string *er
     }
     p->waves_per_simd = std::max(0, o.waves_per_simd);
     if (o.copy_cols < -1 || o.copy_cols > 13) {
-        *err = "copy_cols must be -1 (none), 0 (automatic) or 1..9";
+        *err = "copy_cols must be -1 (none), 0 (automatic) or 1..13";
         return PERM_EINVAL;
     }
     if (!(o.block_queue == -1 || o.block_queue == 0 || o.block_queue == 8 || o.block_queue == 16 ||
