@@ -104,6 +104,12 @@ struct Gen {
     // the prime, reduced at every move) and a_l (the sum of |term| for the
     // error bound), moved up through RP_l (P_l's residue) and |P_l|.
     bool hx = false;
+    // r_l's moves since its last reduction (0: reduced).  A move adds less
+    // than (2^23 + 2)^2 < 2^46.01, so after at most kMaxDeferred of them
+    // |r_l| < 2^50.1 and the next FMA into it stays exact; r_l is reduced
+    // before it multiplies (then every product is below 2^46.01).
+    std::vector<int> rdef;
+    static constexpr int kMaxDeferred = 16;
     long acc_written = 0;  // accumulator operations as written (per chunk; the error bound's length)
     long body_acc = 0;     // of those, one loop iteration's
     double acc_chunk = 0;  // all of one chunk
@@ -287,22 +293,35 @@ struct Gen {
             if (hx) {
                 const std::string al = "a" + std::to_string(l), ab = "a" + std::to_string(l - 1);
                 const std::string rl = "r" + std::to_string(l), rb = "r" + std::to_string(l - 1);
+                if (l - 1 >= 1 && rdef[l - 1] > 0) settle_residue(l - 1, I);  // reduced before it multiplies
                 const std::string rp = "R" + pname(l), t = fresh();
+                int k;
                 if (cz[l]) {
                     os << I << al << " = " << ab << " * fabs(" << pname(l) << ");\n";
                     note(al, "mula", {ab, pname(l)}, 1);
                     os << I << "const double " << t << " = " << rb << " * " << rp << ";\n";
                     note(t, "mul", {rb, rp}, 1);
+                    k = 1;
                 } else {
                     os << I << al << " = fma(" << ab << ", fabs(" << pname(l) << "), " << al << ");\n";
                     note(al, "fmaa", {ab, pname(l), al}, 2);
                     os << I << "const double " << t << " = fma(" << rb << ", " << rp << ", " << rl << ");\n";
                     note(t, "fma", {rb, rp, rl}, 2);
+                    k = rdef[l] + 1;
                 }
-                // |r_{l-1}|, |RP_l| < 2^23 + 2: the product and the sum are exact
-                const std::string red = reduce_expr(t, I);
-                os << I << rl << " = " << red << ";\n";
-                note(rl, "red", {t}, 1);
+                // |r_{l-1}|, |RP_l| < 2^23 + 2 and at most kMaxDeferred
+                // earlier moves in r_l: the product and the sum are exact; the
+                // reduction waits until r_l multiplies or the count is reached
+                if (k > kMaxDeferred) {
+                    const std::string red = reduce_expr(t, I);
+                    os << I << rl << " = " << red << ";\n";
+                    note(rl, "red", {t}, 1);
+                    k = 0;
+                } else {
+                    os << I << rl << " = " << t << ";\n";
+                    alias(rl, t);
+                }
+                rdef[l] = k;
             }
             cz[l] = 0;
             if (l >= 2) cz[l - 1] = 1;
@@ -387,6 +406,20 @@ struct Gen {
         os << I << "const double " << m << " = " << red << ";\n";
         note(m, "red", {t}, 1);
         return m;
+    }
+    // r_l brought back to (-p/2 - 2, p/2 + 2)
+    void settle_residue(int l, const char *I) {
+        const std::string rl = "r" + std::to_string(l);
+        const std::string red = reduce_expr(rl, I);
+        os << I << rl << " = " << red << ";\n";
+        note(rl, "red", {rl}, 1);
+        rdef[l] = 0;
+    }
+    // every r_l reduced (where the generated code joins: the loop's top and
+    // end, the chunk's end)
+    void settle_residues(const char *I) {
+        for (int l = 1; l < (int)rdef.size(); ++l)
+            if (rdef[l] > 0) settle_residue(l, I);
     }
     // t reduced modulo the prime (an exact remainder for exact t below 2^53;
     // the quotient's multiply is an FP64 operation of its own)
@@ -799,6 +832,7 @@ struct Gen {
         const int kw = kappa - c0;
         horner = p.nested && !p.cold && L >= 2;
         hx = horner && p.exact;
+        rdef.assign(L, 0);
         if (hx && !p.pair0) os << "#error exact nested kernels are paired\n";  // the plan pairs them
         dtrack = horner && p.pair0 && p.B.colptr[1] - p.B.colptr[0] == 2;
         cm = horner ? p.copy_cols : 0;
@@ -1185,6 +1219,7 @@ struct Gen {
                     for (int j = c0; j <= u + c0; ++j) loop_top = std::max(loop_top, p.col_top[j]);
                     for (int l = 1; l < loop_top; ++l) cz[l] = 1;
                 }
+                if (hx) settle_residues("  ");  // the same state at every iteration's top
                 os << "#pragma clang loop unroll(disable)\n";
                 os << "  for (u32 base = 0; base < " << DW << "u; base += " << 2 * U << "u) {\n";
                 auto body = [&]() {
@@ -1193,6 +1228,7 @@ struct Gen {
                         os << "    const u32 ell = base + " << 2 * U << "u;\n";
                         dynamic_step("ell", "    ");
                     }
+                    if (hx) settle_residues("    ");
                 };
                 if (horner) {
                     // count the body's operations: a first pass finds the
@@ -1203,6 +1239,7 @@ struct Gen {
                     const std::vector<char> cz0 = cz;
                     const unsigned ts0 = ts;
                     const std::vector<char> dirty0 = dirty;
+                    const std::vector<int> rdef0 = rdef;
                     const long acc0_written = acc_written;
                     track = true;
                     vid.clear();
@@ -1217,6 +1254,7 @@ struct Gen {
                     cz = cz0;
                     ts = ts0;
                     dirty = dirty0;
+                    rdef = rdef0;
                     acc_written = acc0_written;
                     vid.clear();
                     unit.clear();
@@ -1286,6 +1324,7 @@ struct Gen {
         if (horner) {
             // everything up to the top level: c_{L-1} is the chunk's sum
             flush_to(L - 1, "  ");
+            if (hx) settle_residues("  ");
             os << "  acc0 = c" << L - 1 << ";\n";
             if (hx) os << "  racc = r" << L - 1 << "; accA = a" << L - 1 << ";\n";
             acc_chunk = (double)acc_written + (double)body_acc * ((double)std::max<uint64_t>(loop_iters, 1) - 1.0);

@@ -756,11 +756,19 @@ def test_column0_pairing_on_cpu(P, oracle_mod):
     # move up beside the FP64 accumulators, and the error bound's length is
     # the chunk's accumulator operations (at least chunk_log2); residues and
     # the recovered count against the oracle, with and without copies
+    # (n = 15, seed 6: a level takes more than 16 moves before it multiplies,
+    # so the count-limited reductions are emitted too)
     for ccs, kappa, u, m in ((W.single_01(16, 0.2, 2), 7, 3, 0), (W.single_01(20, 0.1, 6), 12, 4, 0),
-                             (W.single_01(20, 0.1, 6), 12, 4, 3), (W.single_01(18, 0.15, 3), 9, 5, -1)):
+                             (W.single_01(20, 0.1, 6), 12, 4, 3), (W.single_01(18, 0.15, 3), 9, 5, -1),
+                             (W.single_01(15, 0.15, 6), 12, 9, 0)):
         opts = dict(chunk_log2=kappa, unroll_log2=u, zero_skip=False, copy_cols=m)
-        head = P.perm_codegen(ccs, **opts).splitlines()[0]
+        src = P.perm_codegen(ccs, **opts)
+        head = src.splitlines()[0]
         assert "pair0" in head and " nested" in head, head
+        # residue moves whose reduction waits until the residue multiplies
+        assert re.search(r"\br\d+ = t\d+;", src), head
+        if ccs[0] == 15:
+            assert re.search(r"\br\d+ = fma\(-t\d+, pmod, t\d+\);", src), head
         if m:
             assert (" copies=" in head) == (m > 0), head  # 0: the plan's choice
         bl = P.compile_info(ccs, **opts)["exact_bound_log2"]
