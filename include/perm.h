@@ -83,7 +83,8 @@ typedef struct {
                               with column-0 pairing 13, exact 9).  Always at most chunk_log2 - 1,
                               paired kernels chunk_log2 - 2; values above 9 are reduced to 9
                               except for nested kernels with pairing */
-    int32_t block;         /* threads per workgroup, multiple of 64, <= 1024; 0 = 256 */
+    int32_t block;         /* threads per workgroup, multiple of 64, <= 1024; 0 = 256 (FP64
+                              kernels with column-0 pairing: 64) */
     int32_t vgpr_budget;   /* target VGPRs per lane for the level plan; 0 = 128 */
     int32_t force_k;       /* > 0: override Alg. 5's k (HYBRID only), with force_c */
     int32_t force_c;       /* > 0: override Alg. 5's c (HYBRID only) */
