@@ -352,6 +352,8 @@ def test_n40_full_exact(P):
         # the exact mode returns the count itself, with its certificate
         assert got == exact and st["exact"] == 1
         assert abs(st["estimate"] - exact) <= st["err_bound"]
+        # the bound's length: a chunk's accumulate operations (nested: more than one per term)
+        assert st["exact_bound_log2"] >= st["chunk_log2"]
 
 
 def test_n40_bench_configuration_block_partials(P, oracle_mod):
