@@ -190,7 +190,7 @@ constexpr int kMaxUnrollCached = 9;
 // Paired FP64 kernels take static blocks beyond 2^9 steps by default only
 // when their best count at 2^9 is at most this many FP64 operations per
 // term (n = 40, d = 0.10: 0.35; ER n = 40..45, p = 0.1: 0.11..0.15; a
-// column-0 pair in ER n = 40, p = 0.2..0.3: 1.5..3.2).
+// column-0 pair in ER n = 40..45, p = 0.2..0.3: 1.7..4.2).
 constexpr double kBigBlockMaxOps = 0.6;
 
 // The extra doubles the copies of the walk's first m columns keep (the
