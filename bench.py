@@ -450,7 +450,8 @@ def main():
     # residue and bound operations) over every evaluated step
     flops = st["flops_per_step"] * kern["evaluated_steps_per_launch_set"]
     achieved_tflops = flops / avg_kernel_s / 1e12
-    src = P.perm_codegen(ccs, **dict(opts, waves_per_simd=st["waves_hint"] or -1))
+    src = P.perm_codegen(ccs, **dict(opts, waves_per_simd=st["waves_hint"] or -1,
+                                     **({"copy_cols": st["copy_cols"]} if st["copy_cols"] else {})))
     out = {
         "metric": METRIC,
         "value": steps_per_perm * args.steps / elapsed,

@@ -209,7 +209,9 @@ typedef struct {
                                   error bound takes (perm_exact_recover's chunk_log2 for this
                                   kernel: chunk_log2, or more with nested accumulators); 0 outside
                                   the exact mode */
-    int32_t pad_stats;
+    int32_t copy_cols;         /* nested kernels: copied columns of the kernel that ran (a paired
+                                  FP64 build that spilled is compiled again with fewer; pass this
+                                  and waves_hint to perm_codegen for the text that ran); 0 = none */
 } perm_stats;
 
 /* Permanent of one matrix (Alg. 1 end to end).  Returns NaN on error
@@ -394,7 +396,8 @@ perm_status perm_partition(const perm_csc *ordered, const double *tau, double gr
 /* The HIP source text generated for a matrix.  Writes at most cap bytes
  * (NUL-terminated when it fits) and the full length to *len.  Generation only:
  * with waves_per_simd 0 (automatic) the text carries no occupancy attribute;
- * passing perm_stats.waves_hint of a run gives the exact text that ran. */
+ * passing perm_stats.waves_hint (and, where nonzero, copy_cols) of a run gives
+ * the exact text that ran. */
 perm_status perm_codegen(const perm_csc *a, const perm_opts *opts, char *buf, size_t cap, size_t *len);
 
 /* Compile the generated kernel for a matrix with hipRTC (gfx950; no GPU

@@ -83,7 +83,7 @@ class PermStats(ctypes.Structure):
                 ("singular", ctypes.c_int32), ("waves_hint", ctypes.c_int32), ("vgpr_spills", ctypes.c_int32),
                 ("exact", ctypes.c_int32), ("exact_passes", ctypes.c_int32), ("estimate", ctypes.c_double),
                 ("err_bound", ctypes.c_double), ("exact_ops_per_step", ctypes.c_double),
-                ("exact_bound_log2", ctypes.c_int32), ("pad_stats", ctypes.c_int32)]
+                ("exact_bound_log2", ctypes.c_int32), ("copy_cols", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

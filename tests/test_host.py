@@ -596,6 +596,21 @@ def test_paired_block_length_follows_density(P, oracle_mod):
                                       copy_cols=-1).splitlines()[0]
 
 
+def test_spilling_paired_build_takes_fewer_copies(P):
+    """A paired FP64 build whose automatically chosen copies spill (ER n = 48,
+    p = 0.1: chunks of 2^16 with 2^13-step blocks and copies of 13 columns) is
+    compiled again with one copied column fewer; the statistics name the
+    copies that ran, and the generated text for them is the compiled one."""
+    ccs = W.er_grid_matrix(48, 0.1, 1)
+    first = P.perm_codegen(ccs).splitlines()[0]
+    assert "copies=13" in first, first
+    info = P.compile_info(ccs)
+    assert info["scratch_bytes"] == 0 and info["copy_cols"] == 12, (info["scratch_bytes"], info["copy_cols"])
+    assert "copies=12" in P.perm_codegen(ccs, copy_cols=info["copy_cols"]).splitlines()[0]
+    # copies asked for are kept as asked, spill or not
+    assert P.compile_info(ccs, copy_cols=13)["copy_cols"] == 13
+
+
 def test_nested_without_pairing_on_cpu(P, oracle_mod):
     """FP64 AUTO kernels whose first column has three or more entries (no
     pairing) sum the terms through per-level accumulators, level 0's own
