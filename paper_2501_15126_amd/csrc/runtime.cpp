@@ -218,16 +218,25 @@ constexpr int kAutoWavesMaxScratch = 128;
 perm_status compile_prepared_build(Prepared *p, const perm_opts &o, CodeObject *co, std::string *err) {
     perm_status s = compile_source(p->src, co, err);
     if (s != PERM_OK) return s;
-    // Paired FP64 kernels in nested form with automatically chosen copies: a
-    // build that spills is generated again with one copied column fewer, up
-    // to three times (ER n = 48, p = 0.1, chunks of 2^16: copies of 13
-    // columns spill 492 bytes per lane and run 975 ms, of 12 none, 455 ms).
+    // Paired kernels in nested form with automatically chosen copies: a build
+    // that spills is generated again with one copied column fewer, up to
+    // three times (ER n = 48, p = 0.1, chunks of 2^16: copies of 13 columns
+    // spill 492 bytes per lane and run 975 ms, of 12 none, 455 ms).  In the
+    // exact mode the error bound's length is taken from the new code's
+    // count.  (Unpaired nested kernels keep their copies: untimed there, and
+    // one column fewer adds 24 % to the operations of an n = 36 0/1 kernel
+    // whose build spills a little.)
     for (int tries = 0; tries < 3 && co->scratch_bytes > 0; ++tries) {
         const Plan &pl = p->plan;
-        if (!(pl.pair0 && pl.nested && !pl.exact && o.copy_cols == 0 && pl.copy_cols > 1)) break;
+        if (!(pl.pair0 && pl.nested && o.copy_cols == 0 && pl.copy_cols >= 1)) break;
         Plan q = pl;
         q.copy_cols -= 1;
-        std::string src2 = generate_source(q);
+        LoopCount lc;
+        std::string src2 = generate_source(q, &lc);
+        if (q.exact) {
+            if (!lc.counted) break;
+            q.acc_log2 = std::max(q.acc_log2, lc.acc_log2);
+        }
         CodeObject c2;
         std::string err2;
         if (compile_source(src2, &c2, &err2) != PERM_OK) break;  // keep the build we have
